@@ -1,0 +1,881 @@
+/*
+ * aaa_oracle.c -- plain, slow FP64 CPU reference of the AAA-Gaussians
+ * rasterisation path (arXiv 2504.12811).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant
+ * generator with the HIP path.
+ *
+ * Everything is computed in double precision from the definitions:
+ *   - Gaussian primitive, Sec. 3.1 Eq.(1)-(3).
+ *   - Response = maximum of the Gaussian along the pixel's line (Sec. 3.1,
+ *     "Evaluation in 3D", Eq.(4)-(5)).  The oracle writes the maximum out as
+ *     the closed-form minimum over t of the Mahalanobis distance of o + t r,
+ *     i.e. the ray form, not the screen-plane form used by the kernels.
+ *   - Adaptive 3D filter, Sec. 3.2 Eq.(6), (10)-(13); volume-normalised
+ *     variant Eq.(7)-(8) behind a flag.
+ *   - Camera-inside discard, Sec. 3.3.
+ *   - 3D frustum culling, Sec. 3.4 Eq.(18): exact minimum of rho^2 over a
+ *     pyramid by enumeration of every active set (faces, edges, apex).
+ *   - Hierarchical ordering (Sec. 3.1 "Blending Sort Order", Sec. 4 impl.
+ *     details): tile list ordered by a per-tile 3D depth, then a bounded
+ *     per-ray window keyed by the per-pixel depth of maximum response.
+ *   - Front-to-back alpha blending with early termination (3DGS lineage).
+ *
+ * Readings where the paper is silent are listed in the design doc and restated at
+ * each use below.  Candidate lists are a conservative bounding sphere (its own
+ * acceleration); extra candidates are filtered out by the per-pixel test and
+ * cannot change the result.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_TILE 16
+
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t _pad;
+    const float *means;          /* [3][n] */
+    const float *log_scales;     /* [3][n] */
+    const float *quats;          /* [4][n] (w,x,y,z) */
+    const float *opacity_logits; /* [n] */
+    const float *sh;             /* [(deg+1)^2][3][n] */
+    const float *v_train;        /* [n] or NULL */
+} or_scene;
+
+typedef struct {
+    double viewmat[16]; /* world -> view, row-major; +x right, +y down, +z forward */
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    double znear;
+    double bg[3];
+} or_camera;
+
+typedef struct {
+    double filter_k;
+    int32_t ray_window;  /* K; 0 = blend in tile order */
+    int32_t filter_mode; /* 0 adaptive (Eq.12), 1 off, 2 volume-normalised (Eq.8) */
+    double alpha_min, alpha_max, t_min;
+    /* relative bands inside which an FP32 decision may legitimately differ */
+    double band_alpha, band_z, band_tie, band_T;
+} or_settings;
+
+enum { OR_VISIBLE = 0, OR_INVALID = 1, OR_LOW_OPACITY = 2, OR_CAM_INSIDE = 3, OR_OUTSIDE = 4 };
+
+typedef struct {
+    int32_t status;
+    int32_t ambiguous; /* camera-inside decision within band: pixels it would touch are flagged */
+    double alpha, alpha_t, tau, filter_a;
+    double s[3], s_t[3];
+    double R[9];   /* row-major; world offset = R * diag(s) * g */
+    double mu[3], mu_v[3], o[3];
+    double o_g[3]; /* camera centre in normalised (filtered) Gaussian space */
+    double A[9];   /* view-space direction -> normalised Gaussian space: S~^-1 R^T R_V^T */
+    double M[9];   /* normalised Gaussian space -> view space: R_V R S~ (row-major) */
+    double color[3];
+    double dir[3]; /* unit direction camera -> mean (world) */
+} or_gauss;
+
+/* ------------------------------------------------------------------------ */
+/* small linear algebra                                                       */
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void matvec3(const double *m, const double *v, double *out)
+{
+    for (int i = 0; i < 3; ++i) out[i] = m[3 * i] * v[0] + m[3 * i + 1] * v[1] + m[3 * i + 2] * v[2];
+}
+
+static void matTvec3(const double *m, const double *v, double *out)
+{
+    for (int i = 0; i < 3; ++i) out[i] = m[i] * v[0] + m[3 + i] * v[1] + m[6 + i] * v[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3.1 Eq.(3): rotation matrix of a quaternion q = (w, x, y, z).        */
+void or_rotation(const double *q_in, double *R)
+{
+    double n = sqrt(q_in[0] * q_in[0] + q_in[1] * q_in[1] + q_in[2] * q_in[2] + q_in[3] * q_in[3]);
+    double w = q_in[0] / n, x = q_in[1] / n, y = q_in[2] / n, z = q_in[3] / n;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* View-dependent colour (Sec. 5 mentions a view-dependent encoding; reading:
+ * real spherical harmonics of degree <= 3).  Written from the textbook
+ * definition: Y_l^m = N_l^|m| P_l^|m|(cos theta) * {sqrt2 cos(m phi), 1,
+ * sqrt2 sin(|m| phi)} with the Condon-Shortley phase inside P_l^m, theta the
+ * polar angle from +z and phi the azimuth from +x towards +y.  Index l*l+l+m. */
+static double fact(int k) { double r = 1; for (int i = 2; i <= k; ++i) r *= i; return r; }
+
+static double assoc_legendre(int l, int m, double x) /* P_l^m(x), m >= 0, with (-1)^m phase */
+{
+    /* Standard recurrences (Abramowitz & Stegun 8.5.3, 8.6.x). */
+    double pmm = 1.0;
+    if (m > 0) {
+        double somx2 = sqrt((1.0 - x) * (1.0 + x));
+        double f = 1.0;
+        for (int i = 1; i <= m; ++i) { pmm *= -f * somx2; f += 2.0; }
+    }
+    if (l == m) return pmm;
+    double pmmp1 = x * (2.0 * m + 1.0) * pmm;
+    if (l == m + 1) return pmmp1;
+    double pll = 0.0;
+    for (int ll = m + 2; ll <= l; ++ll) {
+        pll = ((2.0 * ll - 1.0) * x * pmmp1 - (ll + m - 1.0) * pmm) / (ll - m);
+        pmm = pmmp1;
+        pmmp1 = pll;
+    }
+    return pll;
+}
+
+void or_sh_basis(int degree, const double *dir, double *Y)
+{
+    double r = sqrt(dot3(dir, dir));
+    double ct = dir[2] / r;
+    if (ct > 1) ct = 1;
+    if (ct < -1) ct = -1;
+    double phi = atan2(dir[1], dir[0]);
+    for (int l = 0; l <= degree; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * fact(l - am) / fact(l + am));
+            double P = assoc_legendre(l, am, ct);
+            double v;
+            if (m > 0) v = sqrt(2.0) * N * P * cos(m * phi);
+            else if (m < 0) v = sqrt(2.0) * N * P * sin(am * phi);
+            else v = N * P;
+            Y[l * l + l + m] = v;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-Gaussian preparation: Sec. 3.1 Eq.(1)-(3), Sec. 3.2 Eq.(6)-(13),
+ * Sec. 3.3 camera-inside discard, Sec. 3.4 whole-frustum cull.            */
+
+static void camera_parts(const or_camera *cam, double *RV, double *tV, double *o)
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) RV[3 * i + j] = cam->viewmat[4 * i + j];
+        tV[i] = cam->viewmat[4 * i + 3];
+    }
+    /* camera centre o = -R_V^T t_V (rigid view matrix) */
+    matTvec3(RV, tV, o);
+    o[0] = -o[0]; o[1] = -o[1]; o[2] = -o[2];
+}
+
+double or_cone_min_rho2(const or_gauss *g, const or_camera *cam, double x0, double x1, double y0, double y1);
+
+static int finite_all(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i) if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+void or_prepare(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t i, or_gauss *g)
+{
+    memset(g, 0, sizeof(*g));
+    const int64_t n = sc->n;
+    double RV[9], tV[3], o[3];
+    camera_parts(cam, RV, tV, o);
+    double q[4], ls[3], logit;
+    for (int k = 0; k < 3; ++k) {
+        g->mu[k] = sc->means[k * n + i];
+        ls[k] = sc->log_scales[k * n + i];
+    }
+    for (int k = 0; k < 4; ++k) q[k] = sc->quats[k * n + i];
+    logit = sc->opacity_logits[i];
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    if (!finite_all(g->mu, 3) || !finite_all(ls, 3) || !finite_all(q, 4) || !isfinite(logit) || !(qn > 0)) {
+        g->status = OR_INVALID;
+        return;
+    }
+    /* O1: activations (Eq.1-3). */
+    for (int k = 0; k < 3; ++k) g->s[k] = exp(ls[k]);
+    g->alpha = 1.0 / (1.0 + exp(-logit));
+    or_rotation(q, g->R);
+    /* O2: view transform. */
+    matvec3(RV, g->mu, g->mu_v);
+    for (int k = 0; k < 3; ++k) { g->mu_v[k] += tV[k]; g->o[k] = o[k]; }
+    /* O3: filter.  v = f/d (Eq.6) with d the view depth of the mean, read as
+     * max(z, znear) so that it exists behind the camera; f = fx.  Eq.(13):
+     * v' = min(v_train, v).  Filter variance a = k / v'^2 (Sec. 3.1). */
+    double dz = g->mu_v[2] > cam->znear ? g->mu_v[2] : cam->znear;
+    double v = cam->fx / dz;
+    if (sc->v_train) {
+        double vt = sc->v_train[i];
+        if (vt < v) v = vt;
+    }
+    double a = st->filter_mode == 1 ? 0.0 : st->filter_k / (v * v);
+    g->filter_a = a;
+    double s2[3], sh_[3];
+    for (int k = 0; k < 3; ++k) {
+        s2[k] = g->s[k] * g->s[k];
+        sh_[k] = s2[k] + a; /* hat s_k = s_k^2 + k/v'^2 */
+        g->s_t[k] = sqrt(sh_[k]);
+    }
+    /* unit direction from the camera centre to the mean */
+    double d[3] = {g->mu[0] - o[0], g->mu[1] - o[1], g->mu[2] - o[2]};
+    double dn = sqrt(dot3(d, d));
+    for (int k = 0; k < 3; ++k) { d[k] /= dn; g->dir[k] = d[k]; }
+    if (st->filter_mode == 1) {
+        g->alpha_t = g->alpha;
+    } else if (st->filter_mode == 2) {
+        /* Eq.(8): volume ratio sqrt(prod s^2 / prod (s^2 + a)). */
+        g->alpha_t = g->alpha * sqrt((s2[0] * s2[1] * s2[2]) / (sh_[0] * sh_[1] * sh_[2]));
+    } else {
+        /* Eq.(12): perpendicular ratio with d' = R^T d. */
+        double dp[3];
+        matTvec3(g->R, d, dp);
+        double num = dp[0] * dp[0] * s2[1] * s2[2] + dp[1] * dp[1] * s2[0] * s2[2] + dp[2] * dp[2] * s2[0] * s2[1];
+        double den = dp[0] * dp[0] * sh_[1] * sh_[2] + dp[1] * dp[1] * sh_[0] * sh_[2] + dp[2] * dp[2] * sh_[0] * sh_[1];
+        g->alpha_t = g->alpha * sqrt(num / den);
+    }
+    /* normalised-space maps: g = S~^-1 R^T (x - mu) in world; view dir r_v -> A r_v */
+    double RtRVt[9]; /* R^T R_V^T */
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += g->R[3 * k + r] * RV[3 * c + k];
+            RtRVt[3 * r + c] = acc;
+        }
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) g->A[3 * r + c] = RtRVt[3 * r + c] / g->s_t[r];
+    for (int r = 0; r < 3; ++r) /* M = R_V R S~ */
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0;
+            for (int k = 0; k < 3; ++k) acc += RV[3 * r + k] * g->R[3 * k + c];
+            g->M[3 * r + c] = acc * g->s_t[c];
+        }
+    {
+        double om[3] = {o[0] - g->mu[0], o[1] - g->mu[1], o[2] - g->mu[2]}, t[3];
+        matTvec3(g->R, om, t);
+        for (int k = 0; k < 3; ++k) g->o_g[k] = t[k] / g->s_t[k];
+    }
+    /* O6: colour, c = max(0, 0.5 + sum_lm Y_lm(d) c_lm) per channel. */
+    {
+        double Y[16];
+        int nb = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+        or_sh_basis(sc->sh_degree, d, Y);
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = 0.5;
+            for (int b = 0; b < nb; ++b) acc += Y[b] * (double)sc->sh[((int64_t)b * 3 + ch) * n + i];
+            g->color[ch] = acc > 0 ? acc : 0;
+        }
+    }
+    /* O4: opacity cull; tau = 2 ln(alpha~ / alpha_min) is the rho^2 level at
+     * which alpha~ exp(-rho^2/2) equals alpha_min (reading of tau_rho). */
+    if (!(g->alpha_t >= st->alpha_min)) {
+        g->status = OR_LOW_OPACITY;
+        return;
+    }
+    g->tau = 2.0 * log(g->alpha_t / st->alpha_min);
+    /* O5: camera inside the level-tau ellipsoid -> discard (Sec. 3.3). */
+    double og2 = dot3(g->o_g, g->o_g);
+    if (fabs(og2 - g->tau) <= st->band_alpha * g->tau) g->ambiguous = 1;
+    if (og2 < g->tau) {
+        g->status = OR_CAM_INSIDE;
+        return;
+    }
+    /* Whole-frustum cull (Sec. 3.4 last paragraph): same test as a tile, with
+     * the image borders as the pyramid. */
+    double m = or_cone_min_rho2(g, cam, 0.0, (double)cam->width, 0.0, (double)cam->height);
+    if (!(m < g->tau)) {
+        g->status = OR_OUTSIDE;
+        return;
+    }
+    g->status = OR_VISIBLE;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Response of one Gaussian on the line through pixel position (x, y).
+ * Sec. 3.1 Eq.(4)-(5): the maximum along the line of G equals exp(-rho^2/2)
+ * with rho^2 the squared distance from the origin to the line in normalised
+ * Gaussian space.  Line: o_g + t r_g with r_g = A (u, v, 1); the view depth of
+ * the point at parameter t is t, because the view direction has z = 1.     */
+void or_response(const or_gauss *g, const or_camera *cam, double x, double y, double *rho2, double *zstar)
+{
+    double rv[3] = {(x - cam->cx) / cam->fx, (y - cam->cy) / cam->fy, 1.0};
+    double rg[3];
+    matvec3(g->A, rv, rg);
+    double rr = dot3(rg, rg);
+    double orr = dot3(g->o_g, rg);
+    double t = -orr / rr;
+    double p[3] = {g->o_g[0] + t * rg[0], g->o_g[1] + t * rg[1], g->o_g[2] + t * rg[2]};
+    *rho2 = dot3(p, p);
+    *zstar = t;
+}
+
+/* p satisfies every half-space except skip1/skip2, up to a relative 1e-12. */
+static int feasible(double ng[4][3], const double *dg, const double *p, int skip1, int skip2)
+{
+    for (int j = 0; j < 4; ++j) {
+        if (j == skip1 || j == skip2) continue;
+        double s = dot3(ng[j], p) + dg[j];
+        double scale = sqrt(dot3(ng[j], ng[j])) * sqrt(dot3(p, p)) + fabs(dg[j]) + 1e-300;
+        if (s < -1e-12 * scale) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact minimum of rho^2 over the pyramid spanned by the camera centre and the
+ * screen rectangle [x0,x1] x [y0,y1] (Sec. 3.4, Eq.(18)).  The pyramid is the
+ * intersection of four half-spaces through the camera centre; rho^2 is a
+ * strictly convex quadratic, so its minimum over the pyramid is attained at
+ * the feasible stationary point of some active set.  Every active set is
+ * enumerated: none (the mean itself), one plane, two planes (a line through
+ * the apex), three or more (the apex).                                       */
+double or_cone_min_rho2(const or_gauss *g, const or_camera *cam, double x0, double x1, double y0, double y1)
+{
+    /* view-space half-spaces n . X >= 0 */
+    double nv[4][3] = {
+        {cam->fx, 0.0, cam->cx - x0},   /* x >= x0 */
+        {-cam->fx, 0.0, x1 - cam->cx},  /* x <= x1 */
+        {0.0, cam->fy, cam->cy - y0},   /* y >= y0 */
+        {0.0, -cam->fy, y1 - cam->cy},  /* y <= y1 */
+    };
+    /* transform to normalised Gaussian space: X = M p + mu_v,
+     * n.X = (M^T n).p + n.mu_v (Eq.(5): planes move with T'^T). */
+    double ng[4][3], dg[4];
+    for (int k = 0; k < 4; ++k) {
+        double nn = sqrt(dot3(nv[k], nv[k]));
+        double nk[3] = {nv[k][0] / nn, nv[k][1] / nn, nv[k][2] / nn};
+        matTvec3(g->M, nk, ng[k]);
+        dg[k] = dot3(nk, g->mu_v);
+    }
+    /* empty active set: the mean (p = 0) */
+    {
+        int inside = 1;
+        for (int k = 0; k < 4; ++k) if (dg[k] < 0) inside = 0;
+        if (inside) return 0.0;
+    }
+    double best = INFINITY;
+    /* apex: the camera centre, always in the closed pyramid */
+    best = dot3(g->o_g, g->o_g);
+    /* one active plane */
+    for (int k = 0; k < 4; ++k) {
+        double nn = dot3(ng[k], ng[k]);
+        double p[3] = {-dg[k] * ng[k][0] / nn, -dg[k] * ng[k][1] / nn, -dg[k] * ng[k][2] / nn};
+        if (feasible(ng, dg, p, k, k)) {
+            double v = dot3(p, p);
+            if (v < best) best = v;
+        }
+    }
+    /* two active planes: their intersection line passes through the apex */
+    for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) {
+            double dir[3];
+            cross3(ng[a], ng[b], dir);
+            double dd = dot3(dir, dir);
+            if (!(dd > 0)) continue;
+            double t = -dot3(g->o_g, dir) / dd;
+            double p[3] = {g->o_g[0] + t * dir[0], g->o_g[1] + t * dir[1], g->o_g[2] + t * dir[2]};
+            if (feasible(ng, dg, p, a, b)) {
+                double v = dot3(p, p);
+                if (v < best) best = v;
+            }
+        }
+    return best;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Conservative candidate tiles: sphere of radius sqrt(tau) * max s~ around the
+ * mean (contains the level-tau ellipsoid).  Tile column tx is a candidate if
+ * the sphere reaches both half-spaces of the column's side planes; same for
+ * rows; and the sphere must reach depth znear.                              */
+static int sphere_rect(const or_gauss *g, const or_camera *cam, int tiles_x, int tiles_y, int *rect)
+{
+    double smax = g->s_t[0];
+    if (g->s_t[1] > smax) smax = g->s_t[1];
+    if (g->s_t[2] > smax) smax = g->s_t[2];
+    double rad = sqrt(g->tau) * smax * (1.0 + 1e-9) + 1e-12;
+    if (g->mu_v[2] + rad < cam->znear) return 0;
+    int lo = tiles_x, hi = -1;
+    for (int tx = 0; tx < tiles_x; ++tx) {
+        double x0 = tx * OR_TILE, x1 = x0 + OR_TILE;
+        double nl[3] = {cam->fx, 0, cam->cx - x0}, nr[3] = {-cam->fx, 0, x1 - cam->cx};
+        double dl = dot3(nl, g->mu_v) / sqrt(dot3(nl, nl));
+        double dr = dot3(nr, g->mu_v) / sqrt(dot3(nr, nr));
+        if (dl >= -rad && dr >= -rad) {
+            if (tx < lo) lo = tx;
+            hi = tx;
+        }
+    }
+    if (hi < 0) return 0;
+    int lo_y = tiles_y, hi_y = -1;
+    for (int ty = 0; ty < tiles_y; ++ty) {
+        double y0 = ty * OR_TILE, y1 = y0 + OR_TILE;
+        double nt[3] = {0, cam->fy, cam->cy - y0}, nb[3] = {0, -cam->fy, y1 - cam->cy};
+        double dt = dot3(nt, g->mu_v) / sqrt(dot3(nt, nt));
+        double db = dot3(nb, g->mu_v) / sqrt(dot3(nb, nb));
+        if (dt >= -rad && db >= -rad) {
+            if (ty < lo_y) lo_y = ty;
+            hi_y = ty;
+        }
+    }
+    if (hi_y < 0) return 0;
+    rect[0] = lo; rect[1] = hi + 1; rect[2] = lo_y; rect[3] = hi_y + 1;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rendering. */
+
+typedef struct {
+    double dtile;
+    int64_t id;
+    double z, a;
+    const double *c;
+    double tat; /* transmittance just before this entry was blended; -1 if never blended */
+} or_contrib;
+
+static int cmp_tile_order(const void *pa, const void *pb)
+{
+    const or_contrib *a = (const or_contrib *)pa, *b = (const or_contrib *)pb;
+    if (a->dtile < b->dtile) return -1;
+    if (a->dtile > b->dtile) return 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+typedef struct {
+    double T, C[3];
+    int done;
+    int flag;
+    int64_t nblend;
+} or_pixel_state;
+
+static double max3(const double *c)
+{
+    double m = c[0] > c[1] ? c[0] : c[1];
+    return c[2] > m ? c[2] : m;
+}
+
+/* O12: front-to-back blending with early termination: stop, without blending
+ * it, at the first entry that would take T below t_min (3DGS lineage). */
+static void blend_one(or_pixel_state *ps, const or_settings *st, or_contrib *e)
+{
+    if (ps->done) return;
+    double Tn = ps->T * (1.0 - e->a);
+    double cm = max3(e->c);
+    if (fabs(Tn - st->t_min) <= st->band_T * st->t_min && ps->T * e->a * (cm > 1 ? cm : 1) > 5e-5) ps->flag |= 4;
+    if (Tn < st->t_min) {
+        ps->done = 1;
+        return;
+    }
+    e->tat = ps->T;
+    for (int k = 0; k < 3; ++k) ps->C[k] += ps->T * e->a * e->c[k];
+    ps->T = Tn;
+    ps->nblend++;
+}
+
+/* O11: per-ray window of capacity K keyed by (z*, id): each contributor is
+ * inserted; when the window holds more than K entries its minimum is popped
+ * and blended; at the end of the list the rest is popped in ascending order.
+ * K = 0 blends in list order. */
+static int win_less(const or_contrib *a, const or_contrib *b)
+{
+    if (a->z < b->z) return 1;
+    if (a->z > b->z) return 0;
+    return a->id < b->id;
+}
+
+static void window_blend(or_contrib *seq, int64_t ns, int K, or_pixel_state *ps, const or_settings *st, int64_t *win)
+{
+    if (K <= 0) {
+        for (int64_t i = 0; i < ns && !ps->done; ++i) blend_one(ps, st, &seq[i]);
+        return;
+    }
+    int nw = 0;
+    for (int64_t i = 0; i < ns && !ps->done; ++i) {
+        win[nw++] = i;
+        if (nw > K) {
+            int mi = 0;
+            for (int j = 1; j < nw; ++j) if (win_less(&seq[win[j]], &seq[win[mi]])) mi = j;
+            int64_t e = win[mi];
+            win[mi] = win[nw - 1];
+            nw--;
+            blend_one(ps, st, &seq[e]);
+        }
+    }
+    while (nw > 0 && !ps->done) {
+        int mi = 0;
+        for (int j = 1; j < nw; ++j) if (win_less(&seq[win[j]], &seq[win[mi]])) mi = j;
+        int64_t e = win[mi];
+        win[mi] = win[nw - 1];
+        nw--;
+        blend_one(ps, st, &seq[e]);
+    }
+}
+
+/* Largest change of the pixel if the blend order of entries i and j were
+ * swapped: T_before * a_i * a_j * |c_i - c_j| (both blended), or T_before *
+ * max(a) * max(c) when only one of them was blended (termination between). */
+static double swap_impact(const or_contrib *p, const or_contrib *q)
+{
+    double tp = p->tat, tq = q->tat;
+    if (tp < 0 && tq < 0) return 0.0;
+    if (tp >= 0 && tq >= 0) {
+        double t = tp > tq ? tp : tq, d = 0;
+        for (int k = 0; k < 3; ++k) {
+            double x = fabs(p->c[k] - q->c[k]);
+            if (x > d) d = x;
+        }
+        return t * p->a * q->a * d;
+    }
+    double t = tp >= 0 ? tp : tq;
+    double am = p->a > q->a ? p->a : q->a;
+    double cm = max3(p->c) > max3(q->c) ? max3(p->c) : max3(q->c);
+    return t * am * cm;
+}
+
+/* indices of seq ordered by the window key (insertion sort; lists are short) */
+static void sort_idx_by_key(int64_t *idx, int64_t n, const or_contrib *seq)
+{
+    for (int64_t i = 1; i < n; ++i) {
+        int64_t v = idx[i], j = i - 1;
+        while (j >= 0 && win_less(&seq[v], &seq[idx[j]])) {
+            idx[j + 1] = idx[j];
+            --j;
+        }
+        idx[j + 1] = v;
+    }
+}
+
+typedef struct {
+    int64_t n_visible, n_candidates_total;
+    int64_t n_contrib_total, n_blended_total;
+    int64_t n_flagged;
+} or_stats;
+
+/*
+ * Render.  out_rgb [3][H][W], out_T [H][W], out_flags [H][W] (bit 0: a
+ * contribution test within band, bit 1: depth near-tie, bit 2: termination
+ * within band, bit 3: ambiguous camera-inside Gaussian touches the pixel),
+ * out_ncontrib [H][W] (may be NULL).  tile_sel [tiles] selects the tiles to
+ * render (NULL = all); unselected pixels are left untouched.
+ */
+int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
+              double *out_rgb, double *out_T, uint8_t *out_flags, int32_t *out_ncontrib, or_stats *stats)
+{
+    const int64_t n = sc->n;
+    const int W = cam->width, H = cam->height;
+    const int tiles_x = (W + OR_TILE - 1) / OR_TILE, tiles_y = (H + OR_TILE - 1) / OR_TILE;
+    const int ntiles = tiles_x * tiles_y;
+    or_gauss *gs = (or_gauss *)malloc(sizeof(or_gauss) * (n > 0 ? n : 1));
+    int *rects = (int *)malloc(sizeof(int) * 4 * (n > 0 ? n : 1));
+    unsigned char *use = (unsigned char *)calloc(n > 0 ? n : 1, 1);
+    if (!gs || !rects || !use) return 1;
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+        or_prepare(sc, cam, st, i, &gs[i]);
+        int cand = gs[i].status == OR_VISIBLE;
+        if (gs[i].status == OR_CAM_INSIDE && gs[i].ambiguous) {
+            /* would be visible if the FP32 decision went the other way */
+            cand = 1;
+        }
+        if (cand && sphere_rect(&gs[i], cam, tiles_x, tiles_y, &rects[4 * i])) use[i] = cand;
+    }
+    /* bucket candidates per tile */
+    int64_t *cnt = (int64_t *)calloc(ntiles + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        if (!use[i]) continue;
+        for (int ty = rects[4 * i + 2]; ty < rects[4 * i + 3]; ++ty)
+            for (int tx = rects[4 * i]; tx < rects[4 * i + 1]; ++tx) cnt[ty * tiles_x + tx + 1]++;
+    }
+    for (int t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
+    int64_t total = cnt[ntiles];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (ntiles + 1));
+    memcpy(fill, cnt, sizeof(int64_t) * (ntiles + 1));
+    int64_t *lists = (int64_t *)malloc(sizeof(int64_t) * (total > 0 ? total : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        if (!use[i]) continue;
+        for (int ty = rects[4 * i + 2]; ty < rects[4 * i + 3]; ++ty)
+            for (int tx = rects[4 * i]; tx < rects[4 * i + 1]; ++tx) lists[fill[ty * tiles_x + tx]++] = i;
+    }
+    int64_t nvis = 0;
+    for (int64_t i = 0; i < n; ++i) nvis += gs[i].status == OR_VISIBLE;
+    int64_t tot_contrib = 0, tot_blend = 0, tot_flag = 0;
+    const int K = st->ray_window;
+
+#pragma omp parallel reduction(+ : tot_contrib, tot_blend, tot_flag)
+    {
+        or_contrib *seq = NULL;
+        int64_t *win = (int64_t *)malloc(sizeof(int64_t) * (K + 2));
+        double *dt = NULL;
+        int64_t *zi = NULL;
+        int64_t cap = 0;
+#pragma omp for schedule(dynamic, 1)
+        for (int t = 0; t < ntiles; ++t) {
+            if (tile_sel && !tile_sel[t]) continue;
+            int tx = t % tiles_x, ty = t / tiles_x;
+            int64_t b = cnt[t], e = cnt[t + 1], m = e - b;
+            if (m > cap) {
+                cap = m;
+                seq = (or_contrib *)realloc(seq, sizeof(or_contrib) * cap);
+                dt = (double *)realloc(dt, sizeof(double) * cap);
+                zi = (int64_t *)realloc(zi, sizeof(int64_t) * cap);
+            }
+            /* O9: tile depth = depth of maximum response on the tile-centre line */
+            for (int64_t j = 0; j < m; ++j) {
+                double r2, z;
+                or_response(&gs[lists[b + j]], cam, tx * OR_TILE + 0.5 * OR_TILE, ty * OR_TILE + 0.5 * OR_TILE, &r2, &z);
+                dt[j] = z;
+            }
+            for (int py = ty * OR_TILE; py < ty * OR_TILE + OR_TILE && py < H; ++py)
+                for (int px = tx * OR_TILE; px < tx * OR_TILE + OR_TILE && px < W; ++px) {
+                    or_pixel_state ps = {1.0, {0, 0, 0}, 0, 0, 0};
+                    int64_t ns = 0;
+                    double x = px + 0.5, y = py + 0.5; /* pixel centre */
+                    for (int64_t j = 0; j < m; ++j) {
+                        const or_gauss *g = &gs[lists[b + j]];
+                        double r2, z;
+                        or_response(g, cam, x, y, &r2, &z);
+                        double a = g->alpha_t * exp(-0.5 * r2);
+                        if (a > st->alpha_max) a = st->alpha_max;
+                        int near_a = fabs(a - st->alpha_min) <= st->band_alpha * st->alpha_min;
+                        int near_z = fabs(z - cam->znear) <= st->band_z * fabs(cam->znear);
+                        int contrib = a >= st->alpha_min && z >= cam->znear;
+                        if ((near_a && z >= cam->znear * (1 - st->band_z)) ||
+                            (near_z && a >= st->alpha_min * (1 - st->band_alpha)))
+                            ps.flag |= 1;
+                        if (g->status != OR_VISIBLE) {
+                            /* ambiguous camera-inside Gaussian */
+                            if (a >= st->alpha_min * (1 - st->band_alpha) && z >= cam->znear * (1 - st->band_z)) ps.flag |= 8;
+                            continue;
+                        }
+                        if (contrib) {
+                            seq[ns].dtile = dt[j];
+                            seq[ns].id = lists[b + j];
+                            seq[ns].z = z;
+                            seq[ns].a = a;
+                            seq[ns].c = g->color;
+                            seq[ns].tat = -1.0;
+                            ns++;
+                        }
+                    }
+                    /* O10: order by (tile depth, id) */
+                    qsort(seq, ns, sizeof(or_contrib), cmp_tile_order);
+                    window_blend(seq, ns, K, &ps, st, win);
+                    /* Near-ties in either ordering key whose swap would move the
+                     * pixel by more than a tenth of the image tolerance. */
+                    if (ns > 1) {
+                        const double imp = 1e-4;
+                        if (K == 0 || ns > K) {
+                            for (int64_t j = 1; j < ns; ++j) {
+                                double d0 = seq[j - 1].dtile, d1 = seq[j].dtile;
+                                double sc = fabs(d0) > fabs(d1) ? fabs(d0) : fabs(d1);
+                                if (fabs(d1 - d0) <= st->band_tie * sc && swap_impact(&seq[j - 1], &seq[j]) > imp)
+                                    ps.flag |= 2;
+                            }
+                        }
+                        if (K > 0) {
+                            for (int64_t j = 0; j < ns; ++j) zi[j] = j;
+                            sort_idx_by_key(zi, ns, seq);
+                            for (int64_t j = 1; j < ns; ++j) {
+                                const or_contrib *p0 = &seq[zi[j - 1]], *p1 = &seq[zi[j]];
+                                double sc = fabs(p0->z) > fabs(p1->z) ? fabs(p0->z) : fabs(p1->z);
+                                if (fabs(p1->z - p0->z) <= st->band_tie * sc && swap_impact(p0, p1) > imp) ps.flag |= 2;
+                            }
+                        }
+                    }
+                    int64_t pix = (int64_t)py * W + px;
+                    for (int k = 0; k < 3; ++k) out_rgb[(int64_t)k * H * W + pix] = ps.C[k] + ps.T * cam->bg[k];
+                    out_T[pix] = ps.T;
+                    if (out_flags) out_flags[pix] = (uint8_t)ps.flag;
+                    if (out_ncontrib) out_ncontrib[pix] = (int32_t)ns;
+                    tot_contrib += ns;
+                    tot_blend += ps.nblend;
+                    tot_flag += ps.flag != 0;
+                }
+        }
+        free(seq);
+        free(win);
+        free(dt);
+        free(zi);
+    }
+    if (stats) {
+        stats->n_visible = nvis;
+        stats->n_candidates_total = total;
+        stats->n_contrib_total = tot_contrib;
+        stats->n_blended_total = tot_blend;
+        stats->n_flagged = tot_flag;
+    }
+    free(gs);
+    free(rects);
+    free(use);
+    free(cnt);
+    free(fill);
+    free(lists);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-Gaussian outputs for stage checks: status, alpha~, tau, filtered scales,
+ * colour, view mean, |o_g|^2.  out arrays are [n] (or [3][n]).              */
+int or_preprocess(const or_scene *sc, const or_camera *cam, const or_settings *st, int32_t *status, int32_t *ambiguous,
+                  double *alpha_t, double *tau, double *s_t /*[3][n]*/, double *color /*[3][n]*/, double *mu_v /*[3][n]*/,
+                  double *og2)
+{
+    const int64_t n = sc->n;
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t i = 0; i < n; ++i) {
+        or_gauss g;
+        or_prepare(sc, cam, st, i, &g);
+        status[i] = g.status;
+        if (ambiguous) ambiguous[i] = g.ambiguous;
+        alpha_t[i] = g.alpha_t;
+        tau[i] = g.tau;
+        for (int k = 0; k < 3; ++k) {
+            s_t[k * n + i] = g.s_t[k];
+            color[k * n + i] = g.color[k];
+            mu_v[k * n + i] = g.mu_v[k];
+        }
+        og2[i] = dot3(g.o_g, g.o_g);
+    }
+    return 0;
+}
+
+/* rho^2 and depth of maximum response for query (gaussian, x, y) triples,
+ * ignoring the Gaussian's cull status (status is reported separately). */
+int or_eval_points(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t nq, const int64_t *ids,
+                   const double *xs, const double *ys, double *rho2, double *zstar, double *alpha)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t q = 0; q < nq; ++q) {
+        or_gauss g;
+        or_prepare(sc, cam, st, ids[q], &g);
+        if (g.status == OR_INVALID) {
+            rho2[q] = NAN; zstar[q] = NAN; alpha[q] = NAN;
+            continue;
+        }
+        double r2, z;
+        or_response(&g, cam, xs[q], ys[q], &r2, &z);
+        rho2[q] = r2;
+        zstar[q] = z;
+        double a = g.alpha_t * exp(-0.5 * r2);
+        alpha[q] = a > st->alpha_max ? st->alpha_max : a;
+    }
+    return 0;
+}
+
+/* Exact cone minimum for query (gaussian, rectangle) pairs; returns also tau. */
+int or_cone_min_query(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t nq, const int64_t *ids,
+                      const double *rects /*[nq][4] x0 x1 y0 y1*/, double *out_min, double *out_tau)
+{
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t q = 0; q < nq; ++q) {
+        or_gauss g;
+        or_prepare(sc, cam, st, ids[q], &g);
+        out_tau[q] = g.tau;
+        if (g.status == OR_INVALID || g.status == OR_LOW_OPACITY) {
+            out_min[q] = NAN;
+            continue;
+        }
+        out_min[q] = or_cone_min_rho2(&g, cam, rects[4 * q], rects[4 * q + 1], rects[4 * q + 2], rects[4 * q + 3]);
+    }
+    return 0;
+}
+
+/*
+ * Pair classification for one tile (O13): for each queried Gaussian,
+ *   need    = some pixel of the tile (inside the image) has alpha >= alpha_min
+ *             and z* >= znear,
+ *   near    = some pixel decision lies within the bands (exempt),
+ *   allowed = exact pyramid minimum of rho^2 < tau + (1e-3 tau + 1e-4).
+ * out_class: 0 not allowed, 1 allowed not needed, 2 needed, 3 exempt.
+ * Gaussians whose status is not VISIBLE get class 0 (or 3 if ambiguous).
+ */
+int or_classify_pairs(const or_scene *sc, const or_camera *cam, const or_settings *st, int32_t tile, int64_t nq,
+                      const int64_t *ids, int32_t *out_class)
+{
+    const int W = cam->width, H = cam->height;
+    const int tiles_x = (W + OR_TILE - 1) / OR_TILE;
+    int tx = tile % tiles_x, ty = tile / tiles_x;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < nq; ++q) {
+        or_gauss g;
+        or_prepare(sc, cam, st, ids[q], &g);
+        if (g.status != OR_VISIBLE) {
+            out_class[q] = (g.status == OR_CAM_INSIDE && g.ambiguous) ? 3 : 0;
+            continue;
+        }
+        int need = 0, near = 0;
+        for (int py = ty * OR_TILE; py < ty * OR_TILE + OR_TILE && py < H; ++py)
+            for (int px = tx * OR_TILE; px < tx * OR_TILE + OR_TILE && px < W; ++px) {
+                double r2, z;
+                or_response(&g, cam, px + 0.5, py + 0.5, &r2, &z);
+                double a = g.alpha_t * exp(-0.5 * r2);
+                if (a > st->alpha_max) a = st->alpha_max;
+                if (a >= st->alpha_min && z >= cam->znear) need = 1;
+                if (fabs(a - st->alpha_min) <= st->band_alpha * st->alpha_min && z >= cam->znear * (1 - st->band_z)) near = 1;
+                if (fabs(z - cam->znear) <= st->band_z * fabs(cam->znear) && a >= st->alpha_min * (1 - st->band_alpha)) near = 1;
+            }
+        double m = or_cone_min_rho2(&g, cam, tx * OR_TILE, tx * OR_TILE + OR_TILE, ty * OR_TILE, ty * OR_TILE + OR_TILE);
+        int allowed = m < g.tau + (1e-3 * g.tau + 1e-4);
+        if (need) out_class[q] = 2;
+        else if (near) out_class[q] = 3;
+        else out_class[q] = allowed ? 1 : 0;
+    }
+    return 0;
+}
+
+/*
+ * Reference screen bounds (O14): the x and y screen range covered by the
+ * level-tau ellipsoid's surface points with view depth > 0, from a dense
+ * (nt x np) sampling of the surface.  out[4] = xmin, xmax, ymin, ymax (may be
+ * +-inf when the surface reaches depth 0 with a nonzero lateral offset).
+ * Returns the Gaussian's status.
+ */
+int or_sampled_bounds(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t i, int nt, int np,
+                      double *out)
+{
+    or_gauss g;
+    or_prepare(sc, cam, st, i, &g);
+    out[0] = INFINITY; out[1] = -INFINITY; out[2] = INFINITY; out[3] = -INFINITY;
+    if (g.status == OR_INVALID || g.status == OR_LOW_OPACITY) return g.status;
+    double r = sqrt(g.tau);
+    for (int a = 0; a <= nt; ++a) {
+        double th = M_PI * a / nt;
+        for (int b = 0; b < np; ++b) {
+            double ph = 2 * M_PI * b / np;
+            double p[3] = {r * sin(th) * cos(ph), r * sin(th) * sin(ph), r * cos(th)}, X[3];
+            matvec3(g.M, p, X);
+            for (int k = 0; k < 3; ++k) X[k] += g.mu_v[k];
+            if (!(X[2] > 0)) continue;
+            double xs = cam->cx + cam->fx * X[0] / X[2];
+            double ys = cam->cy + cam->fy * X[1] / X[2];
+            if (xs < out[0]) out[0] = xs;
+            if (xs > out[1]) out[1] = xs;
+            if (ys < out[2]) out[2] = ys;
+            if (ys > out[3]) out[3] = ys;
+        }
+    }
+    return g.status;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
