@@ -1,0 +1,188 @@
+/*
+ * aaa.h -- C ABI of the MI355X (gfx950) AAA-Gaussians rasteriser.
+ *
+ * Renders a cloud of anisotropic 3D Gaussians through a pinhole camera with
+ * the method of "AAA-Gaussians: Anti-Aliased and Artifact-Free 3D Gaussian
+ * Rendering" (arXiv 2504.12811):
+ *   - every Gaussian is evaluated in 3D at its point of maximum response
+ *     along the pixel's line (Sec. 3.1, Eq. 4-5);
+ *   - an adaptive 3D smoothing filter with perpendicular amplitude
+ *     normalisation and the training-frequency clamp (Sec. 3.2, Eq. 6-13);
+ *   - view-space angular bounding that survives Gaussians crossing the
+ *     camera plane (Sec. 3.3, Eq. 14-17) and a camera-inside discard;
+ *   - 3D frustum culling of each (Gaussian, tile) pair and of the whole view
+ *     (Sec. 3.4, Eq. 18);
+ *   - hierarchical ordering: tiles sorted by a per-tile 3D depth, then a
+ *     bounded per-ray window (Sec. 3.1 "Blending Sort Order", Sec. 4);
+ *   - front-to-back alpha blending with early termination.
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays marked DEVICE are device memory on the context's GPU, owned by
+ *     the caller; the library never frees or retains them past the call's
+ *     stream work.  Structs passed by pointer are host memory, read during
+ *     the call only.
+ *   - Scene arrays are float32 structure-of-arrays (index [k][i] is element
+ *     k*n + i).  Images are float32 planar: rgb [3][H][W], T [H][W].
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it; calls return after enqueueing, except where noted.
+ *   - Every call returns an aaa_status.  On failure nothing was enqueued
+ *     unless the status is AAA_ERR_HIP; aaa_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - A context, a workspace or a scene is used by one call at a time; calls
+ *     on different contexts/workspaces may overlap.
+ */
+#ifndef AAA_H
+#define AAA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AAA_OK = 0,
+    AAA_ERR_INVALID = 1,        /* bad argument (NULL, size, degree) */
+    AAA_ERR_WORKSPACE = 2,      /* workspace smaller than aaa_workspace_size() */
+    AAA_ERR_PAIR_OVERFLOW = 3,  /* more (Gaussian, tile) pairs than max_pairs; stats->pairs holds the need */
+    AAA_ERR_HIP = 4,            /* a HIP runtime call failed */
+    AAA_ERR_UNSUPPORTED = 5     /* e.g. sh_degree > 3 */
+} aaa_status;
+
+/* Scene (Sec. 3.1): mean mu, log-scale (s = exp), rotation quaternion
+ * (w,x,y,z; normalised inside), opacity logit (alpha = sigmoid), real
+ * spherical-harmonic colour coefficients of degree <= 3 (colour =
+ * max(0, 0.5 + sum Y_lm(d) c_lm), d = unit camera->mean direction), and the
+ * per-Gaussian maximum training sampling frequency v_train of Sec. 3.2
+ * (Eq. 6, 13) in pixels per world unit (NULL: no clamp).  All DEVICE. */
+typedef struct {
+    int64_t n;
+    int32_t sh_degree;
+    int32_t _pad;
+    const float *means;          /* [3][n] */
+    const float *log_scales;     /* [3][n] */
+    const float *quats;          /* [4][n] */
+    const float *opacity_logits; /* [n] */
+    const float *sh;             /* [(sh_degree+1)^2][3][n] */
+    const float *v_train;        /* [n] or NULL; values > 0, +inf allowed */
+} aaa_scene;
+
+/* Gradients, same layouts as aaa_scene; DEVICE; accumulated (+=). */
+typedef struct {
+    float *means;
+    float *log_scales;
+    float *quats;
+    float *opacity_logits;
+    float *sh;
+} aaa_scene_grad;
+
+/* Pinhole camera (Sec. 3.1: viewport * projection * view).  viewmat is the
+ * rigid world->view matrix, row-major, view axes +x right, +y down, +z
+ * forward; pixel (i, j) has centre (i + 0.5, j + 0.5); screen x = cx + fx X/Z.
+ * znear: smallest depth of a contributing maximum (pixels only blend a
+ * Gaussian whose maximum along the line lies at depth >= znear).  Host. */
+typedef struct {
+    double viewmat[16];
+    double fx, fy, cx, cy;
+    int32_t width, height;
+    double znear;
+    double bg[3];
+} aaa_camera;
+
+#define AAA_FILTER_OFF 1u      /* no 3D smoothing filter (alpha~ = alpha) */
+#define AAA_FILTER_VOLUME 2u   /* volume-normalised amplitude (Eq. 7-8) instead of Eq. 12 */
+#define AAA_NO_TILE_CULL 4u    /* keep every tile of the bounding rectangle (no Eq. 18 per tile) */
+#define AAA_STATS 8u           /* count evaluations / contributors (small overhead) */
+
+/* Method settings.  filter_k: filter size k (0.3 in Sec. 4).  ray_window:
+ * capacity K of the per-ray re-sort window (0 = blend in tile order; the
+ * supported values are 0, 1, 2, 4, 8, 16, 32).  alpha_min: contribution
+ * threshold (a Gaussian contributes to a pixel iff min(alpha_max, alpha~
+ * exp(-rho^2/2)) >= alpha_min); alpha_max: opacity clamp; t_min: blending
+ * stops before the first entry that would take transmittance below t_min.
+ * Host. */
+typedef struct {
+    double filter_k;
+    int32_t ray_window;
+    uint32_t flags;
+    double alpha_min, alpha_max, t_min;
+} aaa_settings;
+
+/* Per-frame counters, host. */
+typedef struct {
+    uint64_t pairs;          /* (Gaussian, tile) pairs after culling */
+    uint64_t visible;        /* Gaussians that survived preprocessing */
+    uint64_t evaluations;    /* pixel x list-entry evaluations (AAA_STATS) */
+    uint64_t contributors;   /* evaluations that passed the contribution test (AAA_STATS) */
+    uint64_t candidate_tiles;/* tile tests executed by the pair emitter (AAA_STATS) */
+    float ms_stage[8];       /* reserved */
+} aaa_stats;
+
+typedef struct aaa_ctx aaa_ctx;
+
+/* Create a context on HIP device `device` (makes it current on this thread). */
+int aaa_create(aaa_ctx **out, int device);
+void aaa_destroy(aaa_ctx *ctx);
+const char *aaa_last_error(void);
+/* Library version string, static storage. */
+const char *aaa_version(void);
+
+/* Bytes of workspace needed to render `scene` through `cam` with room for
+ * max_pairs (Gaussian, tile) pairs.  Host-only computation. */
+int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
+                       uint64_t max_pairs, size_t *bytes_out);
+
+/* Render one view.  out_rgb [3][H][W] = blended colour + T * bg,
+ * out_T [H][W] = final transmittance (DEVICE, written).  The workspace
+ * (DEVICE, >= aaa_workspace_size bytes, 256-byte aligned) keeps the frame's
+ * per-Gaussian records, sorted pairs and per-pixel state until it is used
+ * again; aaa_render_backward reads them.  The call synchronises `stream`
+ * once to learn the pair count; on AAA_ERR_PAIR_OVERFLOW stats->pairs is the
+ * count needed and the outputs are not written.  stats (host) may be NULL. */
+int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
+               void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, float *out_rgb, float *out_T,
+               aaa_stats *stats);
+
+/* Gradient of a scalar loss L given dL/d(out_rgb) [3][H][W] (DEVICE) for the
+ * last aaa_render into `ws` with the same scene, camera and settings.
+ * Accumulates into `grad` (DEVICE arrays, same layouts as the scene; any
+ * pointer may be NULL to skip it).  The blend state is recomputed per tile
+ * (no per-pixel lists are stored).  Decisions (culls, thresholds, clamps)
+ * are held fixed; their gradients are zero or one-sided. */
+int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
+                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *dL_drgb,
+                        aaa_scene_grad *grad);
+
+/* ---- stage outputs of the last aaa_render into `ws` (for checks) ------ */
+
+/* Per-Gaussian preprocessing results (DEVICE outputs, each may be NULL):
+ * status [n] (0 visible, 1 invalid input, 2 alpha~ < alpha_min, 3 camera
+ * inside the level set, 4 outside the view / empty bounds), alpha_t [n]
+ * (filtered opacity alpha~), tau [n] (rho^2 level where alpha~ exp(-rho^2/2)
+ * = alpha_min), color [3][n], rect [4][n] (tile rectangle tx0, tx1, ty0,
+ * ty1, half-open). */
+int aaa_read_gaussians(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_pairs, const void *ws,
+                       size_t ws_bytes, void *stream, int32_t *status, float *alpha_t, float *tau, float *color,
+                       int32_t *rect);
+
+/* Sorted pairs of the last frame: keys [pairs] (tile id << 32 | order key of
+ * the tile depth), values [pairs] (Gaussian index), and tile ranges
+ * [tiles][2] (start, end).  DEVICE outputs sized by the caller (cap pairs);
+ * *n_pairs (host) receives the count.  Synchronises `stream`. */
+int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_pairs, const void *ws,
+                   size_t ws_bytes, void *stream, uint64_t *keys, uint32_t *values, uint32_t *ranges, uint64_t cap,
+                   uint64_t *n_pairs);
+
+/* Stable LSD radix sort of (key, value) pairs by the low `key_bits` bits of
+ * the keys (1..64), in place (DEVICE arrays of n).  tmp: DEVICE scratch of
+ * aaa_sort_tmp_size(n) bytes. */
+int aaa_sort_tmp_size(uint64_t n, size_t *bytes_out);
+int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits, void *tmp, size_t tmp_bytes,
+                   void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAA_H */

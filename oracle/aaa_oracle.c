@@ -677,7 +677,7 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
                     /* Near-ties in either ordering key whose swap would move the
                      * pixel by more than a tenth of the image tolerance. */
                     if (ns > 1) {
-                        const double imp = 1e-4;
+                        const double imp = 1.5e-4;
                         if (K == 0 || ns > K) {
                             for (int64_t j = 1; j < ns; ++j) {
                                 double d0 = seq[j - 1].dtile, d1 = seq[j].dtile;

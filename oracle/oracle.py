@@ -25,7 +25,7 @@ VISIBLE, INVALID, LOW_OPACITY, CAM_INSIDE, OUTSIDE = 0, 1, 2, 3, 4
 # decision the other way; pixels touched by such a decision are flagged.
 BAND_ALPHA = 3e-5
 BAND_Z = 1e-5
-BAND_TIE = 4e-6
+BAND_TIE = 2e-6
 BAND_T = 1e-3
 
 

@@ -1,0 +1,217 @@
+// Internal definitions shared by the HIP kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aaa {
+
+constexpr int kTile = 16;          // tile edge in pixels
+constexpr int kRecQuads = 8;       // float4 per blend record (128 B)
+constexpr int kCullQuads = 8;      // float4 per culling record (128 B)
+constexpr float kLog2eHalf = 0.72134752044448170368f;  // log2(e) / 2
+
+enum Status : int32_t { kVisible = 0, kInvalid = 1, kLowOpacity = 2, kCamInside = 3, kOutside = 4 };
+
+// Blend record of one Gaussian for one view (128 B, float4 granularity):
+//   r_g(dx,dy) = c0 + dx c1 + dy c2   line direction in normalised Gaussian space
+//   w(dx,dy)   = w0 + dx w1 + dy w2   o_g x r_g
+//   l(dx,dy)   = l0 + dx l1 + dy l2   -o_g . r_g
+// with (dx, dy) the pixel-centre offset from the anchor (xa, ya), itself a
+// pixel centre, so offsets are exact in float.  rho^2 = |w|^2 / |r_g|^2 and
+// the depth of the maximum is l / |r_g|^2 (c, w scaled by lambda, l by lambda^2).
+//   q0 = c0x c0y c0z c1x     q4 = w2y w2z l0 l1
+//   q1 = c1y c1z c2x c2y     q5 = l2 xa ya alpha~
+//   q2 = c2z w0x w0y w0z     q6 = tau_pre tau og2 -
+//   q3 = w1x w1y w1z w2x     q7 = r g b -
+// Culling record (screen-plane geometry relative to the anchor, view space):
+//   plane x = xa + D: normal in Gaussian space nx0 - D nx1, offset dx0 - D dx1,
+//   Sigma~_view (1,0,-u) = qx0 - D qx1; same for y.
+//   p0 = dx0 dx1 dy0 dy1      p4 = qx0 qx1.x
+//   p1 = nx0 nx1.x            p5 = qx1.yz qy0.xy
+//   p2 = nx1.yz ny0.xy        p6 = qy0.z qy1
+//   p3 = ny0.z ny1            p7 = mu_view -
+struct Rec {
+    float c0[3], c1[3], c2[3], w0[3], w1[3], w2[3], l[3];
+    float xa, ya, alpha, tau_pre, tau, og2;
+};
+
+template <typename T>
+struct TileGeom {
+    T xa, ya;
+    T c0[3], c1[3], c2[3], w0[3], w1[3], w2[3], l[3];
+    T og2;
+    T dx0, dx1, dy0, dy1;
+    T nx0[3], nx1[3], ny0[3], ny1[3];
+    T qx0[3], qx1[3], qy0[3], qy1[3];
+    T muv[3];
+};
+
+struct CamDev {
+    double fx, fy, cx, cy;
+    int32_t width, height, tiles_x, tiles_y;
+    double znear;
+};
+
+template <typename T>
+__device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Minimum of rho^2 over the pyramid of the screen rectangle [x0,x1]x[y0,y1]
+// (Eq. 18).  The pyramid is four half-spaces through the camera centre; the
+// minimum of the convex rho^2 lies on a face whose half-space the mean
+// violates (or is 0 when the mean is inside).  For each such face: the plane
+// minimum if it lies inside the face (checked with a small slack so that the
+// result never exceeds the exact minimum by more than rounding), and the
+// minima on the face's two edge rays (the apex when the edge minimum is
+// behind the camera).  Rectangle corners are given relative to the anchor.
+template <typename T>
+__device__ __forceinline__ T edge_min(const TileGeom<T> &g, T dX, T dY)
+{
+    T r[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r[k] = g.c0[k] + dX * g.c1[k] + dY * g.c2[k];
+        w[k] = g.w0[k] + dX * g.w1[k] + dY * g.w2[k];
+    }
+    T l = g.l[0] + dX * g.l[1] + dY * g.l[2];
+    T v = dot3(w, w) / dot3(r, r);
+    return l > T(0) ? v : g.og2;
+}
+
+// plane x = xa + dX (vert=true) or y = ya + dY (vert=false); s = signed plane
+// offset; [lo, hi] = the other axis' range as view slopes.
+template <typename T>
+__device__ __forceinline__ T plane_min(const TileGeom<T> &g, bool vert, T D, T s, T lo, T hi)
+{
+    const T *n0 = vert ? g.nx0 : g.ny0;
+    const T *n1 = vert ? g.nx1 : g.ny1;
+    const T *q0 = vert ? g.qx0 : g.qy0;
+    const T *q1 = vert ? g.qx1 : g.qy1;
+    T n[3], q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        n[k] = n0[k] - D * n1[k];
+        q[k] = q0[k] - D * q1[k];
+    }
+    T nn = dot3(n, n);
+    T val = s * s / nn;
+    T f = s / nn;
+    T X[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) X[k] = g.muv[k] - f * q[k];
+    T o = vert ? X[1] : X[0];  // the coordinate bounded by [lo, hi] * z
+    T a = o - lo * X[2];
+    T b = hi * X[2] - o;
+    T scale = (o < T(0) ? -o : o) + (X[2] < T(0) ? -X[2] : X[2]) * ((lo < T(0) ? -lo : lo) + (hi < T(0) ? -hi : hi));
+    T tol = (sizeof(T) == 4 ? T(1e-4) : T(1e-9)) * scale;
+    bool feas = a >= -tol && b >= -tol;
+    return feas ? val : T(INFINITY);
+}
+
+template <typename T>
+__device__ __forceinline__ T tile_min_rho2(const TileGeom<T> &g, T x0, T x1, T y0, T y1, const CamDev &cam)
+{
+    T dX0 = x0 - g.xa, dX1 = x1 - g.xa, dY0 = y0 - g.ya, dY1 = y1 - g.ya;
+    T sL = g.dx0 - dX0 * g.dx1;
+    T sR = g.dx0 - dX1 * g.dx1;
+    T sT = g.dy0 - dY0 * g.dy1;
+    T sB = g.dy0 - dY1 * g.dy1;
+    bool vL = sL < T(0), vR = sR > T(0), vT = sT < T(0), vB = sB > T(0);
+    if (!(vL || vR || vT || vB)) return T(0);
+    T best = g.og2;
+    T u0 = (x0 - T(cam.cx)) / T(cam.fx), u1 = (x1 - T(cam.cx)) / T(cam.fx);
+    T v0 = (y0 - T(cam.cy)) / T(cam.fy), v1 = (y1 - T(cam.cy)) / T(cam.fy);
+    if (vL || vT) best = fmin(best, edge_min(g, dX0, dY0));
+    if (vL || vB) best = fmin(best, edge_min(g, dX0, dY1));
+    if (vR || vT) best = fmin(best, edge_min(g, dX1, dY0));
+    if (vR || vB) best = fmin(best, edge_min(g, dX1, dY1));
+    if (vL) best = fmin(best, plane_min(g, true, dX0, sL, v0, v1));
+    if (vR) best = fmin(best, plane_min(g, true, dX1, sR, v0, v1));
+    if (vT) best = fmin(best, plane_min(g, false, dY0, sT, u0, u1));
+    if (vB) best = fmin(best, plane_min(g, false, dY1, sB, u0, u1));
+    return best;
+}
+
+__device__ __forceinline__ void load_tile_geom(const float4 *__restrict__ rec, const float4 *__restrict__ cull, TileGeom<float> &g)
+{
+    float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5], q6 = rec[6];
+    g.c0[0] = q0.x; g.c0[1] = q0.y; g.c0[2] = q0.z;
+    g.c1[0] = q0.w; g.c1[1] = q1.x; g.c1[2] = q1.y;
+    g.c2[0] = q1.z; g.c2[1] = q1.w; g.c2[2] = q2.x;
+    g.w0[0] = q2.y; g.w0[1] = q2.z; g.w0[2] = q2.w;
+    g.w1[0] = q3.x; g.w1[1] = q3.y; g.w1[2] = q3.z;
+    g.w2[0] = q3.w; g.w2[1] = q4.x; g.w2[2] = q4.y;
+    g.l[0] = q4.z; g.l[1] = q4.w; g.l[2] = q5.x;
+    g.xa = q5.y; g.ya = q5.z;
+    g.og2 = q6.z;
+    float4 p0 = cull[0], p1 = cull[1], p2 = cull[2], p3 = cull[3], p4 = cull[4], p5 = cull[5], p6 = cull[6], p7 = cull[7];
+    g.dx0 = p0.x; g.dx1 = p0.y; g.dy0 = p0.z; g.dy1 = p0.w;
+    g.nx0[0] = p1.x; g.nx0[1] = p1.y; g.nx0[2] = p1.z;
+    g.nx1[0] = p1.w; g.nx1[1] = p2.x; g.nx1[2] = p2.y;
+    g.ny0[0] = p2.z; g.ny0[1] = p2.w; g.ny0[2] = p3.x;
+    g.ny1[0] = p3.y; g.ny1[1] = p3.z; g.ny1[2] = p3.w;
+    g.qx0[0] = p4.x; g.qx0[1] = p4.y; g.qx0[2] = p4.z;
+    g.qx1[0] = p4.w; g.qx1[1] = p5.x; g.qx1[2] = p5.y;
+    g.qy0[0] = p5.z; g.qy0[1] = p5.w; g.qy0[2] = p6.x;
+    g.qy1[0] = p6.y; g.qy1[1] = p6.z; g.qy1[2] = p6.w;
+    g.muv[0] = p7.x; g.muv[1] = p7.y; g.muv[2] = p7.z;
+}
+
+// Order-preserving map of a float to uint32 (-0 -> +0; NaN never occurs).
+__device__ __forceinline__ uint32_t order_key(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    if (b == 0x80000000u) b = 0u;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Tile-pair keep test shared by the pair counter and writer: pyramid minimum
+// below tau with a relative slack of 2e-4 (+1e-5) for float rounding.
+__device__ __forceinline__ bool keep_threshold(float m, float tau) { return m < tau * (1.0f + 2e-4f) + 1e-5f; }
+
+}  // namespace aaa
+
+// Host-side launchers (defined in the .hip files).
+namespace aaa {
+struct PreArgs {
+    const float *means, *log_scales, *quats, *logits, *sh, *v_train;
+    int64_t n;
+    int sh_degree;
+    double RV[9], tV[3], o[3];
+    CamDev cam;
+    double filter_k, alpha_min, alpha_max;
+    int filter_mode;  // 0 adaptive, 1 off, 2 volume
+    int32_t *status;
+    int4 *rect;
+    float4 *rec;
+    float4 *cull;
+};
+hipError_t launch_preprocess(const PreArgs &a, hipStream_t s);
+
+hipError_t launch_count_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
+                              CamDev cam, bool tile_cull, uint32_t *counts, unsigned long long *tests, hipStream_t s);
+hipError_t launch_write_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
+                              CamDev cam, bool tile_cull, const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys,
+                              uint32_t *vals, hipStream_t s);
+size_t scan_tmp_bytes(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s);
+
+size_t sort_tmp_bytes(uint64_t n);
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
+                            int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt);
+hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
+
+struct BlendArgs {
+    const float4 *rec;
+    const uint64_t *keys;
+    const uint32_t *vals;
+    const uint32_t *ranges;
+    CamDev cam;
+    float alpha_min, alpha_max, t_min, znear;
+    float bg[3];
+    float *out_rgb, *out_T;
+    uint32_t *n_done;  // per pixel: list entries consumed
+    unsigned long long *counters;  // [0] evaluations, [1] contributors
+};
+hipError_t launch_blend(const BlendArgs &a, int K, bool stats, hipStream_t s);
+}  // namespace aaa

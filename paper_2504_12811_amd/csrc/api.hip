@@ -1,0 +1,367 @@
+// Host side of the C ABI: argument checks, workspace layout and the launch
+// sequence preprocess -> pair count -> scan -> pair write -> radix sort ->
+// tile ranges -> blend (and the backward pair of kernels).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "aaa_internal.h"
+#include "../../include/aaa.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(AAA_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t hdr, status, rect, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp, ranges,
+        n_done, total;
+};
+
+int tiles_of(const aaa_camera *cam, int *tx, int *ty)
+{
+    *tx = (cam->width + aaa::kTile - 1) / aaa::kTile;
+    *ty = (cam->height + aaa::kTile - 1) / aaa::kTile;
+    return (*tx) * (*ty);
+}
+
+Layout layout(int64_t n, const aaa_camera *cam, uint64_t max_pairs)
+{
+    Layout L;
+    int tx, ty;
+    int ntiles = tiles_of(cam, &tx, &ty);
+    size_t pix = (size_t)cam->width * cam->height;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    int64_t nn = n > 0 ? n : 1;
+    L.hdr = take(256);
+    L.status = take(nn * 4);
+    L.rect = take(nn * 16);
+    L.rec = take(nn * 16 * aaa::kRecQuads);
+    L.cull = take(nn * 16 * aaa::kCullQuads);
+    L.counts = take(nn * 4);
+    L.offsets = take((nn + 1) * 8);
+    L.scan_tmp = take(aaa::scan_tmp_bytes(nn));
+    uint64_t mp = max_pairs > 0 ? max_pairs : 1;
+    L.keys = take(mp * 8);
+    L.keys_alt = take(mp * 8);
+    L.vals = take(mp * 4);
+    L.vals_alt = take(mp * 4);
+    L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
+    L.ranges = take((size_t)ntiles * 8);
+    L.n_done = take(pix * 4);
+    L.total = o;
+    return L;
+}
+
+int key_bits(int ntiles)
+{
+    int b = 0;
+    while ((1ll << b) < ntiles) ++b;
+    return 32 + b;
+}
+
+// The sort runs ceil(bits/8) passes, ping-ponging between the two buffers.
+bool sorted_in_alt(int ntiles) { return ((key_bits(ntiles) + 7) / 8) % 2 == 1; }
+
+int check_common(const aaa_scene *sc, const aaa_camera *cam, const aaa_settings *st)
+{
+    if (!sc || !cam || !st) return fail(AAA_ERR_INVALID, "null scene/camera/settings");
+    if (sc->n < 0 || sc->n >= (1ll << 32)) return fail(AAA_ERR_INVALID, "scene size %lld out of range", (long long)sc->n);
+    if (sc->sh_degree < 0 || sc->sh_degree > 3) return fail(AAA_ERR_UNSUPPORTED, "sh_degree %d not in 0..3", sc->sh_degree);
+    if (sc->n > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+        return fail(AAA_ERR_INVALID, "null scene array");
+    if (cam->width <= 0 || cam->height <= 0 || cam->width > 32768 || cam->height > 32768)
+        return fail(AAA_ERR_INVALID, "image size %dx%d out of range", cam->width, cam->height);
+    if (!(cam->fx > 0) || !(cam->fy > 0) || !(cam->znear > 0))
+        return fail(AAA_ERR_INVALID, "focal lengths and znear must be positive");
+    int K = st->ray_window;
+    if (!(K == 0 || K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32))
+        return fail(AAA_ERR_INVALID, "ray_window %d not one of 0,1,2,4,8,16,32", K);
+    if (!(st->alpha_min > 0 && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0 && st->t_min >= 0 && st->t_min < 1))
+        return fail(AAA_ERR_INVALID, "need 0 < alpha_min < alpha_max <= 1 and 0 <= t_min < 1");
+    if (!(st->filter_k >= 0)) return fail(AAA_ERR_INVALID, "filter_k must be >= 0");
+    return AAA_OK;
+}
+
+aaa::CamDev cam_dev(const aaa_camera *cam)
+{
+    aaa::CamDev c;
+    c.fx = cam->fx;
+    c.fy = cam->fy;
+    c.cx = cam->cx;
+    c.cy = cam->cy;
+    c.width = cam->width;
+    c.height = cam->height;
+    c.tiles_x = (cam->width + aaa::kTile - 1) / aaa::kTile;
+    c.tiles_y = (cam->height + aaa::kTile - 1) / aaa::kTile;
+    c.znear = cam->znear;
+    return c;
+}
+
+template <typename T>
+T *at(void *ws, size_t off) { return (T *)((char *)ws + off); }
+
+}  // namespace
+
+struct aaa_ctx {
+    int device;
+};
+
+extern "C" {
+
+const char *aaa_last_error(void) { return g_err.c_str(); }
+
+const char *aaa_version(void) { return "aaa-gfx950 0.1"; }
+
+int aaa_create(aaa_ctx **out, int device)
+{
+    if (!out) return fail(AAA_ERR_INVALID, "null out");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(AAA_ERR_INVALID, "device %d of %d", device, count);
+    HIP_TRY(hipSetDevice(device));
+    aaa_ctx *c = new aaa_ctx;
+    c->device = device;
+    *out = c;
+    return AAA_OK;
+}
+
+void aaa_destroy(aaa_ctx *ctx) { delete ctx; }
+
+int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, uint64_t max_pairs,
+                       size_t *bytes_out)
+{
+    int rc = check_common(scene, cam, settings);
+    if (rc) return rc;
+    if (!bytes_out) return fail(AAA_ERR_INVALID, "null bytes_out");
+    if (max_pairs >= (1ull << 32)) return fail(AAA_ERR_INVALID, "max_pairs must be < 2^32");
+    *bytes_out = layout(scene->n, cam, max_pairs).total;
+    return AAA_OK;
+}
+
+int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, void *ws,
+               size_t ws_bytes, uint64_t max_pairs, void *stream, float *out_rgb, float *out_T, aaa_stats *stats)
+{
+    if (!ctx) return fail(AAA_ERR_INVALID, "null context");
+    int rc = check_common(scene, cam, settings);
+    if (rc) return rc;
+    if (max_pairs >= (1ull << 32)) return fail(AAA_ERR_INVALID, "max_pairs must be < 2^32");
+    if (!ws || !out_rgb || !out_T) return fail(AAA_ERR_INVALID, "null workspace or output");
+    if (((uintptr_t)ws & 255) != 0) return fail(AAA_ERR_INVALID, "workspace must be 256-byte aligned");
+    Layout L = layout(scene->n, cam, max_pairs);
+    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t n = scene->n;
+    int tx, ty;
+    const int ntiles = tiles_of(cam, &tx, &ty);
+    aaa::CamDev cd = cam_dev(cam);
+    const bool want_stats = (settings->flags & AAA_STATS) != 0;
+    unsigned long long *ctr = at<unsigned long long>(ws, L.hdr);  // [0] visible [1] tests [2] evals [3] contribs
+    HIP_TRY(hipMemsetAsync(ctr, 0, 64, s));
+
+    aaa::PreArgs pa;
+    pa.means = scene->means;
+    pa.log_scales = scene->log_scales;
+    pa.quats = scene->quats;
+    pa.logits = scene->opacity_logits;
+    pa.sh = scene->sh;
+    pa.v_train = scene->v_train;
+    pa.n = n;
+    pa.sh_degree = scene->sh_degree;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) pa.RV[3 * r + c] = cam->viewmat[4 * r + c];
+        pa.tV[r] = cam->viewmat[4 * r + 3];
+    }
+    for (int r = 0; r < 3; ++r) pa.o[r] = -(pa.RV[r] * pa.tV[0] + pa.RV[3 + r] * pa.tV[1] + pa.RV[6 + r] * pa.tV[2]);
+    pa.cam = cd;
+    pa.filter_k = settings->filter_k;
+    pa.alpha_min = settings->alpha_min;
+    pa.alpha_max = settings->alpha_max;
+    pa.filter_mode = (settings->flags & AAA_FILTER_OFF) ? 1 : ((settings->flags & AAA_FILTER_VOLUME) ? 2 : 0);
+    pa.status = at<int32_t>(ws, L.status);
+    pa.rect = at<int4>(ws, L.rect);
+    pa.rec = at<float4>(ws, L.rec);
+    pa.cull = at<float4>(ws, L.cull);
+    HIP_TRY(aaa::launch_preprocess(pa, s));
+
+    const bool tile_cull = (settings->flags & AAA_NO_TILE_CULL) == 0;
+    uint32_t *counts = at<uint32_t>(ws, L.counts);
+    uint64_t *offsets = at<uint64_t>(ws, L.offsets);
+    HIP_TRY(aaa::launch_count_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, cd, tile_cull, counts, ctr, s));
+    HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, n, at<void>(ws, L.scan_tmp), s));
+    uint64_t P = 0;
+    HIP_TRY(hipMemcpyAsync(&P, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        stats->pairs = P;
+    }
+    if (P > max_pairs) return fail(AAA_ERR_PAIR_OVERFLOW, "%llu pairs exceed max_pairs %llu", (unsigned long long)P,
+                                   (unsigned long long)max_pairs);
+    uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
+    uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
+    HIP_TRY(aaa::launch_write_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, cd, tile_cull, offsets, max_pairs, keys,
+                                    vals, s));
+    bool in_alt = false;
+    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,
+                                  &in_alt));
+    if (P > 1 && in_alt != sorted_in_alt(ntiles)) return fail(AAA_ERR_HIP, "internal: sort parity");
+    const uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
+    const uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
+    if (P <= 1 && sorted_in_alt(ntiles)) {
+        // keep the invariant "sorted pairs live where sorted_in_alt says"
+        HIP_TRY(hipMemcpyAsync(keys_alt, keys, P * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(vals_alt, vals, P * 4, hipMemcpyDeviceToDevice, s));
+        skeys = keys_alt;
+        svals = vals_alt;
+    }
+    uint32_t *ranges = at<uint32_t>(ws, L.ranges);
+    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, ntiles, s));
+
+    aaa::BlendArgs ba;
+    ba.rec = pa.rec;
+    ba.keys = skeys;
+    ba.vals = svals;
+    ba.ranges = ranges;
+    ba.cam = cd;
+    ba.alpha_min = (float)settings->alpha_min;
+    ba.alpha_max = (float)settings->alpha_max;
+    ba.t_min = (float)settings->t_min;
+    ba.znear = (float)cam->znear;
+    for (int k = 0; k < 3; ++k) ba.bg[k] = (float)cam->bg[k];
+    ba.out_rgb = out_rgb;
+    ba.out_T = out_T;
+    ba.n_done = at<uint32_t>(ws, L.n_done);
+    ba.counters = ctr + 2;
+    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, s));
+    if (stats && want_stats) {
+        unsigned long long h[4];
+        HIP_TRY(hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        stats->visible = h[0];
+        stats->candidate_tiles = h[1];
+        stats->evaluations = h[2];
+        stats->contributors = h[3];
+    }
+    return AAA_OK;
+}
+
+int aaa_read_gaussians(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_pairs, const void *ws,
+                       size_t ws_bytes, void *stream, int32_t *status, float *alpha_t, float *tau, float *color,
+                       int32_t *rect)
+{
+    if (!scene || !cam || !ws) return fail(AAA_ERR_INVALID, "null argument");
+    Layout L = layout(scene->n, cam, max_pairs);
+    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = scene->n;
+    if (n == 0) return AAA_OK;
+    const char *w = (const char *)ws;
+    if (status) HIP_TRY(hipMemcpyAsync(status, w + L.status, n * 4, hipMemcpyDeviceToDevice, s));
+    // strided fields of the records: rec[i].q5.w = alpha~, rec[i].q6.y = tau, rec[i].q7.xyz = colour
+    const size_t stride = 16 * aaa::kRecQuads;
+    if (alpha_t) HIP_TRY(hipMemcpy2DAsync(alpha_t, 4, w + L.rec + 5 * 16 + 12, stride, 4, n, hipMemcpyDeviceToDevice, s));
+    if (tau) HIP_TRY(hipMemcpy2DAsync(tau, 4, w + L.rec + 6 * 16 + 4, stride, 4, n, hipMemcpyDeviceToDevice, s));
+    if (color)
+        for (int c = 0; c < 3; ++c)
+            HIP_TRY(hipMemcpy2DAsync(color + c * n, 4, w + L.rec + 7 * 16 + 4 * c, stride, 4, n,
+                                     hipMemcpyDeviceToDevice, s));
+    if (rect)
+        for (int c = 0; c < 4; ++c)
+            HIP_TRY(hipMemcpy2DAsync(rect + c * n, 4, w + L.rect + 4 * c, 16, 4, n, hipMemcpyDeviceToDevice, s));
+    return AAA_OK;
+}
+
+int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_pairs, const void *ws, size_t ws_bytes,
+                   void *stream, uint64_t *keys, uint32_t *values, uint32_t *ranges, uint64_t cap, uint64_t *n_pairs)
+{
+    if (!scene || !cam || !ws || !n_pairs) return fail(AAA_ERR_INVALID, "null argument");
+    Layout L = layout(scene->n, cam, max_pairs);
+    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    const char *w = (const char *)ws;
+    uint64_t P = 0;
+    HIP_TRY(hipMemcpyAsync(&P, w + L.offsets + 8 * (size_t)scene->n, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_pairs = P;
+    if (P > max_pairs) return fail(AAA_ERR_PAIR_OVERFLOW, "last frame overflowed");
+    if (P > cap) return fail(AAA_ERR_INVALID, "cap %llu < %llu pairs", (unsigned long long)cap, (unsigned long long)P);
+    int tx, ty;
+    int ntiles = tiles_of(cam, &tx, &ty);
+    bool alt = sorted_in_alt(ntiles);
+    if (keys && P) HIP_TRY(hipMemcpyAsync(keys, w + (alt ? L.keys_alt : L.keys), P * 8, hipMemcpyDeviceToDevice, s));
+    if (values && P) HIP_TRY(hipMemcpyAsync(values, w + (alt ? L.vals_alt : L.vals), P * 4, hipMemcpyDeviceToDevice, s));
+    if (ranges) HIP_TRY(hipMemcpyAsync(ranges, w + L.ranges, (size_t)ntiles * 8, hipMemcpyDeviceToDevice, s));
+    return AAA_OK;
+}
+
+int aaa_sort_tmp_size(uint64_t n, size_t *bytes_out)
+{
+    if (!bytes_out) return fail(AAA_ERR_INVALID, "null bytes_out");
+    if (n >= (1ull << 32)) return fail(AAA_ERR_INVALID, "n must be < 2^32");
+    *bytes_out = align256(n * 8) + align256(n * 4) + align256(aaa::sort_tmp_bytes(n > 0 ? n : 1));
+    return AAA_OK;
+}
+
+int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits_, void *tmp, size_t tmp_bytes, void *stream)
+{
+    if (n >= (1ull << 32)) return fail(AAA_ERR_INVALID, "n must be < 2^32");
+    if (key_bits_ < 1 || key_bits_ > 64) return fail(AAA_ERR_INVALID, "key_bits %d not in 1..64", key_bits_);
+    size_t need = 0;
+    aaa_sort_tmp_size(n, &need);
+    if (n > 0 && (!keys || !values || !tmp)) return fail(AAA_ERR_INVALID, "null argument");
+    if (tmp_bytes < need) return fail(AAA_ERR_WORKSPACE, "tmp %zu < %zu bytes", tmp_bytes, need);
+    if (((uintptr_t)tmp & 255) != 0) return fail(AAA_ERR_INVALID, "tmp must be 256-byte aligned");
+    if (n <= 1) return AAA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    char *t = (char *)tmp;
+    uint64_t *ka = (uint64_t *)t;
+    uint32_t *va = (uint32_t *)(t + align256(n * 8));
+    void *st = t + align256(n * 8) + align256(n * 4);
+    bool in_alt = false;
+    HIP_TRY(aaa::radix_sort_pairs(keys, values, ka, va, n, 0, key_bits_, st, s, &in_alt));
+    if (in_alt) {
+        HIP_TRY(hipMemcpyAsync(keys, ka, n * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(values, va, n * 4, hipMemcpyDeviceToDevice, s));
+    }
+    return AAA_OK;
+}
+
+int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
+                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *dL_drgb,
+                        aaa_scene_grad *grad)
+{
+    (void)ctx; (void)scene; (void)cam; (void)settings; (void)ws; (void)ws_bytes; (void)max_pairs; (void)stream;
+    (void)dL_drgb; (void)grad;
+    return fail(AAA_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+}  // extern "C"

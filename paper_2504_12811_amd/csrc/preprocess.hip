@@ -1,0 +1,306 @@
+// K1: per-Gaussian preprocessing, one thread per Gaussian.
+//
+// Reads the structure-of-arrays scene (coalesced) and writes, per Gaussian,
+// a status word, a tile rectangle, a 128-byte blend record and a 128-byte
+// culling record.  Geometry is computed in double precision (the pass is
+// bound by HBM traffic, and double precision keeps the bounds quadratic and
+// the anchored record free of cancellation); the records are stored as float.
+#include "aaa_internal.h"
+
+namespace aaa {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kBoundEps = 1e-3;  // clamp margin of the angular bounds (rad)
+
+__device__ __forceinline__ void cross3d(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Real spherical harmonics up to degree 3 (Condon-Shortley phase), index l*l+l+m.
+__device__ __forceinline__ void sh_eval(int deg, double x, double y, double z, double *Y)
+{
+    Y[0] = 0.28209479177387814;
+    if (deg < 1) return;
+    Y[1] = -0.48860251190291992 * y;
+    Y[2] = 0.48860251190291992 * z;
+    Y[3] = -0.48860251190291992 * x;
+    if (deg < 2) return;
+    double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792 * x * y;
+    Y[5] = -1.0925484305920792 * y * z;
+    Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
+    Y[7] = -1.0925484305920792 * x * z;
+    Y[8] = 0.54627421529603959 * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -0.59004358992664352 * y * (3.0 * xx - yy);
+    Y[10] = 2.8906114426405538 * x * y * z;
+    Y[11] = -0.45704579946446572 * y * (4.0 * zz - xx - yy);
+    Y[12] = 0.3731763325901154 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -0.45704579946446572 * x * (4.0 * zz - xx - yy);
+    Y[14] = 1.4453057213202769 * z * (xx - yy);
+    Y[15] = -0.59004358992664352 * x * (xx - 3.0 * yy);
+}
+
+// Angular bounds of the level-tau ellipsoid seen from the camera in one view
+// plane (Sec. 3.3, Eq. 14-17).  Rows a (lateral: view x or y) and c (depth)
+// of M = R_V R S~ and the matching mean coordinates.  Returns false when the
+// visible wedge is empty; sets full = true when the lateral axis line meets
+// the ellipsoid (negative discriminant: the whole screen range).
+__device__ bool view_bounds(const double *Ma, const double *Mc, double ma, double mc, double tau, double &lo,
+                            double &hi, bool &full)
+{
+    full = false;
+    // s_ij = tau (M_i . M_j) - mu_i mu_j; discriminant s_ac^2 - s_aa s_cc,
+    // expanded so that the mu^4 terms cancel exactly:
+    //   D = tau |mc Ma - ma Mc|^2 - tau^2 |Ma x Mc|^2
+    double e[3], x[3];
+    for (int k = 0; k < 3; ++k) e[k] = mc * Ma[k] - ma * Mc[k];
+    cross3d(Ma, Mc, x);
+    double D = tau * dot3(e, e) - tau * tau * dot3(x, x);
+    if (D < 0.0) {
+        full = true;
+        return true;
+    }
+    double sac = tau * dot3(Ma, Mc) - ma * mc;
+    double scc = tau * dot3(Mc, Mc) - mc * mc;
+    double sq = sqrt(D);
+    double ra = atan2(sac + sq, scc);
+    double rb = atan2(sac - sq, scc);
+    double tm = atan2(ma, mc);
+    // representative of a root (mod pi) in [tm - pi, tm)
+    auto below = [&](double r) {
+        double t = r - tm;
+        t -= kPi * floor(t / kPi);
+        return tm - kPi + t;
+    };
+    double a1 = below(ra), a2 = below(rb) + kPi;
+    double b1 = below(rb), b2 = below(ra) + kPi;
+    double t1, t2;
+    if (a2 - a1 <= b2 - b1) { t1 = a1; t2 = a2; } else { t1 = b1; t2 = b2; }
+    // bring the wedge to the representation that can meet (-pi/2, pi/2)
+    if (t1 > 0.5 * kPi) { t1 -= 2.0 * kPi; t2 -= 2.0 * kPi; }
+    if (t2 < -0.5 * kPi) { t1 += 2.0 * kPi; t2 += 2.0 * kPi; }
+    t1 = fmax(t1, -0.5 * kPi + kBoundEps);
+    t2 = fmin(t2, 0.5 * kPi - kBoundEps);
+    if (!(t1 < t2)) return false;
+    lo = t1;
+    hi = t2;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    a.rect[i] = make_int4(0, 0, 0, 0);
+    double mu[3], ls[3], q[4];
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) {
+        mu[k] = a.means[k * n + i];
+        ls[k] = a.log_scales[k * n + i];
+        ok = ok && isfinite(mu[k]) && isfinite(ls[k]);
+    }
+    for (int k = 0; k < 4; ++k) {
+        q[k] = a.quats[k * n + i];
+        ok = ok && isfinite(q[k]);
+    }
+    double logit = a.logits[i];
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    ok = ok && isfinite(logit) && qn > 0.0;
+    if (!ok) {
+        a.status[i] = kInvalid;
+        return;
+    }
+    // Eq. 1-3: activations and rotation
+    double s[3];
+    for (int k = 0; k < 3; ++k) s[k] = exp(ls[k]);
+    double alpha = 1.0 / (1.0 + exp(-logit));
+    double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                   2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                   2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    double muv[3];
+    for (int r = 0; r < 3; ++r) muv[r] = a.RV[3 * r] * mu[0] + a.RV[3 * r + 1] * mu[1] + a.RV[3 * r + 2] * mu[2] + a.tV[r];
+    // Sec. 3.2: filter variance k / v'^2, v = fx / max(z, znear), v' = min(v_train, v)
+    double dz = fmax(muv[2], a.cam.znear);
+    double v = a.cam.fx / dz;
+    if (a.v_train) v = fmin(v, (double)a.v_train[i]);
+    double fa = a.filter_mode == 1 ? 0.0 : a.filter_k / (v * v);
+    double s2[3], sh_[3], st[3];
+    for (int k = 0; k < 3; ++k) {
+        s2[k] = s[k] * s[k];
+        sh_[k] = s2[k] + fa;
+        st[k] = sqrt(sh_[k]);
+    }
+    double d[3] = {mu[0] - a.o[0], mu[1] - a.o[1], mu[2] - a.o[2]};
+    double dn = sqrt(dot3(d, d));
+    for (int k = 0; k < 3; ++k) d[k] /= dn;
+    double alpha_t;
+    if (a.filter_mode == 1) {
+        alpha_t = alpha;
+    } else if (a.filter_mode == 2) {
+        alpha_t = alpha * sqrt((s2[0] * s2[1] * s2[2]) / (sh_[0] * sh_[1] * sh_[2]));  // Eq. 8
+    } else {
+        double dp[3];  // d' = R^T d
+        for (int k = 0; k < 3; ++k) dp[k] = R[k] * d[0] + R[3 + k] * d[1] + R[6 + k] * d[2];
+        double p0 = dp[0] * dp[0], p1 = dp[1] * dp[1], p2 = dp[2] * dp[2];
+        double num = p0 * s2[1] * s2[2] + p1 * s2[0] * s2[2] + p2 * s2[0] * s2[1];
+        double den = p0 * sh_[1] * sh_[2] + p1 * sh_[0] * sh_[2] + p2 * sh_[0] * sh_[1];
+        alpha_t = alpha * sqrt(num / den);  // Eq. 12
+    }
+    if (!(alpha_t >= a.alpha_min)) {
+        a.status[i] = kLowOpacity;
+        return;
+    }
+    const double tau = 2.0 * log(alpha_t / a.alpha_min);
+    // M = R_V R S~ (normalised Gaussian space -> view); A = M^-1 = S~^-1 R^T R_V^T
+    double M[9], A[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = a.RV[3 * r] * R[c] + a.RV[3 * r + 1] * R[3 + c] + a.RV[3 * r + 2] * R[6 + c];
+            M[3 * r + c] = acc * st[c];
+            A[3 * c + r] = acc / st[c];
+        }
+    double og[3];  // camera centre (view origin) in normalised space: -A mu_v
+    for (int r = 0; r < 3; ++r) og[r] = -(A[3 * r] * muv[0] + A[3 * r + 1] * muv[1] + A[3 * r + 2] * muv[2]);
+    const double og2 = dot3(og, og);
+    if (og2 < tau) {  // Sec. 3.3: camera inside the ellipsoid
+        a.status[i] = kCamInside;
+        return;
+    }
+    // Sec. 3.3 bounds in the x-z and y-z view planes
+    const CamDev &cam = a.cam;
+    double tx_lo, tx_hi, ty_lo, ty_hi;
+    bool fullx, fully;
+    bool okx = view_bounds(&M[0], &M[6], muv[0], muv[2], tau, tx_lo, tx_hi, fullx);
+    bool oky = view_bounds(&M[3], &M[6], muv[1], muv[2], tau, ty_lo, ty_hi, fully);
+    if (!okx || !oky) {
+        a.status[i] = kOutside;
+        return;
+    }
+    int x0 = 0, x1 = cam.tiles_x, y0 = 0, y1 = cam.tiles_y;
+    if (!fullx) {
+        double px_lo = cam.cx + cam.fx * tan(tx_lo) - 1e-3, px_hi = cam.cx + cam.fx * tan(tx_hi) + 1e-3;
+        x0 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_lo / kTile)));
+        x1 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_hi / kTile) + 1.0));
+    }
+    if (!fully) {
+        double py_lo = cam.cy + cam.fy * tan(ty_lo) - 1e-3, py_hi = cam.cy + cam.fy * tan(ty_hi) + 1e-3;
+        y0 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_lo / kTile)));
+        y1 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_hi / kTile) + 1.0));
+    }
+    if (x0 >= x1 || y0 >= y1) {
+        a.status[i] = kOutside;
+        return;
+    }
+    // anchor: the pixel centre nearest the projected mean, kept inside the
+    // rectangle's pixels (rectangle centre when the mean is not in front)
+    int pxl = x0 * kTile, pxh = min(x1 * kTile, cam.width) - 1;
+    int pyl = y0 * kTile, pyh = min(y1 * kTile, cam.height) - 1;
+    double xa, ya;
+    if (muv[2] > 0.0) {
+        double xm = cam.cx + cam.fx * muv[0] / muv[2];
+        double ym = cam.cy + cam.fy * muv[1] / muv[2];
+        xa = fmin(fmax(floor(xm), (double)pxl), (double)pxh) + 0.5;
+        ya = fmin(fmax(floor(ym), (double)pyl), (double)pyh) + 0.5;
+    } else {
+        xa = floor(0.5 * (pxl + pxh)) + 0.5;
+        ya = floor(0.5 * (pyl + pyh)) + 0.5;
+    }
+    // anchored line coefficients (Eq. 4-5 written as o_g x r_g and -o_g . r_g)
+    double ua = (xa - cam.cx) / cam.fx, va = (ya - cam.cy) / cam.fy;
+    TileGeom<double> g;
+    g.xa = xa;
+    g.ya = ya;
+    for (int r = 0; r < 3; ++r) {
+        g.c0[r] = A[3 * r] * ua + A[3 * r + 1] * va + A[3 * r + 2];
+        g.c1[r] = A[3 * r] / cam.fx;
+        g.c2[r] = A[3 * r + 1] / cam.fy;
+    }
+    // scale so that |c0| = 1 (rho^2 and depth are invariant)
+    double lam = 1.0 / sqrt(dot3(g.c0, g.c0));
+    for (int r = 0; r < 3; ++r) { g.c0[r] *= lam; g.c1[r] *= lam; g.c2[r] *= lam; }
+    cross3d(og, g.c0, g.w0);
+    cross3d(og, g.c1, g.w1);
+    cross3d(og, g.c2, g.w2);
+    // c carries one factor lambda already; l needs lambda^2
+    g.l[0] = -lam * dot3(og, g.c0);
+    g.l[1] = -lam * dot3(og, g.c1);
+    g.l[2] = -lam * dot3(og, g.c2);
+    g.og2 = og2;
+    // culling geometry of the screen planes relative to the anchor
+    double G[9];  // Sigma~ in view space = M M^T
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) G[3 * r + c] = dot3(&M[3 * r], &M[3 * c]);
+    g.dx0 = muv[0] - ua * muv[2];
+    g.dx1 = muv[2] / cam.fx;
+    g.dy0 = muv[1] - va * muv[2];
+    g.dy1 = muv[2] / cam.fy;
+    for (int k = 0; k < 3; ++k) {
+        g.nx0[k] = M[k] - ua * M[6 + k];
+        g.nx1[k] = M[6 + k] / cam.fx;
+        g.ny0[k] = M[3 + k] - va * M[6 + k];
+        g.ny1[k] = M[6 + k] / cam.fy;
+        g.qx0[k] = G[3 * k] - ua * G[3 * k + 2];
+        g.qx1[k] = G[3 * k + 2] / cam.fx;
+        g.qy0[k] = G[3 * k + 1] - va * G[3 * k + 2];
+        g.qy1[k] = G[3 * k + 2] / cam.fy;
+        g.muv[k] = muv[k];
+    }
+    // Sec. 3.4: cull against the whole view frustum
+    double mview = tile_min_rho2<double>(g, 0.0, (double)cam.width, 0.0, (double)cam.height, cam);
+    if (!(mview < tau)) {
+        a.status[i] = kOutside;
+        return;
+    }
+    // colour from real SH along the camera->mean direction
+    double Y[16];
+    sh_eval(a.sh_degree, d[0], d[1], d[2], Y);
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    float col[3];
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.5;
+        for (int b = 0; b < nb; ++b) acc += Y[b] * (double)a.sh[((int64_t)b * 3 + ch) * n + i];
+        col[ch] = (float)fmax(acc, 0.0);
+    }
+    float4 *rec = a.rec + (size_t)i * kRecQuads;
+    rec[0] = make_float4(g.c0[0], g.c0[1], g.c0[2], g.c1[0]);
+    rec[1] = make_float4(g.c1[1], g.c1[2], g.c2[0], g.c2[1]);
+    rec[2] = make_float4(g.c2[2], g.w0[0], g.w0[1], g.w0[2]);
+    rec[3] = make_float4(g.w1[0], g.w1[1], g.w1[2], g.w2[0]);
+    rec[4] = make_float4(g.w2[1], g.w2[2], g.l[0], g.l[1]);
+    rec[5] = make_float4(g.l[2], xa, ya, alpha_t);
+    // prefilter level slightly above tau so that it never rejects an
+    // evaluation the exact alpha test would accept
+    rec[6] = make_float4((float)(tau * (1.0 + 1e-4) + 1e-6), (float)tau, (float)og2, 0.f);
+    rec[7] = make_float4(col[0], col[1], col[2], 0.f);
+    float4 *cu = a.cull + (size_t)i * kCullQuads;
+    cu[0] = make_float4(g.dx0, g.dx1, g.dy0, g.dy1);
+    cu[1] = make_float4(g.nx0[0], g.nx0[1], g.nx0[2], g.nx1[0]);
+    cu[2] = make_float4(g.nx1[1], g.nx1[2], g.ny0[0], g.ny0[1]);
+    cu[3] = make_float4(g.ny0[2], g.ny1[0], g.ny1[1], g.ny1[2]);
+    cu[4] = make_float4(g.qx0[0], g.qx0[1], g.qx0[2], g.qx1[0]);
+    cu[5] = make_float4(g.qx1[1], g.qx1[2], g.qy0[0], g.qy0[1]);
+    cu[6] = make_float4(g.qy0[2], g.qy1[0], g.qy1[1], g.qy1[2]);
+    cu[7] = make_float4(muv[0], muv[1], muv[2], 0.f);
+    a.rect[i] = make_int4(x0, x1, y0, y1);
+    a.status[i] = kVisible;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const PreArgs &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    int64_t blocks = (a.n + 255) / 256;
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace aaa

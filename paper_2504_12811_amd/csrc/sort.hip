@@ -1,0 +1,178 @@
+// K3: stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit
+// digits, and K4: tile ranges of the sorted keys.
+//
+// Each pass: (1) per-block digit histograms, (2) an exclusive scan over the
+// digit-major [digit][block] table, (3) a stable scatter.  A block owns 4096
+// consecutive keys; each of its four wavefronts ranks a contiguous quarter in
+// rounds of 64 with a ballot-based match on the digit bits (lanes with equal
+// digits see each other through eight ballots), so the rank of a key is the
+// number of equal digits before it in its wave's segment.  Wave segments are
+// then offset by the counts of the earlier waves and by the global prefix of
+// the block.
+#include "aaa_internal.h"
+
+namespace aaa {
+
+namespace {
+
+constexpr int kBits = 8;
+constexpr int kBins = 1 << kBits;
+constexpr int kThreads = 256;
+constexpr int kItems = 16;
+constexpr int kPerBlock = kThreads * kItems;   // 4096
+constexpr int kPerWave = kPerBlock / 4;        // 1024
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    unsigned lane = __lane_id();
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift,
+                                                   uint32_t *__restrict__ hist, uint32_t nblocks)
+{
+    __shared__ uint32_t h[4][kBins];
+    const int t = threadIdx.x, wave = t >> 6;
+    for (int k = t; k < 4 * kBins; k += kThreads) (&h[0][0])[k] = 0;
+    __syncthreads();
+    const uint64_t b0 = (uint64_t)blockIdx.x * kPerBlock;
+#pragma unroll 4
+    for (int k = 0; k < kItems; ++k) {
+        uint64_t idx = b0 + (uint64_t)k * kThreads + t;
+        if (idx < n) {
+            uint32_t d = (uint32_t)(keys[idx] >> shift) & (kBins - 1);
+            atomicAdd(&h[wave][d], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t s = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+    hist[(uint64_t)t * nblocks + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ keys_in,
+                                                      const uint32_t *__restrict__ vals_in, uint64_t n, int shift,
+                                                      const uint64_t *__restrict__ offsets, uint32_t nblocks,
+                                                      uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
+{
+    __shared__ uint32_t cnt[4][kBins];
+    __shared__ uint32_t off[4][kBins];
+    const int t = threadIdx.x, wave = t >> 6;
+    for (int k = t; k < 4 * kBins; k += kThreads) (&cnt[0][0])[k] = 0;
+    __syncthreads();
+    const uint64_t seg = (uint64_t)blockIdx.x * kPerBlock + (uint64_t)wave * kPerWave;
+    const uint64_t lt = lanemask_lt();
+    uint64_t key[kItems];
+    uint32_t val[kItems], rank[kItems], dig[kItems];
+    bool valid[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        uint64_t idx = seg + (uint64_t)r * 64 + __lane_id();
+        valid[r] = idx < n;
+        key[r] = valid[r] ? keys_in[idx] : 0ull;
+        val[r] = valid[r] ? vals_in[idx] : 0u;
+        uint32_t d = (uint32_t)(key[r] >> shift) & (kBins - 1);
+        dig[r] = d;
+        uint64_t m = __ballot(valid[r]);
+#pragma unroll
+        for (int b = 0; b < kBits; ++b) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t before = (uint32_t)__popcll(m & lt);
+        uint32_t base = 0;
+        if (valid[r]) base = cnt[wave][d];
+        rank[r] = base + before;
+        __builtin_amdgcn_wave_barrier();
+        if (valid[r] && before == 0) cnt[wave][d] = base + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        uint64_t g = offsets[(uint64_t)t * nblocks + blockIdx.x];
+        uint32_t run = 0;
+        for (int w = 0; w < 4; ++w) {
+            off[w][t] = (uint32_t)(g + run);
+            run += cnt[w][t];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        if (valid[r]) {
+            uint32_t pos = off[wave][dig[r]] + rank[r];
+            keys_out[pos] = key[r];
+            vals_out[pos] = val[r];
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t *__restrict__ ranges)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t tile = (uint32_t)(keys[i] >> 32);
+    if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * (uint64_t)tile] = (uint32_t)i;
+    if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[2 * (uint64_t)tile + 1] = (uint32_t)(i + 1);
+}
+
+}  // namespace
+
+static uint32_t sort_blocks(uint64_t n) { return (uint32_t)((n + kPerBlock - 1) / kPerBlock); }
+
+size_t sort_tmp_bytes(uint64_t n)
+{
+    uint64_t nb = sort_blocks(n > 0 ? n : 1);
+    uint64_t cells = nb * kBins;
+    size_t b = cells * sizeof(uint32_t);
+    b = (b + 255) & ~(size_t)255;
+    b += (cells + 1) * sizeof(uint64_t);
+    b = (b + 255) & ~(size_t)255;
+    b += scan_tmp_bytes((int64_t)cells);
+    return b + 256;
+}
+
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
+                            int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt)
+{
+    *result_in_alt = false;
+    if (n <= 1 || end_bit <= begin_bit) return hipSuccess;
+    uint32_t nb = sort_blocks(n);
+    uint64_t cells = (uint64_t)nb * kBins;
+    char *p = (char *)tmp;
+    uint32_t *hist = (uint32_t *)p;
+    size_t o = (cells * sizeof(uint32_t) + 255) & ~(size_t)255;
+    uint64_t *offs = (uint64_t *)(p + o);
+    o += (((cells + 1) * sizeof(uint64_t)) + 255) & ~(size_t)255;
+    void *scan_tmp = p + o;
+    uint64_t *ki = keys, *ko = keys_alt;
+    uint32_t *vi = vals, *vo = vals_alt;
+    for (int shift = begin_bit; shift < end_bit; shift += kBits) {
+        hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, n, shift, hist, nb);
+        hipError_t e = launch_exclusive_scan(hist, offs, (int64_t)cells, scan_tmp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, (const uint32_t *)vi, n,
+                           shift, (const uint64_t *)offs, nb, ko, vo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t *tk = ki; ki = ko; ko = tk;
+        uint32_t *tv = vi; vi = vo; vo = tv;
+        *result_in_alt = !*result_in_alt;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s)
+{
+    uint64_t m = 2ull * (uint64_t)ntiles;
+    if (m) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, ranges, m, 0u);
+    if (n) hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, ranges);
+    return hipGetLastError();
+}
+
+}  // namespace aaa

@@ -1,0 +1,272 @@
+"""GPU forward path vs the FP64 oracle, through the C ABI.
+
+Images: max |GPU - oracle| <= 2e-4 per channel on pixels the oracle does not
+flag (a flagged pixel has a threshold decision or an ordering tie within the
+FP32 band; see oracle/aaa_oracle.c).  Per-Gaussian outputs: relative 1e-5.
+Pairs: every needed pair present, every emitted pair allowed (O13).  Sort:
+bit-exact against a stable sort of the same keys.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2504_12811_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def ras():
+    from paper_2504_12811_amd.render import Rasterizer
+    assert torch.cuda.is_available()
+    return Rasterizer(0)
+
+
+def dev(scene):
+    from paper_2504_12811_amd.render import DeviceScene
+    return DeviceScene.from_host(scene, "cuda:0")
+
+
+def compare_image(ras, scene, cam, st, tile_sel=None, label=""):
+    rgb, T, stats = ras.render(dev(scene), cam, st)
+    torch.cuda.synchronize()
+    ref = O.render(scene, cam, st, tile_sel=tile_sel)
+    g = rgb.cpu().numpy().astype(np.float64)
+    gT = T.cpu().numpy().astype(np.float64)
+    mask = ref.flags == 0
+    if tile_sel is not None:
+        tx, ty = cam.tiles
+        sel = np.asarray(tile_sel, bool).reshape(ty, tx)
+        pixsel = np.kron(sel, np.ones((16, 16), bool))[: cam.height, : cam.width]
+        mask &= pixsel
+        nsel = pixsel.sum()
+    else:
+        nsel = cam.width * cam.height
+    err = np.abs(g - ref.rgb)[:, mask]
+    errT = np.abs(gT - ref.T)[mask]
+    emax = float(err.max()) if err.size else 0.0
+    eT = float(errT.max()) if errT.size else 0.0
+    flagged = int(nsel - mask.sum())
+    fl = (ref.flags != 0)
+    if tile_sel is not None:
+        fl &= pixsel
+    ef = np.abs(g - ref.rgb).max(0)[fl]
+    print(f"[{label}] pairs={stats.pairs} pixels={nsel} flagged={flagged} ({flagged / max(nsel, 1):.2e}) "
+          f"max|drgb|={emax:.3e} max|dT|={eT:.3e} flagged: max|drgb|={ef.max() if ef.size else 0:.3e} "
+          f"over-tol={int((ef > TOL).sum())}", flush=True)
+    if emax > TOL:
+        bad = np.argwhere(np.abs(g - ref.rgb).max(0) * mask > TOL)
+        print("worst pixels (y,x):", bad[:10].tolist(), flush=True)
+    assert emax <= TOL
+    assert eT <= TOL
+    assert flagged <= max(8, 0.02 * nsel)
+    return rgb, T, stats, ref
+
+
+# --------------------------------------------------------------------------
+# stage checks
+
+
+def test_preprocess_matches_oracle(ras):
+    scene, cam = S.small_scene()
+    st = S.Settings()
+    ds = dev(scene)
+    ras.render(ds, cam, st)
+    out = {k: v.cpu().numpy() for k, v in ras.read_gaussians(ds, cam).items()}
+    ref = O.preprocess(scene, cam, st)
+    amb = ref["ambiguous"] != 0
+    np.testing.assert_array_equal(out["status"][~amb], ref["status"][~amb])
+    vis = ref["status"] == O.VISIBLE
+    print(f"visible {vis.sum()} / {scene.n}", flush=True)
+    np.testing.assert_allclose(out["alpha_t"][vis], ref["alpha_t"][vis], rtol=1e-5)
+    np.testing.assert_allclose(out["tau"][vis], ref["tau"][vis], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(out["color"][:, vis], ref["color"][:, vis], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("filter_mode", [0, 1, 2])
+def test_preprocess_filter_modes(ras, filter_mode):
+    scene, cam = S.small_scene(n=500, seed=77)
+    st = S.Settings(filter_mode=filter_mode)
+    ds = dev(scene)
+    ras.render(ds, cam, st)
+    out = {k: v.cpu().numpy() for k, v in ras.read_gaussians(ds, cam).items()}
+    ref = O.preprocess(scene, cam, st)
+    vis = (ref["status"] == O.VISIBLE) & (ref["ambiguous"] == 0)
+    np.testing.assert_array_equal(out["status"][vis], 0)
+    np.testing.assert_allclose(out["alpha_t"][vis], ref["alpha_t"][vis], rtol=1e-5)
+
+
+def pair_sets_check(ras, scene, cam, st, tiles, label=""):
+    ds = dev(scene)
+    ras.render(ds, cam, st)
+    keys, vals, ranges = ras.read_pairs(ds, cam)
+    keys = keys.cpu().numpy().view(np.uint64)
+    vals = vals.cpu().numpy().view(np.uint32)
+    ranges = ranges.cpu().numpy().view(np.uint32)
+    # sortedness: keys non-decreasing, equal keys by increasing Gaussian index
+    assert np.all(keys[1:] >= keys[:-1])
+    eq = keys[1:] == keys[:-1]
+    assert np.all(vals[1:][eq] > vals[:-1][eq])
+    pp = O.preprocess(scene, cam, st)
+    cand = np.nonzero((pp["status"] == O.VISIBLE) | (pp["ambiguous"] != 0))[0]
+    missing = extra = 0
+    for t in tiles:
+        s, e = ranges[t]
+        got = set(vals[s:e].tolist())
+        assert np.all((keys[s:e] >> np.uint64(32)) == t)
+        cls = O.classify_pairs(scene, cam, st, int(t), cand)
+        need = set(cand[cls == 2].tolist())
+        allowed = set(cand[cls >= 1].tolist())
+        missing += len(need - got)
+        extra += len(got - allowed)
+    print(f"[{label}] tiles={len(tiles)} missing={missing} not-allowed={extra}", flush=True)
+    assert missing == 0
+    assert extra == 0
+
+
+def test_pair_sets_small(ras):
+    scene, cam = S.small_scene()
+    tx, ty = cam.tiles
+    pair_sets_check(ras, scene, cam, S.Settings(), range(tx * ty), "C1 all tiles")
+
+
+def test_pair_sets_near_camera(ras):
+    """Gaussians straddling the camera plane and the image border (view-space bounding)."""
+    scene, cam = near_scene()
+    tx, ty = cam.tiles
+    pair_sets_check(ras, scene, cam, S.Settings(), range(tx * ty), "near set")
+
+
+def test_sort_bit_exact(ras):
+    from paper_2504_12811_amd.render import sort_pairs
+    rng = np.random.default_rng(5)
+    for n, bits in [(1, 40), (7, 40), (4096, 45), (4097, 45), (300_001, 45), (1 << 20, 64)]:
+        tiles = rng.integers(0, 8160, n, dtype=np.uint64)
+        depth = rng.integers(0, 1 << 32, n, dtype=np.uint64)
+        depth[: n // 3] = depth[0]  # many ties
+        keys = (tiles << np.uint64(32)) | depth
+        if bits < 64:
+            keys &= np.uint64((1 << bits) - 1)
+        vals = rng.permutation(n).astype(np.uint32)
+        kt = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+        vt = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+        sort_pairs(kt, vt, bits)
+        order = np.argsort(keys, kind="stable")
+        np.testing.assert_array_equal(kt.cpu().numpy().view(np.uint64), keys[order])
+        np.testing.assert_array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
+
+
+# --------------------------------------------------------------------------
+# images
+
+
+@pytest.mark.parametrize("K", [0, 1, 4, 16, 32])
+def test_image_small(ras, K):
+    scene, cam = S.small_scene()
+    compare_image(ras, scene, cam, S.Settings(ray_window=K), label=f"C1 K={K}")
+
+
+def test_image_small_sh3_ragged(ras):
+    """SH degree 3, ragged image (partial tiles on both axes), background colour."""
+    scene, cam = S.small_scene(n=3000, seed=42, sh_degree=3)
+    cam = S.pinhole(cam.position, 151, 87, 70.0, bg=(0.25, 0.5, 0.75))
+    compare_image(ras, scene, cam, S.Settings(), label="C1 SH3 151x87")
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_image_filter_variants(ras, mode):
+    scene, cam = S.small_scene(n=1500, seed=9)
+    compare_image(ras, scene, cam, S.Settings(filter_mode=mode), label=f"filter mode {mode}")
+
+
+def test_image_without_tile_culling_is_identical(ras):
+    scene, cam = S.small_scene()
+    rgb0, T0, s0, _ = compare_image(ras, scene, cam, S.Settings(), label="cull on")
+    rgb1, T1, s1 = ras.render(dev(scene), cam, S.Settings(tile_cull=False))
+    assert s1.pairs > s0.pairs
+    assert torch.equal(rgb0, rgb1) or float((rgb0 - rgb1).abs().max()) <= 1e-6
+
+
+def near_scene(n=3000, seed=3):
+    """Small cluster scene viewed from close range: many Gaussians straddle the
+    near plane, the camera plane and the image borders."""
+    rng = np.random.default_rng(seed)
+    cam = S.pinhole((0.0, 0.0, -0.6), 160, 120, 120.0, znear=0.01)
+    means = rng.uniform(-1.0, 1.0, size=(3, n)) * np.array([[1.2], [1.0], [1.0]])
+    means[2] = rng.uniform(-0.8, 0.8, n)
+    sc = S.Scene(means.astype(np.float32), rng.normal(-2.5, 0.5, (3, n)).astype(np.float32),
+                 rng.normal(size=(4, n)).astype(np.float32), rng.normal(0.5, 1.0, n).astype(np.float32),
+                 ((rng.uniform(0, 1, (1, 3, n)) - 0.5) / S.SH_C0).astype(np.float32))
+    return sc, cam
+
+
+def test_image_near_camera_wide_fov(ras):
+    scene, cam = near_scene()
+    compare_image(ras, scene, cam, S.Settings(), label="near 120deg")
+
+
+def test_empty_and_culled_scenes(ras):
+    scene, cam = S.small_scene(n=50)
+    cam.bg = (0.1, 0.2, 0.3)
+    empty = scene.subset(np.arange(0))
+    rgb, T, st = ras.render(dev(empty), cam, S.Settings())
+    assert st.pairs == 0
+    assert torch.all(T == 1)
+    for c in range(3):
+        assert torch.all(rgb[c] == np.float32(cam.bg[c]))
+    behind = scene.subset(np.arange(50))
+    fwd = cam.viewmat[2, :3]
+    behind.means[:] = (cam.position - 5.0 * fwd)[:, None]  # all behind the camera
+    rgb, T, st = ras.render(dev(behind), cam, S.Settings())
+    assert st.pairs == 0 and torch.all(T == 1)
+
+
+def test_nan_gaussians_are_culled(ras):
+    scene, cam = S.small_scene(n=400)
+    bad = scene.subset(np.arange(400))
+    bad.means[0, :50] = np.nan
+    bad.quats[:, 50:60] = 0.0
+    bad.log_scales[1, 60:70] = np.inf
+    good = scene.subset(np.arange(70, 400))
+    rgb_b, T_b, _ = ras.render(dev(bad), cam, S.Settings())
+    rgb_g, T_g, _ = ras.render(dev(good), cam, S.Settings())
+    assert torch.isfinite(rgb_b).all()
+    # same image up to the order ties of Gaussians with shifted indices
+    assert float((rgb_b - rgb_g).abs().max()) <= 1e-5
+
+
+def test_tiny_images(ras):
+    scene, cam = S.small_scene(n=800)
+    for (w, h) in [(1, 1), (17, 3), (16, 16), (33, 1)]:
+        c = S.pinhole(cam.position, w, h, 60.0)
+        compare_image(ras, scene, c, S.Settings(), label=f"{w}x{h}")
+
+
+def test_determinism(ras):
+    scene, cam = S.small_scene(n=5000, seed=8)
+    ds = dev(scene)
+    a = ras.render(ds, cam, S.Settings())[0].clone()
+    b = ras.render(ds, cam, S.Settings())[0]
+    assert torch.equal(a, b)
+
+
+def test_medium_cluster_scene_ragged(ras):
+    """Cluster generator at 30k Gaussians, 250x170 (ragged tiles), SH3."""
+    scene, poses = S.cluster_scene(30_000, seed=1002, n_rig=8)
+    cam = S.pinhole(poses[0], 250, 170, 60.0)
+    compare_image(ras, scene, cam, S.Settings(), label="30k 250x170")
+
+
+def test_headline_sampled_tiles(ras):
+    """1M Gaussians at 1920x1080 (the benchmark configuration): oracle on a
+    sample of 24 tiles."""
+    scene, cams = S.headline()
+    cam = cams[0]
+    tx, ty = cam.tiles
+    rng = np.random.default_rng(0)
+    sel = np.zeros(tx * ty, np.uint8)
+    sel[rng.choice(tx * ty, 24, replace=False)] = 1
+    compare_image(ras, scene, cam, S.Settings(), tile_sel=sel, label="1M 1080p sampled")
