@@ -94,6 +94,7 @@ typedef struct {
 #define AAA_FILTER_VOLUME 2u   /* volume-normalised amplitude (Eq. 7-8) instead of Eq. 12 */
 #define AAA_NO_TILE_CULL 4u    /* keep every tile of the bounding rectangle (no Eq. 18 per tile) */
 #define AAA_STATS 8u           /* count evaluations / contributors (small overhead) */
+#define AAA_TIMING 16u         /* time each stage with HIP events on `stream` (see aaa_stage_times) */
 
 /* Method settings.  filter_k: filter size k (0.3 in Sec. 4).  ray_window:
  * capacity K of the per-ray re-sort window (0 = blend in tile order; the
@@ -116,8 +117,14 @@ typedef struct {
     uint64_t evaluations;    /* pixel x list-entry evaluations (AAA_STATS) */
     uint64_t contributors;   /* evaluations that passed the contribution test (AAA_STATS) */
     uint64_t candidate_tiles;/* tile tests executed by the pair emitter (AAA_STATS) */
-    float ms_stage[8];       /* reserved */
+    uint64_t near;           /* evaluations that passed the rho^2 prefilter (AAA_STATS) */
 } aaa_stats;
+
+/* Stages timed under AAA_TIMING, in launch order. */
+enum {
+    AAA_STAGE_PREPROCESS = 0, AAA_STAGE_COUNT = 1, AAA_STAGE_SCAN = 2, AAA_STAGE_WRITE = 3, AAA_STAGE_SORT = 4,
+    AAA_STAGE_RANGES = 5, AAA_STAGE_BLEND = 6, AAA_STAGE_FRAME = 7, AAA_NUM_STAGES = 8
+};
 
 typedef struct aaa_ctx aaa_ctx;
 
@@ -153,6 +160,13 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
 int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
                         void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *dL_drgb,
                         aaa_scene_grad *grad);
+
+/* Accumulated stage times (milliseconds, HIP events on the render stream) of
+ * every aaa_render with AAA_TIMING since the last reset, and the number of
+ * such frames.  Waits for the last timed frame to finish.  ms [AAA_NUM_STAGES]
+ * (host); the last entry is the whole frame (first to last kernel).  reset != 0
+ * clears the totals after reading. */
+int aaa_stage_times(aaa_ctx *ctx, double *ms, uint64_t *frames, int reset);
 
 /* ---- stage outputs of the last aaa_render into `ws` (for checks) ------ */
 

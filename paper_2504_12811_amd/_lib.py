@@ -13,11 +13,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libaaa_hip.so")
 
 AAA_OK, AAA_ERR_INVALID, AAA_ERR_WORKSPACE, AAA_ERR_PAIR_OVERFLOW, AAA_ERR_HIP, AAA_ERR_UNSUPPORTED = range(6)
-AAA_FILTER_OFF, AAA_FILTER_VOLUME, AAA_NO_TILE_CULL, AAA_STATS = 1, 2, 4, 8
+AAA_FILTER_OFF, AAA_FILTER_VOLUME, AAA_NO_TILE_CULL, AAA_STATS, AAA_TIMING = 1, 2, 4, 8, 16
+STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "frame"]
 
 # Every symbol include/aaa.h declares (checked by the ABI test).
 EXPORTS = [
     "aaa_create", "aaa_destroy", "aaa_last_error", "aaa_version", "aaa_workspace_size", "aaa_render",
+    "aaa_stage_times",
     "aaa_render_backward", "aaa_read_gaussians", "aaa_read_pairs", "aaa_sort_tmp_size", "aaa_sort_pairs",
 ]
 
@@ -52,7 +54,7 @@ class Settings(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("pairs", C.c_uint64), ("visible", C.c_uint64), ("evaluations", C.c_uint64),
-                ("contributors", C.c_uint64), ("candidate_tiles", C.c_uint64), ("ms_stage", C.c_float * 8)]
+                ("contributors", C.c_uint64), ("candidate_tiles", C.c_uint64), ("near", C.c_uint64)]
 
 
 _lib = None
@@ -82,6 +84,7 @@ def lib():
                                          vp]
         L.aaa_read_pairs.argtypes = [C.POINTER(Scene), C.POINTER(Camera), u64, vp, C.c_size_t, vp, vp, vp, vp, u64,
                                      C.POINTER(C.c_uint64)]
+        L.aaa_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_int]
         L.aaa_sort_tmp_size.argtypes = [u64, C.POINTER(C.c_size_t)]
         L.aaa_sort_pairs.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
         for f in EXPORTS:

@@ -211,7 +211,7 @@ struct BlendArgs {
     float bg[3];
     float *out_rgb, *out_T;
     uint32_t *n_done;  // per pixel: list entries consumed
-    unsigned long long *counters;  // [0] evaluations, [1] contributors
+    unsigned long long *counters;  // [0] evaluations, [1] contributors, [2] prefilter passes
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, hipStream_t s);
 }  // namespace aaa

@@ -132,7 +132,36 @@ T *at(void *ws, size_t off) { return (T *)((char *)ws + off); }
 
 struct aaa_ctx {
     int device;
+    // AAA_TIMING: two sets of stage events (frame i uses set i % 2); a set is
+    // folded into the totals once a later frame has synchronised past it.
+    static constexpr int kEvents = 9;
+    hipEvent_t ev[2][kEvents];
+    bool pending[2];
+    int cur;
+    double total_ms[AAA_NUM_STAGES];
+    uint64_t frames;
 };
+
+namespace {
+
+void fold_events(aaa_ctx *c, int set)
+{
+    if (!c->pending[set]) return;
+    float ms[aaa_ctx::kEvents - 1];
+    hipEvent_t *e = c->ev[set];
+    // e0 start | preprocess | e1 | count | e2 | scan | e3 .. host wait .. e4 | write | e5 | sort | e6 | ranges | e7 | blend | e8
+    const int a[AAA_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 0};
+    const int b[AAA_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 8};
+    for (int k = 0; k < AAA_NUM_STAGES; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, e[a[k]], e[b[k]]) == hipSuccess) c->total_ms[k] += t;
+    }
+    (void)ms;
+    c->frames++;
+    c->pending[set] = false;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -149,11 +178,48 @@ int aaa_create(aaa_ctx **out, int device)
     HIP_TRY(hipSetDevice(device));
     aaa_ctx *c = new aaa_ctx;
     c->device = device;
+    for (int s_ = 0; s_ < 2; ++s_) {
+        c->pending[s_] = false;
+        for (int k = 0; k < aaa_ctx::kEvents; ++k) {
+            hipError_t e = hipEventCreate(&c->ev[s_][k]);
+            if (e != hipSuccess) {
+                delete c;
+                return fail(AAA_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    c->cur = 0;
+    c->frames = 0;
+    for (int k = 0; k < AAA_NUM_STAGES; ++k) c->total_ms[k] = 0.0;
     *out = c;
     return AAA_OK;
 }
 
-void aaa_destroy(aaa_ctx *ctx) { delete ctx; }
+void aaa_destroy(aaa_ctx *ctx)
+{
+    if (!ctx) return;
+    for (int s_ = 0; s_ < 2; ++s_)
+        for (int k = 0; k < aaa_ctx::kEvents; ++k) (void)hipEventDestroy(ctx->ev[s_][k]);
+    delete ctx;
+}
+
+int aaa_stage_times(aaa_ctx *ctx, double *ms, uint64_t *frames, int reset)
+{
+    if (!ctx || !ms || !frames) return fail(AAA_ERR_INVALID, "null argument");
+    HIP_TRY(hipSetDevice(ctx->device));
+    for (int k = 0; k < 2; ++k) {
+        int set = (ctx->cur + k) % 2;  // oldest first
+        if (ctx->pending[set]) HIP_TRY(hipEventSynchronize(ctx->ev[set][aaa_ctx::kEvents - 1]));
+        fold_events(ctx, set);
+    }
+    for (int k = 0; k < AAA_NUM_STAGES; ++k) ms[k] = ctx->total_ms[k];
+    *frames = ctx->frames;
+    if (reset) {
+        for (int k = 0; k < AAA_NUM_STAGES; ++k) ctx->total_ms[k] = 0.0;
+        ctx->frames = 0;
+    }
+    return AAA_OK;
+}
 
 int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, uint64_t max_pairs,
                        size_t *bytes_out)
@@ -184,7 +250,17 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     const int ntiles = tiles_of(cam, &tx, &ty);
     aaa::CamDev cd = cam_dev(cam);
     const bool want_stats = (settings->flags & AAA_STATS) != 0;
-    unsigned long long *ctr = at<unsigned long long>(ws, L.hdr);  // [0] visible [1] tests [2] evals [3] contribs
+    unsigned long long *ctr = at<unsigned long long>(ws, L.hdr);  // [0] visible [1] tests [2] evals [3] contribs [4] near
+    const bool timing = (settings->flags & AAA_TIMING) != 0;
+    hipEvent_t *ev = ctx->ev[ctx->cur];
+    if (timing) {
+        // the set was last used two frames ago; the previous frame's host
+        // wait already ordered it, so its events are complete
+        fold_events(ctx, ctx->cur);
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
+#define STAGE_MARK(k) \
+    do { if (timing) HIP_TRY(hipEventRecord(ev[k], s)); } while (0)
     HIP_TRY(hipMemsetAsync(ctr, 0, 64, s));
 
     aaa::PreArgs pa;
@@ -211,12 +287,15 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     pa.rec = at<float4>(ws, L.rec);
     pa.cull = at<float4>(ws, L.cull);
     HIP_TRY(aaa::launch_preprocess(pa, s));
+    STAGE_MARK(1);
 
     const bool tile_cull = (settings->flags & AAA_NO_TILE_CULL) == 0;
     uint32_t *counts = at<uint32_t>(ws, L.counts);
     uint64_t *offsets = at<uint64_t>(ws, L.offsets);
     HIP_TRY(aaa::launch_count_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, cd, tile_cull, counts, ctr, s));
+    STAGE_MARK(2);
     HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, n, at<void>(ws, L.scan_tmp), s));
+    STAGE_MARK(3);
     uint64_t P = 0;
     HIP_TRY(hipMemcpyAsync(&P, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -228,8 +307,10 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
                                    (unsigned long long)max_pairs);
     uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
     uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
+    STAGE_MARK(4);
     HIP_TRY(aaa::launch_write_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, cd, tile_cull, offsets, max_pairs, keys,
                                     vals, s));
+    STAGE_MARK(5);
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,
                                   &in_alt));
@@ -243,8 +324,10 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
         skeys = keys_alt;
         svals = vals_alt;
     }
+    STAGE_MARK(6);
     uint32_t *ranges = at<uint32_t>(ws, L.ranges);
     HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, ntiles, s));
+    STAGE_MARK(7);
 
     aaa::BlendArgs ba;
     ba.rec = pa.rec;
@@ -262,14 +345,21 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     ba.n_done = at<uint32_t>(ws, L.n_done);
     ba.counters = ctr + 2;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, s));
+    if (timing) {
+        STAGE_MARK(8);
+        ctx->pending[ctx->cur] = true;
+        ctx->cur ^= 1;
+    }
+#undef STAGE_MARK
     if (stats && want_stats) {
-        unsigned long long h[4];
+        unsigned long long h[5];
         HIP_TRY(hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         stats->visible = h[0];
         stats->candidate_tiles = h[1];
         stats->evaluations = h[2];
         stats->contributors = h[3];
+        stats->near = h[4];
     }
     return AAA_OK;
 }

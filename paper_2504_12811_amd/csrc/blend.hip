@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     ps.C[0] = ps.C[1] = ps.C[2] = 0.0f;
     ps.done = !inside;
     uint32_t consumed = 0;
-    uint32_t n_eval = 0, n_contrib = 0;
+    uint32_t n_eval = 0, n_contrib = 0, n_near = 0;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = a.znear;
 
     for (uint32_t i = start; i < end; ++i) {
@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
         // wave-uniform branches from here on: the window registers are only
         // ever updated with all lanes active (no divergent copies)
         if (__ballot(near) == 0ull) continue;
+        if (STATS && near) ++n_near;
         const float inv = __builtin_amdgcn_rcpf(D);
         const float rho2 = N * inv;
         const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-rho2 * kLog2eHalf));
@@ -141,14 +142,16 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
         a.n_done[pix] = consumed;
     }
     if (STATS) {
-        unsigned long long e = n_eval, c = n_contrib;
+        unsigned long long e = n_eval, c = n_contrib, nr = n_near;
         for (int off = 32; off > 0; off >>= 1) {
             e += __shfl_down(e, off);
             c += __shfl_down(c, off);
+            nr += __shfl_down(nr, off);
         }
         if (lane == 0) {
             atomicAdd(&a.counters[0], e);
             atomicAdd(&a.counters[1], c);
+            atomicAdd(&a.counters[2], nr);
         }
     }
 }

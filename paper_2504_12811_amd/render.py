@@ -98,11 +98,12 @@ class Rasterizer:
         return self._ws.data_ptr(), self._ws_bytes, self.max_pairs
 
     # forward ------------------------------------------------------------
-    def render(self, scene: DeviceScene, cam, settings, stats: bool = False, max_pairs: Optional[int] = None):
+    def render(self, scene: DeviceScene, cam, settings, stats: bool = False, timing: bool = False,
+               max_pairs: Optional[int] = None):
         """Render one view; returns (rgb [3,H,W], T [H,W], Stats)."""
         sc = scene.abi()
         c = L.make_camera(cam)
-        st = L.make_settings(settings, L.AAA_STATS if stats else 0)
+        st = L.make_settings(settings, (L.AAA_STATS if stats else 0) | (L.AAA_TIMING if timing else 0))
         H, W = int(cam.height), int(cam.width)
         rgb = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
         T = torch.empty((H, W), dtype=torch.float32, device=self.device)
@@ -120,6 +121,13 @@ class Rasterizer:
             self.last_pairs = int(out.pairs)
             return rgb, T, out
         raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
+
+    def stage_times(self, reset: bool = True):
+        """(dict stage -> accumulated ms, frames) of the renders made with timing=True."""
+        ms = (C.c_double * len(L.STAGES))()
+        frames = C.c_uint64()
+        L.check(L.lib().aaa_stage_times(self._ctx, ms, C.byref(frames), int(reset)))
+        return {k: ms[i] for i, k in enumerate(L.STAGES)}, int(frames.value)
 
     def read_gaussians(self, scene: DeviceScene, cam):
         n = scene.n
