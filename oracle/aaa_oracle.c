@@ -42,12 +42,14 @@ typedef struct {
     int64_t n;
     int32_t sh_degree;
     int32_t _pad;
-    const float *means;          /* [3][n] */
-    const float *log_scales;     /* [3][n] */
-    const float *quats;          /* [4][n] (w,x,y,z) */
-    const float *opacity_logits; /* [n] */
-    const float *sh;             /* [(deg+1)^2][3][n] */
-    const float *v_train;        /* [n] or NULL */
+    /* double precision so that finite differences can perturb inputs;
+     * float32 scenes convert exactly */
+    const double *means;          /* [3][n] */
+    const double *log_scales;     /* [3][n] */
+    const double *quats;          /* [4][n] (w,x,y,z) */
+    const double *opacity_logits; /* [n] */
+    const double *sh;             /* [(deg+1)^2][3][n] */
+    const double *v_train;        /* [n] or NULL */
 } or_scene;
 
 typedef struct {
@@ -276,7 +278,7 @@ void or_prepare(const or_scene *sc, const or_camera *cam, const or_settings *st,
         or_sh_basis(sc->sh_degree, d, Y);
         for (int ch = 0; ch < 3; ++ch) {
             double acc = 0.5;
-            for (int b = 0; b < nb; ++b) acc += Y[b] * (double)sc->sh[((int64_t)b * 3 + ch) * n + i];
+            for (int b = 0; b < nb; ++b) acc += Y[b] * sc->sh[((int64_t)b * 3 + ch) * n + i];
             g->color[ch] = acc > 0 ? acc : 0;
         }
     }
@@ -445,6 +447,8 @@ typedef struct {
     double z, a;
     const double *c;
     double tat; /* transmittance just before this entry was blended; -1 if never blended */
+    double r2;  /* rho^2 on the pixel line */
+    int clamped;/* alpha hit alpha_max */
 } or_contrib;
 
 static int cmp_tile_order(const void *pa, const void *pb)
@@ -572,8 +576,60 @@ typedef struct {
  * out_ncontrib [H][W] (may be NULL).  tile_sel [tiles] selects the tiles to
  * render (NULL = all); unselected pixels are left untouched.
  */
-int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
-              double *out_rgb, double *out_T, uint8_t *out_flags, int32_t *out_ncontrib, or_stats *stats)
+/* Reverse pass of one pixel (plain reverse-mode recursion over the blended
+ * entries, in the order they were blended: decreasing T).  Accumulates into
+ * per-Gaussian intermediate gradients gi[16 * id]: o_g (3), A (9), alpha~ (1),
+ * colour (3). */
+#define OR_GI 16
+static void pixel_reverse(or_contrib *seq, int64_t ns, int64_t *idx, const or_gauss *gs, const or_camera *cam,
+                          const double *gC, double x, double y, double *gi)
+{
+    int64_t m = 0;
+    for (int64_t j = 0; j < ns; ++j)
+        if (seq[j].tat >= 0) idx[m++] = j;
+    for (int64_t i = 1; i < m; ++i) { /* sort by decreasing T (= blend order) */
+        int64_t v = idx[i], j = i - 1;
+        while (j >= 0 && seq[idx[j]].tat < seq[v].tat) { idx[j + 1] = idx[j]; --j; }
+        idx[j + 1] = v;
+    }
+    double gT = cam->bg[0] * gC[0] + cam->bg[1] * gC[1] + cam->bg[2] * gC[2];
+    double rv[3] = {(x - cam->cx) / cam->fx, (y - cam->cy) / cam->fy, 1.0};
+    for (int64_t k = m - 1; k >= 0; --k) {
+        const or_contrib *e = &seq[idx[k]];
+        const or_gauss *g = &gs[e->id];
+        double Tk = e->tat, a = e->a;
+        double cg = e->c[0] * gC[0] + e->c[1] * gC[1] + e->c[2] * gC[2];
+        double ga = Tk * cg - Tk * gT;
+        double *G = gi + OR_GI * e->id;
+        for (int c = 0; c < 3; ++c) {
+#pragma omp atomic
+            G[13 + c] += Tk * a * gC[c];
+        }
+        gT = a * cg + (1.0 - a) * gT;
+        if (e->clamped) continue;
+        double ex = exp(-0.5 * e->r2);
+#pragma omp atomic
+        G[12] += ga * ex;
+        double gr2 = -0.5 * ga * a;
+        double r[3];
+        matvec3(g->A, rv, r);
+        double rr = dot3(r, r), orr = dot3(g->o_g, r);
+        for (int c = 0; c < 3; ++c) {
+            double dro = 2.0 * g->o_g[c] - 2.0 * orr / rr * r[c];
+            double drr = -2.0 * orr / rr * g->o_g[c] + 2.0 * orr * orr / (rr * rr) * r[c];
+#pragma omp atomic
+            G[c] += gr2 * dro;
+            for (int j = 0; j < 3; ++j) {
+#pragma omp atomic
+                G[3 + 3 * c + j] += gr2 * drr * rv[j];
+            }
+        }
+    }
+}
+
+static int render_impl(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
+                       double *out_rgb, double *out_T, uint8_t *out_flags, int32_t *out_ncontrib, or_stats *stats,
+                       const double *dL_drgb, double *gi)
 {
     const int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
@@ -619,6 +675,7 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
     {
         or_contrib *seq = NULL;
         int64_t *win = (int64_t *)malloc(sizeof(int64_t) * (K + 2));
+        int64_t *ridx = NULL;
         double *dt = NULL;
         int64_t *zi = NULL;
         int64_t cap = 0;
@@ -632,6 +689,7 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
                 seq = (or_contrib *)realloc(seq, sizeof(or_contrib) * cap);
                 dt = (double *)realloc(dt, sizeof(double) * cap);
                 zi = (int64_t *)realloc(zi, sizeof(int64_t) * cap);
+                ridx = (int64_t *)realloc(ridx, sizeof(int64_t) * cap);
             }
             /* O9: tile depth = depth of maximum response on the tile-centre line */
             for (int64_t j = 0; j < m; ++j) {
@@ -668,6 +726,8 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
                             seq[ns].a = a;
                             seq[ns].c = g->color;
                             seq[ns].tat = -1.0;
+                            seq[ns].r2 = r2;
+                            seq[ns].clamped = g->alpha_t * exp(-0.5 * r2) > st->alpha_max;
                             ns++;
                         }
                     }
@@ -697,6 +757,10 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
                         }
                     }
                     int64_t pix = (int64_t)py * W + px;
+                    if (dL_drgb) {
+                        double gC[3] = {dL_drgb[pix], dL_drgb[(int64_t)H * W + pix], dL_drgb[2 * (int64_t)H * W + pix]};
+                        pixel_reverse(seq, ns, ridx, gs, cam, gC, x, y, gi);
+                    }
                     for (int k = 0; k < 3; ++k) out_rgb[(int64_t)k * H * W + pix] = ps.C[k] + ps.T * cam->bg[k];
                     out_T[pix] = ps.T;
                     if (out_flags) out_flags[pix] = (uint8_t)ps.flag;
@@ -710,6 +774,7 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
         free(win);
         free(dt);
         free(zi);
+        free(ridx);
     }
     if (stats) {
         stats->n_visible = nvis;
@@ -725,6 +790,12 @@ int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, c
     free(fill);
     free(lists);
     return 0;
+}
+
+int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
+              double *out_rgb, double *out_T, uint8_t *out_flags, int32_t *out_ncontrib, or_stats *stats)
+{
+    return render_impl(sc, cam, st, tile_sel, out_rgb, out_T, out_flags, out_ncontrib, stats, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -878,4 +949,208 @@ int or_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradients (reverse mode with every discrete decision held fixed).
+ *
+ * The pixel part is the plain reverse recursion of the blend (pixel_reverse),
+ * giving per-Gaussian gradients of o_g, A, alpha~ and the colour.  The
+ * per-Gaussian chain from the parameters to those quantities is
+ * differentiated by the complex step: the same formulas as or_prepare are
+ * evaluated in complex arithmetic with one parameter perturbed by i*h, and
+ * Im(output)/h is the exact derivative (no subtraction, so no cancellation).
+ * Decisions (max(z, znear), min(v_train, v), the colour clamp) are taken on
+ * real parts, as in the forward pass.                                      */
+#include <complex.h>
+
+typedef double complex cx;
+
+static cx cdot3(const cx *a, const cx *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Real spherical harmonics in polynomial form: for a unit direction,
+ * sin^m(theta) cos(m phi) and sin^m(theta) sin(m phi) are the real and
+ * imaginary parts of (x + i y)^m (expanded with real recurrences), and
+ * P_l^m(cos theta) = sin^m(theta) Q_l^m(z) with Q_m^m = (-1)^m (2m-1)!!,
+ * Q_{m+1}^m = (2m+1) z Q_m^m, (l-m) Q_l^m = (2l-1) z Q_{l-1}^m - (l+m-1) Q_{l-2}^m. */
+static void sh_poly_cx(int degree, const cx *d, cx *Y)
+{
+    cx x = d[0], y = d[1], z = d[2];
+    cx Am[4], Bm[4];
+    Am[0] = 1.0;
+    Bm[0] = 0.0;
+    for (int m = 1; m <= 3; ++m) {
+        Am[m] = x * Am[m - 1] - y * Bm[m - 1];
+        Bm[m] = x * Bm[m - 1] + y * Am[m - 1];
+    }
+    for (int m = 0; m <= degree; ++m) {
+        cx Q[4];
+        double dfact = 1.0;
+        for (int k = 1; k <= 2 * m - 1; k += 2) dfact *= k;
+        Q[m] = ((m % 2) ? -1.0 : 1.0) * dfact;
+        if (m + 1 <= degree) Q[m + 1] = (2.0 * m + 1.0) * z * Q[m];
+        for (int l = m + 2; l <= degree; ++l) Q[l] = ((2.0 * l - 1.0) * z * Q[l - 1] - (l + m - 1.0) * Q[l - 2]) / (l - m);
+        for (int l = m; l <= degree; ++l) {
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * fact(l - m) / fact(l + m));
+            if (m == 0) {
+                Y[l * l + l] = N * Q[l];
+            } else {
+                Y[l * l + l + m] = sqrt(2.0) * N * Q[l] * Am[m];
+                Y[l * l + l - m] = sqrt(2.0) * N * Q[l] * Bm[m];
+            }
+        }
+    }
+}
+
+void or_sh_basis_poly(int degree, const double *dir, double *Y)
+{
+    double n = sqrt(dot3(dir, dir));
+    cx d[3] = {dir[0] / n, dir[1] / n, dir[2] / n}, Yc[16];
+    sh_poly_cx(degree, d, Yc);
+    for (int b = 0; b < (degree + 1) * (degree + 1); ++b) Y[b] = creal(Yc[b]);
+}
+
+/* Parameter vector of one Gaussian: mu (3), log s (3), q (4), logit (1),
+ * sh [(deg+1)^2][3] (coefficient-major).  Outputs: o_g (3), A (9), alpha~,
+ * colour (3) -- the same quantities as or_prepare. */
+#define OR_NPAR_MAX (11 + 48)
+static void cont_cx(const cx *par, int deg, double v_train, const or_camera *cam, const or_settings *st, cx *out)
+{
+    double RV[9], tV[3], o[3];
+    camera_parts(cam, RV, tV, o);
+    const cx *mu = par, *ls = par + 3, *q = par + 6;
+    cx logit = par[10];
+    const cx *sh = par + 11;
+    cx s[3], s2[3], shat[3], st_[3];
+    for (int k = 0; k < 3; ++k) s[k] = cexp(ls[k]);
+    cx alpha = 1.0 / (1.0 + cexp(-logit));
+    cx qn = csqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    cx w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+    cx R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+               2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+               2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    cx muv[3];
+    for (int r = 0; r < 3; ++r) muv[r] = RV[3 * r] * mu[0] + RV[3 * r + 1] * mu[1] + RV[3 * r + 2] * mu[2] + tV[r];
+    cx dz = creal(muv[2]) > cam->znear ? muv[2] : (cx)cam->znear;
+    cx v = cam->fx / dz;
+    if (v_train > 0 && v_train < creal(v)) v = v_train;
+    cx a = st->filter_mode == 1 ? (cx)0.0 : st->filter_k / (v * v);
+    for (int k = 0; k < 3; ++k) {
+        s2[k] = s[k] * s[k];
+        shat[k] = s2[k] + a;
+        st_[k] = csqrt(shat[k]);
+    }
+    cx d[3] = {mu[0] - o[0], mu[1] - o[1], mu[2] - o[2]};
+    cx dn = csqrt(cdot3(d, d));
+    for (int k = 0; k < 3; ++k) d[k] /= dn;
+    cx alpha_t;
+    if (st->filter_mode == 1) {
+        alpha_t = alpha;
+    } else if (st->filter_mode == 2) {
+        alpha_t = alpha * csqrt((s2[0] * s2[1] * s2[2]) / (shat[0] * shat[1] * shat[2]));
+    } else {
+        cx dp[3];
+        for (int k = 0; k < 3; ++k) dp[k] = R[k] * d[0] + R[3 + k] * d[1] + R[6 + k] * d[2];
+        cx num = dp[0] * dp[0] * s2[1] * s2[2] + dp[1] * dp[1] * s2[0] * s2[2] + dp[2] * dp[2] * s2[0] * s2[1];
+        cx den = dp[0] * dp[0] * shat[1] * shat[2] + dp[1] * dp[1] * shat[0] * shat[2] + dp[2] * dp[2] * shat[0] * shat[1];
+        alpha_t = alpha * csqrt(num / den);
+    }
+    /* o_g = S~^-1 R^T (o - mu);  A = S~^-1 R^T R_V^T */
+    cx om[3] = {o[0] - mu[0], o[1] - mu[1], o[2] - mu[2]};
+    for (int r = 0; r < 3; ++r) {
+        out[r] = (R[r] * om[0] + R[3 + r] * om[1] + R[6 + r] * om[2]) / st_[r];
+        for (int c = 0; c < 3; ++c)
+            out[3 + 3 * r + c] = (R[r] * RV[3 * c] + R[3 + r] * RV[3 * c + 1] + R[6 + r] * RV[3 * c + 2]) / st_[r];
+    }
+    out[12] = alpha_t;
+    cx Y[16];
+    sh_poly_cx(deg, d, Y);
+    int nb = (deg + 1) * (deg + 1);
+    for (int ch = 0; ch < 3; ++ch) {
+        cx acc = 0.5;
+        for (int b = 0; b < nb; ++b) acc += Y[b] * sh[3 * b + ch];
+        out[13 + ch] = creal(acc) > 0 ? acc : (cx)0.0;
+    }
+}
+
+/* Values of the continuous chain (real parts), for consistency checks against or_prepare. */
+int or_cont_values(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t i, double *out16)
+{
+    const int64_t n = sc->n;
+    int nb = (sc->sh_degree + 1) * (sc->sh_degree + 1);
+    cx par[OR_NPAR_MAX], out[16];
+    for (int k = 0; k < 3; ++k) { par[k] = sc->means[k * n + i]; par[3 + k] = sc->log_scales[k * n + i]; }
+    for (int k = 0; k < 4; ++k) par[6 + k] = sc->quats[k * n + i];
+    par[10] = sc->opacity_logits[i];
+    for (int b = 0; b < nb; ++b)
+        for (int ch = 0; ch < 3; ++ch) par[11 + 3 * b + ch] = sc->sh[((int64_t)b * 3 + ch) * n + i];
+    cont_cx(par, sc->sh_degree, sc->v_train ? sc->v_train[i] : -1.0, cam, st, out);
+    for (int k = 0; k < 16; ++k) out16[k] = creal(out[k]);
+    return 0;
+}
+
+/*
+ * Gradient of L = sum(dL_drgb * rgb) with respect to the scene parameters,
+ * written (not accumulated) into g_means [3][n], g_log_scales [3][n],
+ * g_quats [4][n], g_logits [n], g_sh [(deg+1)^2][3][n].  Also returns the
+ * forward image and flags (rgb, T, flags as in or_render).
+ */
+int or_render_backward(const or_scene *sc, const or_camera *cam, const or_settings *st, const double *dL_drgb,
+                       double *out_rgb, double *out_T, uint8_t *out_flags, double *g_means, double *g_log_scales,
+                       double *g_quats, double *g_logits, double *g_sh)
+{
+    const int64_t n = sc->n;
+    double *gi = (double *)calloc((size_t)(n > 0 ? n : 1) * OR_GI, sizeof(double));
+    if (!gi) return 1;
+    or_stats stt;
+    int rc = render_impl(sc, cam, st, NULL, out_rgb, out_T, out_flags, NULL, &stt, dL_drgb, gi);
+    if (rc) { free(gi); return rc; }
+    const int deg = sc->sh_degree, nb = (deg + 1) * (deg + 1);
+    const int npar = 11 + 3 * nb;
+    const double h = 1e-20;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const double *G = gi + OR_GI * i;
+        double gpar[OR_NPAR_MAX];
+        for (int p = 0; p < npar; ++p) gpar[p] = 0.0;
+        int any = 0;
+        for (int k = 0; k < OR_GI; ++k) any |= G[k] != 0.0;
+        if (any) {
+            cx par[OR_NPAR_MAX], out[16];
+            for (int k = 0; k < 3; ++k) { par[k] = sc->means[k * n + i]; par[3 + k] = sc->log_scales[k * n + i]; }
+            for (int k = 0; k < 4; ++k) par[6 + k] = sc->quats[k * n + i];
+            par[10] = sc->opacity_logits[i];
+            for (int b = 0; b < nb; ++b)
+                for (int ch = 0; ch < 3; ++ch) par[11 + 3 * b + ch] = sc->sh[((int64_t)b * 3 + ch) * n + i];
+            double vt = sc->v_train ? sc->v_train[i] : -1.0;
+            for (int p = 0; p < npar; ++p) {
+                cx keep = par[p];
+                par[p] = creal(keep) + I * h;
+                cont_cx(par, deg, vt, cam, st, out);
+                par[p] = keep;
+                double acc = 0.0;
+                for (int k = 0; k < 16; ++k) acc += G[k] * cimag(out[k]) / h;
+                gpar[p] = acc;
+            }
+        }
+        for (int k = 0; k < 3; ++k) { g_means[k * n + i] = gpar[k]; g_log_scales[k * n + i] = gpar[3 + k]; }
+        for (int k = 0; k < 4; ++k) g_quats[k * n + i] = gpar[6 + k];
+        g_logits[i] = gpar[10];
+        for (int b = 0; b < nb; ++b)
+            for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)b * 3 + ch) * n + i] = gpar[11 + 3 * b + ch];
+    }
+    free(gi);
+    return 0;
+}
+
+/* The same 16 quantities from the real-arithmetic preparation. */
+int or_prepare_values(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t i, double *out16)
+{
+    or_gauss g;
+    or_prepare(sc, cam, st, i, &g);
+    for (int k = 0; k < 3; ++k) out16[k] = g.o_g[k];
+    for (int k = 0; k < 9; ++k) out16[3 + k] = g.A[k];
+    out16[12] = g.alpha_t;
+    for (int k = 0; k < 3; ++k) out16[13 + k] = g.color[k];
+    return g.status;
 }

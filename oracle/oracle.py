@@ -71,15 +71,16 @@ def lib():
     return _lib
 
 
-def _f32(a):
-    return np.ascontiguousarray(a, dtype=np.float32)
+def _f64(a):
+    # float32 inputs convert exactly; float64 inputs (finite differences) pass through
+    return np.ascontiguousarray(a, dtype=np.float64)
 
 
 class _SceneHolder:
     def __init__(self, scene):
-        self.arrays = [_f32(scene.means), _f32(scene.log_scales), _f32(scene.quats), _f32(scene.opacity_logits),
-                       _f32(scene.sh)]
-        self.vt = None if scene.v_train is None else _f32(scene.v_train)
+        self.arrays = [_f64(scene.means), _f64(scene.log_scales), _f64(scene.quats), _f64(scene.opacity_logits),
+                       _f64(scene.sh)]
+        self.vt = None if scene.v_train is None else _f64(scene.v_train)
         n = self.arrays[0].shape[1]
         nb = self.arrays[4].shape[0]
         deg = int(round(np.sqrt(nb))) - 1
@@ -238,3 +239,58 @@ def rotation(q):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def sh_basis_poly(degree, direction):
+    """Polynomial-form real SH (the form the gradient chain uses)."""
+    L = lib()
+    d = np.ascontiguousarray(direction, np.float64)
+    Y = np.zeros(16)
+    L.or_sh_basis_poly.argtypes = [C.c_int, C.c_void_p, C.c_void_p]
+    L.or_sh_basis_poly(int(degree), _p(d), _p(Y))
+    return Y[: (degree + 1) ** 2]
+
+
+def gauss_values(scene, cam, settings, i, complex_chain=False):
+    """o_g (3), A (9), alpha~, colour (3) of Gaussian i, from the real
+    preparation or from the complex-arithmetic chain used for gradients."""
+    L = lib()
+    sh = _SceneHolder(scene)
+    c, s = _camera(cam), _settings(settings)
+    out = np.zeros(16)
+    f = L.or_cont_values if complex_chain else L.or_prepare_values
+    f.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Settings), C.c_int64, C.c_void_p]
+    st = f(C.byref(sh.s), C.byref(c), C.byref(s), int(i), _p(out))
+    return out, st
+
+
+@dataclass
+class GradResult:
+    rgb: np.ndarray
+    T: np.ndarray
+    flags: np.ndarray
+    means: np.ndarray
+    log_scales: np.ndarray
+    quats: np.ndarray
+    opacity_logits: np.ndarray
+    sh: np.ndarray
+
+
+def render_backward(scene, cam, settings, dL_drgb) -> GradResult:
+    """FP64 gradient of sum(dL_drgb * rgb) w.r.t. every scene parameter
+    (decisions held fixed)."""
+    L = lib()
+    sh = _SceneHolder(scene)
+    c, s = _camera(cam), _settings(settings)
+    H, W = int(cam.height), int(cam.width)
+    g = np.ascontiguousarray(dL_drgb, np.float64).reshape(3, H, W)
+    n = sh.s.n
+    nb = (sh.s.sh_degree + 1) ** 2
+    rgb, T = np.zeros((3, H, W)), np.zeros((H, W))
+    flags = np.zeros((H, W), np.uint8)
+    gm, gl, gq, go, gs = np.zeros((3, n)), np.zeros((3, n)), np.zeros((4, n)), np.zeros(n), np.zeros((nb, 3, n))
+    L.or_render_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Settings)] + [C.c_void_p] * 9
+    rc = L.or_render_backward(C.byref(sh.s), C.byref(c), C.byref(s), _p(g), _p(rgb), _p(T), _p(flags), _p(gm),
+                              _p(gl), _p(gq), _p(go), _p(gs))
+    assert rc == 0
+    return GradResult(rgb, T, flags, gm, gl, gq, go, gs)
