@@ -152,14 +152,17 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
                aaa_stats *stats);
 
 /* Gradient of a scalar loss L given dL/d(out_rgb) [3][H][W] (DEVICE) for the
- * last aaa_render into `ws` with the same scene, camera and settings.
- * Accumulates into `grad` (DEVICE arrays, same layouts as the scene; any
- * pointer may be NULL to skip it).  The blend state is recomputed per tile
- * (no per-pixel lists are stored).  Decisions (culls, thresholds, clamps)
- * are held fixed; their gradients are zero or one-sided. */
+ * last aaa_render into `ws` with the same scene, camera and settings; out_rgb
+ * is that render's output (DEVICE, read).  Accumulates (+=) into `grad`
+ * (DEVICE arrays, same layouts as the scene; any pointer may be NULL to skip
+ * it).  The blend state is recomputed per tile from the stored sorted pairs
+ * (no per-pixel lists are stored).  Decisions (culls, thresholds, the window
+ * order, the alpha clamp, min(v_train, v), the colour clamp) are held fixed;
+ * their gradients are zero or one-sided.  Uses the workspace's gradient
+ * region; the forward state is left intact (backward may be called again). */
 int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
-                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *dL_drgb,
-                        aaa_scene_grad *grad);
+                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
+                        const float *dL_drgb, aaa_scene_grad *grad);
 
 /* Accumulated stage times (milliseconds, HIP events on the render stream) of
  * every aaa_render with AAA_TIMING since the last reset, and the number of

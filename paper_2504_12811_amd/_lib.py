@@ -79,7 +79,7 @@ def lib():
         L.aaa_render.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t, u64,
                                  vp, vp, vp, C.POINTER(Stats)]
         L.aaa_render_backward.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t,
-                                          u64, vp, vp, C.POINTER(SceneGrad)]
+                                          u64, vp, vp, vp, C.POINTER(SceneGrad)]
         L.aaa_read_gaussians.argtypes = [C.POINTER(Scene), C.POINTER(Camera), u64, vp, C.c_size_t, vp, vp, vp, vp, vp,
                                          vp]
         L.aaa_read_pairs.argtypes = [C.POINTER(Scene), C.POINTER(Camera), u64, vp, C.c_size_t, vp, vp, vp, vp, u64,

@@ -9,12 +9,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaaa_hip.so")
-SOURCES = ["api.hip", "preprocess.hip", "emit.hip", "sort.hip", "blend.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "emit.hip", "sort.hip", "blend.hip", "backward.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are disabled throughout
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # native float atomic adds (device memory is coarse-grained)
+    "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 

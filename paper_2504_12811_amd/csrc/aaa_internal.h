@@ -10,6 +10,8 @@ constexpr int kTile = 16;          // tile edge in pixels
 constexpr int kRecQuads = 8;       // float4 per blend record (128 B)
 constexpr int kCullQuads = 8;      // float4 per culling record (128 B)
 constexpr float kLog2eHalf = 0.72134752044448170368f;  // log2(e) / 2
+constexpr int kGradStride = 24;    // floats per Gaussian in the record-gradient buffer:
+                                   // c0 c1 c2 w0 w1 w2 (18), alpha~ (1), colour (3), pad
 
 enum Status : int32_t { kVisible = 0, kInvalid = 1, kLowOpacity = 2, kCamInside = 3, kOutside = 4 };
 
@@ -209,9 +211,16 @@ struct BlendArgs {
     CamDev cam;
     float alpha_min, alpha_max, t_min, znear;
     float bg[3];
-    float *out_rgb, *out_T;
+    float *out_rgb, *out_T;        // forward: written; backward: out_rgb read (C_out)
     uint32_t *n_done;  // per pixel: list entries consumed
     unsigned long long *counters;  // [0] evaluations, [1] contributors, [2] prefilter passes
+    const float *dL_drgb;          // backward only
+    float *grad_rec;               // backward only: [n][kGradStride]
 };
-hipError_t launch_blend(const BlendArgs &a, int K, bool stats, hipStream_t s);
+hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool bwd, hipStream_t s);
+
+struct GradOut {
+    float *means, *log_scales, *quats, *logits, *sh;
+};
+hipError_t launch_preprocess_bwd(const PreArgs &a, const float *grad_rec, GradOut g, hipStream_t s);
 }  // namespace aaa

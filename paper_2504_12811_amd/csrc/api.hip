@@ -37,7 +37,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t hdr, status, rect, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp, ranges,
-        n_done, total;
+        n_done, grad_rec, total;
 };
 
 int tiles_of(const aaa_camera *cam, int *tx, int *ty)
@@ -76,6 +76,7 @@ Layout layout(int64_t n, const aaa_camera *cam, uint64_t max_pairs)
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
     L.ranges = take((size_t)ntiles * 8);
     L.n_done = take(pix * 4);
+    L.grad_rec = take(nn * 4 * aaa::kGradStride);
     L.total = o;
     return L;
 }
@@ -127,6 +128,35 @@ aaa::CamDev cam_dev(const aaa_camera *cam)
 
 template <typename T>
 T *at(void *ws, size_t off) { return (T *)((char *)ws + off); }
+
+aaa::PreArgs pre_args(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, void *ws,
+                      const Layout &L)
+{
+    aaa::PreArgs pa;
+    pa.means = scene->means;
+    pa.log_scales = scene->log_scales;
+    pa.quats = scene->quats;
+    pa.logits = scene->opacity_logits;
+    pa.sh = scene->sh;
+    pa.v_train = scene->v_train;
+    pa.n = scene->n;
+    pa.sh_degree = scene->sh_degree;
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) pa.RV[3 * r + c] = cam->viewmat[4 * r + c];
+        pa.tV[r] = cam->viewmat[4 * r + 3];
+    }
+    for (int r = 0; r < 3; ++r) pa.o[r] = -(pa.RV[r] * pa.tV[0] + pa.RV[3 + r] * pa.tV[1] + pa.RV[6 + r] * pa.tV[2]);
+    pa.cam = cam_dev(cam);
+    pa.filter_k = settings->filter_k;
+    pa.alpha_min = settings->alpha_min;
+    pa.alpha_max = settings->alpha_max;
+    pa.filter_mode = (settings->flags & AAA_FILTER_OFF) ? 1 : ((settings->flags & AAA_FILTER_VOLUME) ? 2 : 0);
+    pa.status = at<int32_t>(ws, L.status);
+    pa.rect = at<int4>(ws, L.rect);
+    pa.rec = at<float4>(ws, L.rec);
+    pa.cull = at<float4>(ws, L.cull);
+    return pa;
+}
 
 }  // namespace
 
@@ -263,29 +293,7 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     do { if (timing) HIP_TRY(hipEventRecord(ev[k], s)); } while (0)
     HIP_TRY(hipMemsetAsync(ctr, 0, 64, s));
 
-    aaa::PreArgs pa;
-    pa.means = scene->means;
-    pa.log_scales = scene->log_scales;
-    pa.quats = scene->quats;
-    pa.logits = scene->opacity_logits;
-    pa.sh = scene->sh;
-    pa.v_train = scene->v_train;
-    pa.n = n;
-    pa.sh_degree = scene->sh_degree;
-    for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c) pa.RV[3 * r + c] = cam->viewmat[4 * r + c];
-        pa.tV[r] = cam->viewmat[4 * r + 3];
-    }
-    for (int r = 0; r < 3; ++r) pa.o[r] = -(pa.RV[r] * pa.tV[0] + pa.RV[3 + r] * pa.tV[1] + pa.RV[6 + r] * pa.tV[2]);
-    pa.cam = cd;
-    pa.filter_k = settings->filter_k;
-    pa.alpha_min = settings->alpha_min;
-    pa.alpha_max = settings->alpha_max;
-    pa.filter_mode = (settings->flags & AAA_FILTER_OFF) ? 1 : ((settings->flags & AAA_FILTER_VOLUME) ? 2 : 0);
-    pa.status = at<int32_t>(ws, L.status);
-    pa.rect = at<int4>(ws, L.rect);
-    pa.rec = at<float4>(ws, L.rec);
-    pa.cull = at<float4>(ws, L.cull);
+    aaa::PreArgs pa = pre_args(scene, cam, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
     STAGE_MARK(1);
 
@@ -344,7 +352,9 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     ba.out_T = out_T;
     ba.n_done = at<uint32_t>(ws, L.n_done);
     ba.counters = ctr + 2;
-    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, s));
+    ba.dL_drgb = nullptr;
+    ba.grad_rec = nullptr;
+    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, false, s));
     if (timing) {
         STAGE_MARK(8);
         ctx->pending[ctx->cur] = true;
@@ -446,12 +456,51 @@ int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits_, 
 }
 
 int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
-                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *dL_drgb,
-                        aaa_scene_grad *grad)
+                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
+                        const float *dL_drgb, aaa_scene_grad *grad)
 {
-    (void)ctx; (void)scene; (void)cam; (void)settings; (void)ws; (void)ws_bytes; (void)max_pairs; (void)stream;
-    (void)dL_drgb; (void)grad;
-    return fail(AAA_ERR_UNSUPPORTED, "backward not built yet");
+    if (!ctx) return fail(AAA_ERR_INVALID, "null context");
+    int rc = check_common(scene, cam, settings);
+    if (rc) return rc;
+    if (!ws || !out_rgb || !dL_drgb || !grad) return fail(AAA_ERR_INVALID, "null workspace, image or gradient");
+    Layout L = layout(scene->n, cam, max_pairs);
+    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t n = scene->n;
+    if (n == 0) return AAA_OK;
+    int tx, ty;
+    const int ntiles = tiles_of(cam, &tx, &ty);
+    float *grad_rec = at<float>(ws, L.grad_rec);
+    HIP_TRY(hipMemsetAsync(grad_rec, 0, (size_t)n * 4 * aaa::kGradStride, s));
+    aaa::PreArgs pa = pre_args(scene, cam, settings, ws, L);
+    const bool alt = sorted_in_alt(ntiles);
+    aaa::BlendArgs ba;
+    ba.rec = pa.rec;
+    ba.keys = at<uint64_t>(ws, alt ? L.keys_alt : L.keys);
+    ba.vals = at<uint32_t>(ws, alt ? L.vals_alt : L.vals);
+    ba.ranges = at<uint32_t>(ws, L.ranges);
+    ba.cam = cam_dev(cam);
+    ba.alpha_min = (float)settings->alpha_min;
+    ba.alpha_max = (float)settings->alpha_max;
+    ba.t_min = (float)settings->t_min;
+    ba.znear = (float)cam->znear;
+    for (int k = 0; k < 3; ++k) ba.bg[k] = (float)cam->bg[k];
+    ba.out_rgb = const_cast<float *>(out_rgb);
+    ba.out_T = nullptr;
+    ba.n_done = at<uint32_t>(ws, L.n_done);
+    ba.counters = nullptr;
+    ba.dL_drgb = dL_drgb;
+    ba.grad_rec = grad_rec;
+    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));
+    aaa::GradOut go;
+    go.means = grad->means;
+    go.log_scales = grad->log_scales;
+    go.quats = grad->quats;
+    go.logits = grad->opacity_logits;
+    go.sh = grad->sh;
+    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, s));
+    return AAA_OK;
 }
 
 }  // extern "C"

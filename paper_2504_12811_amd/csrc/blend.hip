@@ -1,8 +1,10 @@
-// K5: per-tile blending.  One workgroup per 16x16 tile; each wavefront owns
-// an 8x8 quadrant and walks the tile's sorted list on its own (no barriers,
-// per-wave early exit).  Every lane of a wave needs the same Gaussian at the
-// same time, so the list entry and its record are fetched with scalar loads
-// and reach the arithmetic as SGPR operands.
+// K5: per-tile blending, and K6a: its adjoint (the same kernel replayed).
+//
+// One workgroup per 16x16 tile; each wavefront owns an 8x8 quadrant and walks
+// the tile's sorted list on its own (no barriers, per-wave early exit).  Every
+// lane of a wave needs the same Gaussian at the same time, so the list entry
+// and its record are fetched with scalar loads and reach the arithmetic as
+// SGPR operands.
 //
 // Per pixel and list entry (Sec. 3.1, Eq. 4-5): rho^2 and the depth of the
 // maximum along the pixel line from the anchored record; alpha =
@@ -11,6 +13,14 @@
 // registers (the per-ray level of the hierarchical re-sort, Sec. 4); when it
 // overflows its front is blended front to back; blending stops before the
 // first entry that would take the transmittance below t_min.
+//
+// The adjoint replays exactly the same decisions (same code, explicit FMAs)
+// and, at every blended entry k with transmittance T_k, uses the
+// front-to-back form of the blend derivative:
+//   dC/dalpha_k = T_k c_k - (C_out - A_k) / (1 - alpha_k),  A_k = sum_{j<=k} T_j alpha_j c_j,
+// so no per-pixel list is stored: the state is recomputed per tile.  The 22
+// record gradients of an entry (line coefficients, alpha~, colour) are summed
+// over the lanes that blended the same Gaussian and added atomically.
 #include "aaa_internal.h"
 
 namespace aaa {
@@ -22,25 +32,127 @@ struct PixelState {
     bool done;
 };
 
-__device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t id, float a,
-                                            float t_min)
+struct Eval {
+    float rx, ry, rz, wx, wy, wz, D, N;
+};
+
+// Line direction r and o_g x r at a pixel offset, with explicit FMAs so that
+// the forward pass and its replay take identical decisions.
+__device__ __forceinline__ Eval eval_line(float dx, float dy, float4 q0, float4 q1, float4 q2, float4 q3, float4 q4)
 {
-    if (a > 0.0f) {  // window fillers carry alpha 0
-        float Tn = ps.T * (1.0f - a);
-        if (Tn < t_min) {
-            ps.done = true;
-        } else {
-            float4 c = rec[(size_t)id * kRecQuads + 7];
-            float wgt = ps.T * a;
-            ps.C[0] += wgt * c.x;
-            ps.C[1] += wgt * c.y;
-            ps.C[2] += wgt * c.z;
-            ps.T = Tn;
-        }
+    Eval e;
+    e.rx = __fmaf_rn(dy, q1.z, __fmaf_rn(dx, q0.w, q0.x));
+    e.ry = __fmaf_rn(dy, q1.w, __fmaf_rn(dx, q1.x, q0.y));
+    e.rz = __fmaf_rn(dy, q2.x, __fmaf_rn(dx, q1.y, q0.z));
+    e.wx = __fmaf_rn(dy, q3.w, __fmaf_rn(dx, q3.x, q2.y));
+    e.wy = __fmaf_rn(dy, q4.x, __fmaf_rn(dx, q3.y, q2.z));
+    e.wz = __fmaf_rn(dy, q4.y, __fmaf_rn(dx, q3.z, q2.w));
+    e.D = __fmaf_rn(e.rz, e.rz, __fmaf_rn(e.ry, e.ry, e.rx * e.rx));
+    e.N = __fmaf_rn(e.wz, e.wz, __fmaf_rn(e.wy, e.wy, e.wx * e.wx));
+    return e;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+struct BwdPixel {
+    float A[3];     // front colour accumulated so far
+    float Cout[3];  // forward output of the pixel
+    float g[3];     // dL / d out_rgb
+    float fx, fy;   // pixel centre
+};
+
+// Gradients of one blended entry at one pixel (22 values) for Gaussian id.
+__device__ __forceinline__ void entry_grad(const float4 *__restrict__ rec, uint32_t id, float T, float a, float amax,
+                                           BwdPixel &bp, float *v)
+{
+    const float4 *r = rec + (size_t)id * kRecQuads;
+    const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q7 = r[7];
+    const float W = T * a;
+    bp.A[0] += W * q7.x;
+    bp.A[1] += W * q7.y;
+    bp.A[2] += W * q7.z;
+    const float cg = q7.x * bp.g[0] + q7.y * bp.g[1] + q7.z * bp.g[2];
+    const float Sg = (bp.Cout[0] - bp.A[0]) * bp.g[0] + (bp.Cout[1] - bp.A[1]) * bp.g[1] +
+                     (bp.Cout[2] - bp.A[2]) * bp.g[2];
+    const float ga = T * cg - Sg / (1.0f - a);
+    v[19] = W * bp.g[0];
+    v[20] = W * bp.g[1];
+    v[21] = W * bp.g[2];
+    if (a >= amax) {  // clamped: alpha does not move with rho^2 or alpha~
+        for (int k = 0; k < 19; ++k) v[k] = 0.0f;
+        return;
+    }
+    v[18] = ga * a / q5.w;
+    const float gr2 = -0.5f * ga * a;
+    const float dx = bp.fx - q5.y, dy = bp.fy - q5.z;
+    const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
+    const float invD = 1.0f / e.D;
+    const float rho2 = e.N * invD;
+    const float kw = 2.0f * gr2 * invD, kr = -2.0f * gr2 * rho2 * invD;
+    const float gr[3] = {kr * e.rx, kr * e.ry, kr * e.rz};
+    const float gw[3] = {kw * e.wx, kw * e.wy, kw * e.wz};
+    for (int k = 0; k < 3; ++k) {
+        v[k] = gr[k];
+        v[3 + k] = dx * gr[k];
+        v[6 + k] = dy * gr[k];
+        v[9 + k] = gw[k];
+        v[12 + k] = dx * gw[k];
+        v[15 + k] = dy * gw[k];
     }
 }
 
-template <int K, bool STATS>
+// Sum the pending entry gradients of lanes that blended the same Gaussian
+// and add them to the record-gradient buffer (one atomic per value and group).
+__device__ __forceinline__ void flush_grads(bool pending, uint32_t id, const float *v, float *__restrict__ grad_rec)
+{
+    uint64_t left = __ballot(pending);
+    while (left) {
+        const int leader = __ffsll((unsigned long long)left) - 1;
+        const uint32_t gid = (uint32_t)__shfl((int)id, leader);
+        const bool mine = pending && id == gid;
+        float *dst = grad_rec + (size_t)gid * kGradStride;
+#pragma unroll
+        for (int k = 0; k < 22; ++k) {
+            const float s = wave_sum(mine ? v[k] : 0.0f);
+            if ((int)__lane_id() == leader && s != 0.0f) atomicAdd(&dst[k], s);
+        }
+        left &= ~__ballot(mine);
+    }
+}
+
+template <bool BWD>
+__device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t id, float a,
+                                            float t_min, float amax, BwdPixel &bp, float *__restrict__ grad_rec)
+{
+    bool pending = false;
+    float v[BWD ? 22 : 1];
+    if (a > 0.0f && !ps.done) {  // window fillers and idle lanes carry alpha 0
+        const float Tn = ps.T * (1.0f - a);
+        if (Tn < t_min) {
+            ps.done = true;
+        } else {
+            if (BWD) {
+                entry_grad(rec, id, ps.T, a, amax, bp, v);
+                pending = true;
+            } else {
+                const float4 c = rec[(size_t)id * kRecQuads + 7];
+                const float wgt = ps.T * a;
+                ps.C[0] += wgt * c.x;
+                ps.C[1] += wgt * c.y;
+                ps.C[2] += wgt * c.z;
+            }
+            ps.T = Tn;
+        }
+    }
+    if (BWD) flush_grads(pending, id, v, grad_rec);
+}
+
+template <int K, bool STATS, bool BWD>
 __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
 {
     const int ntiles = a.cam.tiles_x * a.cam.tiles_y;
@@ -56,6 +168,8 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     const bool inside = px < a.cam.width && py < a.cam.height;
     const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const size_t hw = (size_t)a.cam.width * a.cam.height;
+    const size_t pix = inside ? (size_t)py * a.cam.width + px : 0;
 
     float wz[K > 0 ? K : 1];
     uint32_t wid[K > 0 ? K : 1];
@@ -70,6 +184,14 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     ps.T = 1.0f;
     ps.C[0] = ps.C[1] = ps.C[2] = 0.0f;
     ps.done = !inside;
+    BwdPixel bp;
+    bp.fx = fxp;
+    bp.fy = fyp;
+    for (int c = 0; c < 3; ++c) {
+        bp.A[c] = 0.0f;
+        bp.Cout[c] = (BWD && inside) ? a.out_rgb[c * hw + pix] : 0.0f;
+        bp.g[c] = (BWD && inside) ? a.dL_drgb[c * hw + pix] : 0.0f;
+    }
     uint32_t consumed = 0;
     uint32_t n_eval = 0, n_contrib = 0, n_near = 0;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = a.znear;
@@ -81,28 +203,21 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
         const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
         if (STATS && !ps.done) ++n_eval;
         const float dx = fxp - q5.y, dy = fyp - q5.z;
-        const float rx = q0.x + dx * q0.w + dy * q1.z;
-        const float ry = q0.y + dx * q1.x + dy * q1.w;
-        const float rz = q0.z + dx * q1.y + dy * q2.x;
-        const float wx = q2.y + dx * q3.x + dy * q3.w;
-        const float wy = q2.z + dx * q3.y + dy * q4.x;
-        const float wzz = q2.w + dx * q3.z + dy * q4.y;
-        const float D = rx * rx + ry * ry + rz * rz;
-        const float N = wx * wx + wy * wy + wzz * wzz;
-        const bool near = !ps.done && N <= q6.x * D;
+        const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
+        const bool near = !ps.done && e.N <= q6.x * e.D;
         // wave-uniform branches from here on: the window registers are only
         // ever updated with all lanes active (no divergent copies)
         if (__ballot(near) == 0ull) continue;
         if (STATS && near) ++n_near;
-        const float inv = __builtin_amdgcn_rcpf(D);
-        const float rho2 = N * inv;
-        const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-rho2 * kLog2eHalf));
-        const float z = (q4.z + dx * q4.w + dy * q5.x) * inv;
+        const float inv = __builtin_amdgcn_rcpf(e.D);
+        const float rho2 = e.N * inv;
+        const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
+        const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
         const bool contrib = near && al >= amin && z >= znear;
         if (__ballot(contrib) == 0ull) continue;
         if (STATS && contrib) ++n_contrib;
         if (K == 0) {
-            if (contrib) blend_entry(ps, a.rec, id, al, tmin);
+            blend_entry<BWD>(ps, a.rec, id, contrib ? al : 0.0f, tmin, amax, bp, a.grad_rec);
         } else {
             // Non-contributing lanes insert a NaN depth: every comparison is
             // false, the window stays as it is and the popped entry is the
@@ -122,19 +237,19 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
                 wa[k] = gnext ? wa[kn] : (gcur ? ak : wa[k]);
                 gcur = gnext;
             }
-            blend_entry(ps, a.rec, pop_id, pop_a, tmin);
+            blend_entry<BWD>(ps, a.rec, pop_id, pop_a, tmin, amax, bp, a.grad_rec);
         }
         if (contrib && ps.done && consumed == 0) consumed = i - start + 1;
     }
-    if (!ps.done) {
-        consumed = end - start;
+    // drain the window in depth order (lanes already done pass alpha 0)
+    const bool draining = !ps.done;
+    if (K > 0) {
 #pragma unroll
         for (int k = 0; k < (K > 0 ? K : 1); ++k)
-            if (K > 0 && !ps.done) blend_entry(ps, a.rec, wid[k], wa[k], tmin);
+            blend_entry<BWD>(ps, a.rec, wid[k], ps.done ? 0.0f : wa[k], tmin, amax, bp, a.grad_rec);
     }
-    if (inside) {
-        const size_t hw = (size_t)a.cam.width * a.cam.height;
-        const size_t pix = (size_t)py * a.cam.width + px;
+    if (draining) consumed = end - start;
+    if (!BWD && inside) {
         a.out_rgb[pix] = ps.C[0] + ps.T * a.bg[0];
         a.out_rgb[hw + pix] = ps.C[1] + ps.T * a.bg[1];
         a.out_rgb[2 * hw + pix] = ps.C[2] + ps.T * a.bg[2];
@@ -157,31 +272,33 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
 }
 
 template <int K>
-hipError_t launch_k(const BlendArgs &a, bool stats, hipStream_t s)
+hipError_t launch_k(const BlendArgs &a, bool stats, bool bwd, hipStream_t s)
 {
     const int ntiles = a.cam.tiles_x * a.cam.tiles_y;
     const int per = (ntiles + 7) / 8;
     dim3 grid((unsigned)(per * 8));
-    if (stats)
-        hipLaunchKernelGGL((k_blend<K, true>), grid, dim3(256), 0, s, a);
+    if (bwd)
+        hipLaunchKernelGGL((k_blend<K, false, true>), grid, dim3(256), 0, s, a);
+    else if (stats)
+        hipLaunchKernelGGL((k_blend<K, true, false>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_blend<K, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_blend<K, false, false>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_blend(const BlendArgs &a, int K, bool stats, hipStream_t s)
+hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool bwd, hipStream_t s)
 {
     if (a.cam.tiles_x * a.cam.tiles_y <= 0) return hipSuccess;
     switch (K) {
-    case 0: return launch_k<0>(a, stats, s);
-    case 1: return launch_k<1>(a, stats, s);
-    case 2: return launch_k<2>(a, stats, s);
-    case 4: return launch_k<4>(a, stats, s);
-    case 8: return launch_k<8>(a, stats, s);
-    case 16: return launch_k<16>(a, stats, s);
-    case 32: return launch_k<32>(a, stats, s);
+    case 0: return launch_k<0>(a, stats, bwd, s);
+    case 1: return launch_k<1>(a, stats, bwd, s);
+    case 2: return launch_k<2>(a, stats, bwd, s);
+    case 4: return launch_k<4>(a, stats, bwd, s);
+    case 8: return launch_k<8>(a, stats, bwd, s);
+    case 16: return launch_k<16>(a, stats, bwd, s);
+    case 32: return launch_k<32>(a, stats, bwd, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -6,6 +6,7 @@
 // bound by HBM traffic, and double precision keeps the bounds quadratic and
 // the anchored record free of cancellation); the records are stored as float.
 #include "aaa_internal.h"
+#include "gauss_setup.h"
 
 namespace aaa {
 
@@ -13,38 +14,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kBoundEps = 1e-3;  // clamp margin of the angular bounds (rad)
-
-__device__ __forceinline__ void cross3d(const double *a, const double *b, double *c)
-{
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-// Real spherical harmonics up to degree 3 (Condon-Shortley phase), index l*l+l+m.
-__device__ __forceinline__ void sh_eval(int deg, double x, double y, double z, double *Y)
-{
-    Y[0] = 0.28209479177387814;
-    if (deg < 1) return;
-    Y[1] = -0.48860251190291992 * y;
-    Y[2] = 0.48860251190291992 * z;
-    Y[3] = -0.48860251190291992 * x;
-    if (deg < 2) return;
-    double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = 1.0925484305920792 * x * y;
-    Y[5] = -1.0925484305920792 * y * z;
-    Y[6] = 0.31539156525252005 * (2.0 * zz - xx - yy);
-    Y[7] = -1.0925484305920792 * x * z;
-    Y[8] = 0.54627421529603959 * (xx - yy);
-    if (deg < 3) return;
-    Y[9] = -0.59004358992664352 * y * (3.0 * xx - yy);
-    Y[10] = 2.8906114426405538 * x * y * z;
-    Y[11] = -0.45704579946446572 * y * (4.0 * zz - xx - yy);
-    Y[12] = 0.3731763325901154 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-    Y[13] = -0.45704579946446572 * x * (4.0 * zz - xx - yy);
-    Y[14] = 1.4453057213202769 * z * (xx - yy);
-    Y[15] = -0.59004358992664352 * x * (xx - 3.0 * yy);
-}
 
 // Angular bounds of the level-tau ellipsoid seen from the camera in one view
 // plane (Sec. 3.3, Eq. 14-17).  Rows a (lateral: view x or y) and c (depth)
@@ -99,77 +68,14 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     if (i >= a.n) return;
     const int64_t n = a.n;
     a.rect[i] = make_int4(0, 0, 0, 0);
-    double mu[3], ls[3], q[4];
-    bool ok = true;
-    for (int k = 0; k < 3; ++k) {
-        mu[k] = a.means[k * n + i];
-        ls[k] = a.log_scales[k * n + i];
-        ok = ok && isfinite(mu[k]) && isfinite(ls[k]);
-    }
-    for (int k = 0; k < 4; ++k) {
-        q[k] = a.quats[k * n + i];
-        ok = ok && isfinite(q[k]);
-    }
-    double logit = a.logits[i];
-    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    ok = ok && isfinite(logit) && qn > 0.0;
-    if (!ok) {
-        a.status[i] = kInvalid;
+    Setup S;
+    const int st0 = setup_gaussian(a, i, S);
+    if (st0 != kVisible) {
+        a.status[i] = st0;
         return;
     }
-    // Eq. 1-3: activations and rotation
-    double s[3];
-    for (int k = 0; k < 3; ++k) s[k] = exp(ls[k]);
-    double alpha = 1.0 / (1.0 + exp(-logit));
-    double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-    double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
-                   2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
-                   2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
-    double muv[3];
-    for (int r = 0; r < 3; ++r) muv[r] = a.RV[3 * r] * mu[0] + a.RV[3 * r + 1] * mu[1] + a.RV[3 * r + 2] * mu[2] + a.tV[r];
-    // Sec. 3.2: filter variance k / v'^2, v = fx / max(z, znear), v' = min(v_train, v)
-    double dz = fmax(muv[2], a.cam.znear);
-    double v = a.cam.fx / dz;
-    if (a.v_train) v = fmin(v, (double)a.v_train[i]);
-    double fa = a.filter_mode == 1 ? 0.0 : a.filter_k / (v * v);
-    double s2[3], sh_[3], st[3];
-    for (int k = 0; k < 3; ++k) {
-        s2[k] = s[k] * s[k];
-        sh_[k] = s2[k] + fa;
-        st[k] = sqrt(sh_[k]);
-    }
-    double d[3] = {mu[0] - a.o[0], mu[1] - a.o[1], mu[2] - a.o[2]};
-    double dn = sqrt(dot3(d, d));
-    for (int k = 0; k < 3; ++k) d[k] /= dn;
-    double alpha_t;
-    if (a.filter_mode == 1) {
-        alpha_t = alpha;
-    } else if (a.filter_mode == 2) {
-        alpha_t = alpha * sqrt((s2[0] * s2[1] * s2[2]) / (sh_[0] * sh_[1] * sh_[2]));  // Eq. 8
-    } else {
-        double dp[3];  // d' = R^T d
-        for (int k = 0; k < 3; ++k) dp[k] = R[k] * d[0] + R[3 + k] * d[1] + R[6 + k] * d[2];
-        double p0 = dp[0] * dp[0], p1 = dp[1] * dp[1], p2 = dp[2] * dp[2];
-        double num = p0 * s2[1] * s2[2] + p1 * s2[0] * s2[2] + p2 * s2[0] * s2[1];
-        double den = p0 * sh_[1] * sh_[2] + p1 * sh_[0] * sh_[2] + p2 * sh_[0] * sh_[1];
-        alpha_t = alpha * sqrt(num / den);  // Eq. 12
-    }
-    if (!(alpha_t >= a.alpha_min)) {
-        a.status[i] = kLowOpacity;
-        return;
-    }
-    const double tau = 2.0 * log(alpha_t / a.alpha_min);
-    // M = R_V R S~ (normalised Gaussian space -> view); A = M^-1 = S~^-1 R^T R_V^T
-    double M[9], A[9];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) {
-            double acc = a.RV[3 * r] * R[c] + a.RV[3 * r + 1] * R[3 + c] + a.RV[3 * r + 2] * R[6 + c];
-            M[3 * r + c] = acc * st[c];
-            A[3 * c + r] = acc / st[c];
-        }
-    double og[3];  // camera centre (view origin) in normalised space: -A mu_v
-    for (int r = 0; r < 3; ++r) og[r] = -(A[3 * r] * muv[0] + A[3 * r + 1] * muv[1] + A[3 * r + 2] * muv[2]);
-    const double og2 = dot3(og, og);
+    const double *muv = S.muv, *M = S.M, *A = S.A, *og = S.og, *d = S.d;
+    const double alpha_t = S.alpha_t, tau = S.tau, og2 = S.og2;
     if (og2 < tau) {  // Sec. 3.3: camera inside the ellipsoid
         a.status[i] = kCamInside;
         return;

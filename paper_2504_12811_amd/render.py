@@ -59,6 +59,21 @@ def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+class Workspace:
+    """A 256-byte-aligned slice of device memory sized for one frame."""
+
+    def __init__(self, device, nbytes: int, max_pairs: int):
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.buf.data_ptr()) % 256
+        self.view = self.buf[off: off + nbytes]
+        self.nbytes = nbytes
+        self.max_pairs = max_pairs
+
+    @property
+    def ptr(self) -> int:
+        return self.view.data_ptr()
+
+
 class Rasterizer:
     """Owns a library context and a growable workspace on one device."""
 
@@ -67,8 +82,8 @@ class Rasterizer:
         ctx = C.c_void_p()
         L.check(L.lib().aaa_create(C.byref(ctx), int(device)))
         self._ctx = ctx
-        self._ws = None
-        self._ws_bytes = 0
+        self._ws: Optional[Workspace] = None
+        self.last_ws: Optional[Workspace] = None
         self.max_pairs = 0
         self.last_pairs = 0
 
@@ -80,47 +95,70 @@ class Rasterizer:
             pass
 
     # workspace --------------------------------------------------------
-    def _ensure_ws(self, sc: L.Scene, cam: L.Camera, st: L.Settings, max_pairs: int):
+    def workspace_bytes(self, sc: L.Scene, cam: L.Camera, st: L.Settings, max_pairs: int) -> int:
         need = C.c_size_t()
         L.check(L.lib().aaa_workspace_size(C.byref(sc), C.byref(cam), C.byref(st), max_pairs, C.byref(need)))
-        if self._ws is None or self._ws_bytes < need.value:
-            self._ws = None
-            torch.cuda.synchronize(self.device)
-            nbytes = int(need.value * 1.1) + 4096
-            buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-            off = (-buf.data_ptr()) % 256
-            self._ws_buf = buf
-            self._ws = buf[off: off + nbytes]
-            self._ws_bytes = nbytes
-        self.max_pairs = max_pairs
+        return int(need.value)
 
-    def workspace(self):
-        return self._ws.data_ptr(), self._ws_bytes, self.max_pairs
+    def _fit(self, ws: Optional[Workspace], sc, cam, st, max_pairs) -> Workspace:
+        need = self.workspace_bytes(sc, cam, st, max_pairs)
+        if ws is not None and ws.nbytes >= need:
+            ws.max_pairs = max_pairs
+            return ws
+        return Workspace(self.device, int(need * 1.1) + 4096, max_pairs)
 
     # forward ------------------------------------------------------------
     def render(self, scene: DeviceScene, cam, settings, stats: bool = False, timing: bool = False,
-               max_pairs: Optional[int] = None):
-        """Render one view; returns (rgb [3,H,W], T [H,W], Stats)."""
+               max_pairs: Optional[int] = None, ws: Optional[Workspace] = None, fresh_ws: bool = False):
+        """Render one view; returns (rgb [3,H,W], T [H,W], Stats).  Uses the
+        rasteriser's own workspace unless `ws` is given or `fresh_ws` asks for
+        a new one; the frame state stays in that workspace (`last_ws`), e.g.
+        for a later backward."""
         sc = scene.abi()
         c = L.make_camera(cam)
         st = L.make_settings(settings, (L.AAA_STATS if stats else 0) | (L.AAA_TIMING if timing else 0))
         H, W = int(cam.height), int(cam.width)
         rgb = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
         T = torch.empty((H, W), dtype=torch.float32, device=self.device)
-        mp = max_pairs or max(self.max_pairs, 8 * max(scene.n, 1), 1 << 16)
+        own = ws is None and not fresh_ws
+        cur = self._ws if own else ws
+        mp = max_pairs or max(cur.max_pairs if cur is not None else 0, self.max_pairs, 8 * max(scene.n, 1), 1 << 16)
         for _ in range(4):
-            self._ensure_ws(sc, c, st, mp)
+            new = self._fit(cur, sc, c, st, mp)
+            if new is not cur and cur is not None and own:
+                torch.cuda.current_stream(self.device).synchronize()
+            cur = new
+            if own:
+                self._ws = cur
             out = L.Stats()
-            rc = L.lib().aaa_render(self._ctx, C.byref(sc), C.byref(c), C.byref(st), self._ws.data_ptr(),
-                                    self._ws_bytes, mp, _stream_ptr(self.device), rgb.data_ptr(), T.data_ptr(),
-                                    C.byref(out))
+            rc = L.lib().aaa_render(self._ctx, C.byref(sc), C.byref(c), C.byref(st), cur.ptr, cur.nbytes, mp,
+                                    _stream_ptr(self.device), rgb.data_ptr(), T.data_ptr(), C.byref(out))
             if rc == L.AAA_ERR_PAIR_OVERFLOW:
                 mp = min(int(out.pairs * 1.25) + 1024, (1 << 32) - 1)
                 continue
             L.check(rc)
             self.last_pairs = int(out.pairs)
+            self.max_pairs = max(self.max_pairs, mp)
+            self.last_ws = cur
             return rgb, T, out
         raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
+
+    def backward(self, scene: DeviceScene, cam, settings, ws: Workspace, out_rgb: torch.Tensor,
+                 grad_rgb: torch.Tensor) -> dict:
+        """Gradients of sum(grad_rgb * rgb) for the frame held in `ws`."""
+        sc = scene.abi()
+        c = L.make_camera(cam)
+        st = L.make_settings(settings)
+        grads = {k: torch.zeros_like(t) for k, t in zip(["means", "log_scales", "quats", "opacity_logits", "sh"],
+                                                        scene.tensors())}
+        g = L.SceneGrad()
+        g.means, g.log_scales, g.quats = grads["means"].data_ptr(), grads["log_scales"].data_ptr(), grads["quats"].data_ptr()
+        g.opacity_logits, g.sh = grads["opacity_logits"].data_ptr(), grads["sh"].data_ptr()
+        gr = grad_rgb.contiguous().float()
+        L.check(L.lib().aaa_render_backward(self._ctx, C.byref(sc), C.byref(c), C.byref(st), ws.ptr, ws.nbytes,
+                                            ws.max_pairs, _stream_ptr(self.device), out_rgb.data_ptr(), gr.data_ptr(),
+                                            C.byref(g)))
+        return grads
 
     def stage_times(self, reset: bool = True):
         """(dict stage -> accumulated ms, frames) of the renders made with timing=True."""
@@ -137,8 +175,9 @@ class Rasterizer:
         tau = torch.empty(n, dtype=torch.float32, device=dev)
         color = torch.empty((3, n), dtype=torch.float32, device=dev)
         rect = torch.empty((4, n), dtype=torch.int32, device=dev)
-        L.check(L.lib().aaa_read_gaussians(C.byref(scene.abi()), C.byref(L.make_camera(cam)), self.max_pairs,
-                                           self._ws.data_ptr(), self._ws_bytes, _stream_ptr(dev), status.data_ptr(),
+        ws = self.last_ws
+        L.check(L.lib().aaa_read_gaussians(C.byref(scene.abi()), C.byref(L.make_camera(cam)), ws.max_pairs,
+                                           ws.ptr, ws.nbytes, _stream_ptr(dev), status.data_ptr(),
                                            alpha_t.data_ptr(), tau.data_ptr(), color.data_ptr(), rect.data_ptr()))
         return dict(status=status, alpha_t=alpha_t, tau=tau, color=color, rect=rect)
 
@@ -150,8 +189,9 @@ class Rasterizer:
         tx, ty = (int(cam.width) + 15) // 16, (int(cam.height) + 15) // 16
         ranges = torch.empty((tx * ty, 2), dtype=torch.int32, device=dev)
         n = C.c_uint64()
-        L.check(L.lib().aaa_read_pairs(C.byref(scene.abi()), C.byref(L.make_camera(cam)), self.max_pairs,
-                                       self._ws.data_ptr(), self._ws_bytes, _stream_ptr(dev), keys.data_ptr(),
+        ws = self.last_ws
+        L.check(L.lib().aaa_read_pairs(C.byref(scene.abi()), C.byref(L.make_camera(cam)), ws.max_pairs,
+                                       ws.ptr, ws.nbytes, _stream_ptr(dev), keys.data_ptr(),
                                        vals.data_ptr(), ranges.data_ptr(), cap, C.byref(n)))
         P = int(n.value)
         return keys[:P], vals[:P], ranges
@@ -168,3 +208,30 @@ def sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int):
     L.check(L.lib().aaa_sort_pairs(keys.data_ptr(), vals.data_ptr(), n, int(key_bits), buf.data_ptr() + off,
                                    need.value, _stream_ptr(keys.device)))
     return keys, vals
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, v_train, cam, settings, ras):
+        scene = DeviceScene(means.detach().contiguous(), log_scales.detach().contiguous(), quats.detach().contiguous(),
+                            opacity_logits.detach().contiguous(), sh.detach().contiguous(),
+                            None if v_train is None else v_train.detach().contiguous())
+        # a workspace of its own, kept alive for the backward of this call
+        rgb, T, _ = ras.render(scene, cam, settings, fresh_ws=True)
+        ctx.scene, ctx.cam, ctx.settings, ctx.ras = scene, cam, settings, ras
+        ctx.ws = ras.last_ws
+        ctx.save_for_backward(rgb)
+        ctx.mark_non_differentiable(T)
+        return rgb, T
+
+    @staticmethod
+    def backward(ctx, grad_rgb, grad_T):
+        (rgb,) = ctx.saved_tensors
+        g = ctx.ras.backward(ctx.scene, ctx.cam, ctx.settings, ctx.ws, rgb, grad_rgb)
+        return g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None, None, None
+
+
+def render(means, log_scales, quats, opacity_logits, sh, cam, settings, ras: Rasterizer, v_train=None):
+    """Differentiable render of one view: returns (rgb [3,H,W], T [H,W]).
+    Gradients flow to means, log_scales, quats, opacity_logits and sh."""
+    return _RenderFn.apply(means, log_scales, quats, opacity_logits, sh, v_train, cam, settings, ras)
