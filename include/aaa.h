@@ -164,6 +164,28 @@ int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *
                         void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
                         const float *dL_drgb, aaa_scene_grad *grad);
 
+/* ---- batches of views (serving, multi-view steps) ---------------------- */
+
+/* A batch renders n_views (1..256) views of the same resident scene in one
+ * sequence of launches: the per-Gaussian stages run over (Gaussian, view)
+ * items, the sort key carries a global tile index across views, and the
+ * blend covers every view's tiles.  Each view's image is bit-identical to
+ * rendering that view alone.  cams: host array [n_views]; out_rgb, out_T:
+ * host arrays of n_views DEVICE pointers.  n * n_views must be < 2^32.  The
+ * single-view calls above are the batch of one view. */
+int aaa_workspace_size_batch(const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                             const aaa_settings *settings, uint64_t max_pairs, size_t *bytes_out);
+int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                     const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream,
+                     float *const *out_rgb, float *const *out_T, aaa_stats *stats);
+/* Backward of the last aaa_render_batch into `ws`: the gradient of
+ * sum_v sum(dL_drgb[v] * out_rgb[v]) accumulated (+=) into `grad`
+ * (a multi-view training step).  Synchronises `stream` before returning. */
+int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                              const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                              void *stream, const float *const *out_rgb, const float *const *dL_drgb,
+                              aaa_scene_grad *grad);
+
 /* Accumulated stage times (milliseconds, HIP events on the render stream) of
  * every aaa_render with AAA_TIMING since the last reset, and the number of
  * such frames.  Waits for the last timed frame to finish.  ms [AAA_NUM_STAGES]

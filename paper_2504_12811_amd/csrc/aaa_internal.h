@@ -55,6 +55,20 @@ struct CamDev {
     double znear;
 };
 
+// One view of a batch (device memory).  Items of the per-Gaussian stages are
+// indexed i * nviews + v; tiles of view v are tile_base + ty * tiles_x + tx in
+// the global tile numbering shared by the sort and the ranges.
+struct ViewDev {
+    double RV[9], tV[3], o[3];  // world->view rotation, translation, camera centre
+    CamDev cam;
+    int32_t tile_base;
+    int32_t _pad;
+    int64_t pix_base;            // offset of the view's pixels in the per-pixel scratch
+    float bg[3];
+    float *out_rgb, *out_T;      // [3][H][W], [H][W]
+    const float *dL_drgb;        // backward only
+};
+
 template <typename T>
 __device__ __forceinline__ T dot3(const T *a, const T *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
@@ -179,11 +193,11 @@ struct PreArgs {
     const float *means, *log_scales, *quats, *logits, *sh, *v_train;
     int64_t n;
     int sh_degree;
-    double RV[9], tV[3], o[3];
-    CamDev cam;
+    const ViewDev *views;
+    int nviews;
     double filter_k, alpha_min, alpha_max;
     int filter_mode;  // 0 adaptive, 1 off, 2 volume
-    int32_t *status;
+    int32_t *status;  // per item
     int4 *rect;
     float4 *rec;
     float4 *cull;
@@ -191,10 +205,11 @@ struct PreArgs {
 hipError_t launch_preprocess(const PreArgs &a, hipStream_t s);
 
 hipError_t launch_count_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              CamDev cam, bool tile_cull, uint32_t *counts, unsigned long long *tests, hipStream_t s);
+                              const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
+                              unsigned long long *tests, hipStream_t s);
 hipError_t launch_write_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              CamDev cam, bool tile_cull, const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys,
-                              uint32_t *vals, hipStream_t s);
+                              const ViewDev *views, int nviews, bool tile_cull, const uint64_t *offsets,
+                              uint64_t max_pairs, uint64_t *keys, uint32_t *vals, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s);
 
@@ -204,18 +219,16 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
 
 struct BlendArgs {
-    const float4 *rec;
-    const uint64_t *keys;
+    const float4 *rec;             // per item (i * nviews + v)
     const uint32_t *vals;
-    const uint32_t *ranges;
-    CamDev cam;
-    float alpha_min, alpha_max, t_min, znear;
-    float bg[3];
-    float *out_rgb, *out_T;        // forward: written; backward: out_rgb read (C_out)
-    uint32_t *n_done;  // per pixel: list entries consumed
+    const uint32_t *ranges;        // per global tile
+    const ViewDev *views;
+    int nviews;
+    int total_tiles;
+    float alpha_min, alpha_max, t_min;
+    uint32_t *n_done;              // per pixel (view pix_base + y * W + x): list entries consumed
     unsigned long long *counters;  // [0] evaluations, [1] contributors, [2] prefilter passes
-    const float *dL_drgb;          // backward only
-    float *grad_rec;               // backward only: [n][kGradStride]
+    float *grad_rec;               // backward only: per item, kGradStride floats
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool bwd, hipStream_t s);
 

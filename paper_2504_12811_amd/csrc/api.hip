@@ -1,17 +1,21 @@
-// Host side of the C ABI: argument checks, workspace layout and the launch
-// sequence preprocess -> pair count -> scan -> pair write -> radix sort ->
-// tile ranges -> blend (and the backward pair of kernels).
+// Host side of the C ABI: argument checks, the view table, the workspace
+// layout and the launch sequence preprocess -> pair count -> scan -> pair
+// write -> radix sort -> tile ranges -> blend (and the backward pair of
+// kernels).  A single-view render is the batch of one view.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "aaa_internal.h"
 #include "../../include/aaa.h"
 
 namespace {
+
+constexpr int kMaxViews = 256;
 
 thread_local std::string g_err;
 
@@ -27,18 +31,13 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
+#define HIP_TRY(expr)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
         if (e_ != hipSuccess) return fail(AAA_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-struct Layout {
-    size_t hdr, status, rect, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp, ranges,
-        n_done, grad_rec, total;
-};
 
 int tiles_of(const aaa_camera *cam, int *tx, int *ty)
 {
@@ -47,41 +46,66 @@ int tiles_of(const aaa_camera *cam, int *tx, int *ty)
     return (*tx) * (*ty);
 }
 
-Layout layout(int64_t n, const aaa_camera *cam, uint64_t max_pairs)
+struct Shape {
+    int64_t n;
+    int nviews;
+    int64_t total_tiles;
+    int64_t total_pixels;
+};
+
+Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
+{
+    Shape sh;
+    sh.n = scene->n;
+    sh.nviews = nviews;
+    sh.total_tiles = 0;
+    sh.total_pixels = 0;
+    for (int v = 0; v < nviews; ++v) {
+        int tx, ty;
+        sh.total_tiles += tiles_of(&cams[v], &tx, &ty);
+        sh.total_pixels += (int64_t)cams[v].width * cams[v].height;
+    }
+    return sh;
+}
+
+struct Layout {
+    size_t hdr, views, status, rect, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+        ranges, n_done, grad_rec, total;
+};
+
+Layout layout(const Shape &sh, uint64_t max_pairs)
 {
     Layout L;
-    int tx, ty;
-    int ntiles = tiles_of(cam, &tx, &ty);
-    size_t pix = (size_t)cam->width * cam->height;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
         o = align256(o + bytes);
         return at;
     };
-    int64_t nn = n > 0 ? n : 1;
+    const int64_t items = sh.n * sh.nviews > 0 ? sh.n * sh.nviews : 1;
     L.hdr = take(256);
-    L.status = take(nn * 4);
-    L.rect = take(nn * 16);
-    L.rec = take(nn * 16 * aaa::kRecQuads);
-    L.cull = take(nn * 16 * aaa::kCullQuads);
-    L.counts = take(nn * 4);
-    L.offsets = take((nn + 1) * 8);
-    L.scan_tmp = take(aaa::scan_tmp_bytes(nn));
+    L.views = take(sizeof(aaa::ViewDev) * (size_t)(sh.nviews > 0 ? sh.nviews : 1));
+    L.status = take(items * 4);
+    L.rect = take(items * 16);
+    L.rec = take(items * 16 * aaa::kRecQuads);
+    L.cull = take(items * 16 * aaa::kCullQuads);
+    L.counts = take(items * 4);
+    L.offsets = take((items + 1) * 8);
+    L.scan_tmp = take(aaa::scan_tmp_bytes(items));
     uint64_t mp = max_pairs > 0 ? max_pairs : 1;
     L.keys = take(mp * 8);
     L.keys_alt = take(mp * 8);
     L.vals = take(mp * 4);
     L.vals_alt = take(mp * 4);
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
-    L.ranges = take((size_t)ntiles * 8);
-    L.n_done = take(pix * 4);
-    L.grad_rec = take(nn * 4 * aaa::kGradStride);
+    L.ranges = take((size_t)sh.total_tiles * 8);
+    L.n_done = take((size_t)sh.total_pixels * 4);
+    L.grad_rec = take(items * 4 * aaa::kGradStride);
     L.total = o;
     return L;
 }
 
-int key_bits(int ntiles)
+int key_bits(int64_t ntiles)
 {
     int b = 0;
     while ((1ll << b) < ntiles) ++b;
@@ -89,19 +113,34 @@ int key_bits(int ntiles)
 }
 
 // The sort runs ceil(bits/8) passes, ping-ponging between the two buffers.
-bool sorted_in_alt(int ntiles) { return ((key_bits(ntiles) + 7) / 8) % 2 == 1; }
+bool sorted_in_alt(int64_t ntiles) { return ((key_bits(ntiles) + 7) / 8) % 2 == 1; }
 
-int check_common(const aaa_scene *sc, const aaa_camera *cam, const aaa_settings *st)
+int check_camera(const aaa_camera *cam)
 {
-    if (!sc || !cam || !st) return fail(AAA_ERR_INVALID, "null scene/camera/settings");
-    if (sc->n < 0 || sc->n >= (1ll << 32)) return fail(AAA_ERR_INVALID, "scene size %lld out of range", (long long)sc->n);
-    if (sc->sh_degree < 0 || sc->sh_degree > 3) return fail(AAA_ERR_UNSUPPORTED, "sh_degree %d not in 0..3", sc->sh_degree);
-    if (sc->n > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
-        return fail(AAA_ERR_INVALID, "null scene array");
     if (cam->width <= 0 || cam->height <= 0 || cam->width > 32768 || cam->height > 32768)
         return fail(AAA_ERR_INVALID, "image size %dx%d out of range", cam->width, cam->height);
     if (!(cam->fx > 0) || !(cam->fy > 0) || !(cam->znear > 0))
         return fail(AAA_ERR_INVALID, "focal lengths and znear must be positive");
+    return AAA_OK;
+}
+
+int check_common(const aaa_scene *sc, int nviews, const aaa_camera *cams, const aaa_settings *st)
+{
+    if (!sc || !cams || !st) return fail(AAA_ERR_INVALID, "null scene/camera/settings");
+    if (nviews < 1 || nviews > kMaxViews) return fail(AAA_ERR_INVALID, "n_views %d not in 1..%d", nviews, kMaxViews);
+    if (sc->n < 0 || sc->n * (int64_t)nviews >= (1ll << 32))
+        return fail(AAA_ERR_INVALID, "scene size %lld x %d views out of range", (long long)sc->n, nviews);
+    if (sc->sh_degree < 0 || sc->sh_degree > 3) return fail(AAA_ERR_UNSUPPORTED, "sh_degree %d not in 0..3", sc->sh_degree);
+    if (sc->n > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+        return fail(AAA_ERR_INVALID, "null scene array");
+    int64_t tiles = 0;
+    for (int v = 0; v < nviews; ++v) {
+        int rc = check_camera(&cams[v]);
+        if (rc) return rc;
+        int tx, ty;
+        tiles += tiles_of(&cams[v], &tx, &ty);
+    }
+    if (tiles >= (1ll << 30)) return fail(AAA_ERR_INVALID, "too many tiles in the batch");
     int K = st->ray_window;
     if (!(K == 0 || K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32))
         return fail(AAA_ERR_INVALID, "ray_window %d not one of 0,1,2,4,8,16,32", K);
@@ -126,11 +165,37 @@ aaa::CamDev cam_dev(const aaa_camera *cam)
     return c;
 }
 
+void fill_views(int nviews, const aaa_camera *cams, float *const *out_rgb, float *const *out_T,
+                const float *const *dL_drgb, aaa::ViewDev *vd)
+{
+    int32_t tile_base = 0;
+    int64_t pix_base = 0;
+    for (int v = 0; v < nviews; ++v) {
+        const aaa_camera *cam = &cams[v];
+        aaa::ViewDev &w = vd[v];
+        memset(&w, 0, sizeof w);
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) w.RV[3 * r + c] = cam->viewmat[4 * r + c];
+            w.tV[r] = cam->viewmat[4 * r + 3];
+        }
+        // camera centre o = -R_V^T t_V
+        for (int r = 0; r < 3; ++r) w.o[r] = -(w.RV[r] * w.tV[0] + w.RV[3 + r] * w.tV[1] + w.RV[6 + r] * w.tV[2]);
+        w.cam = cam_dev(cam);
+        w.tile_base = tile_base;
+        w.pix_base = pix_base;
+        for (int k = 0; k < 3; ++k) w.bg[k] = (float)cam->bg[k];
+        w.out_rgb = out_rgb ? out_rgb[v] : nullptr;
+        w.out_T = out_T ? out_T[v] : nullptr;
+        w.dL_drgb = dL_drgb ? dL_drgb[v] : nullptr;
+        tile_base += w.cam.tiles_x * w.cam.tiles_y;
+        pix_base += (int64_t)cam->width * cam->height;
+    }
+}
+
 template <typename T>
 T *at(void *ws, size_t off) { return (T *)((char *)ws + off); }
 
-aaa::PreArgs pre_args(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, void *ws,
-                      const Layout &L)
+aaa::PreArgs pre_args(const aaa_scene *scene, int nviews, const aaa_settings *settings, void *ws, const Layout &L)
 {
     aaa::PreArgs pa;
     pa.means = scene->means;
@@ -141,12 +206,8 @@ aaa::PreArgs pre_args(const aaa_scene *scene, const aaa_camera *cam, const aaa_s
     pa.v_train = scene->v_train;
     pa.n = scene->n;
     pa.sh_degree = scene->sh_degree;
-    for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c) pa.RV[3 * r + c] = cam->viewmat[4 * r + c];
-        pa.tV[r] = cam->viewmat[4 * r + 3];
-    }
-    for (int r = 0; r < 3; ++r) pa.o[r] = -(pa.RV[r] * pa.tV[0] + pa.RV[3 + r] * pa.tV[1] + pa.RV[6 + r] * pa.tV[2]);
-    pa.cam = cam_dev(cam);
+    pa.views = at<aaa::ViewDev>(ws, L.views);
+    pa.nviews = nviews;
     pa.filter_k = settings->filter_k;
     pa.alpha_min = settings->alpha_min;
     pa.alpha_max = settings->alpha_max;
@@ -162,6 +223,8 @@ aaa::PreArgs pre_args(const aaa_scene *scene, const aaa_camera *cam, const aaa_s
 
 struct aaa_ctx {
     int device;
+    // pinned staging for the view table (copied to the workspace per call)
+    aaa::ViewDev *views_host;
     // AAA_TIMING: two sets of stage events (frame i uses set i % 2); a set is
     // folded into the totals once a later frame has synchronised past it.
     static constexpr int kEvents = 9;
@@ -177,7 +240,6 @@ namespace {
 void fold_events(aaa_ctx *c, int set)
 {
     if (!c->pending[set]) return;
-    float ms[aaa_ctx::kEvents - 1];
     hipEvent_t *e = c->ev[set];
     // e0 start | preprocess | e1 | count | e2 | scan | e3 .. host wait .. e4 | write | e5 | sort | e6 | ranges | e7 | blend | e8
     const int a[AAA_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 0};
@@ -186,7 +248,6 @@ void fold_events(aaa_ctx *c, int set)
         float t = 0.f;
         if (hipEventElapsedTime(&t, e[a[k]], e[b[k]]) == hipSuccess) c->total_ms[k] += t;
     }
-    (void)ms;
     c->frames++;
     c->pending[set] = false;
 }
@@ -197,7 +258,7 @@ extern "C" {
 
 const char *aaa_last_error(void) { return g_err.c_str(); }
 
-const char *aaa_version(void) { return "aaa-gfx950 0.1"; }
+const char *aaa_version(void) { return "aaa-gfx950 0.2"; }
 
 int aaa_create(aaa_ctx **out, int device)
 {
@@ -208,11 +269,18 @@ int aaa_create(aaa_ctx **out, int device)
     HIP_TRY(hipSetDevice(device));
     aaa_ctx *c = new aaa_ctx;
     c->device = device;
+    c->views_host = nullptr;
+    hipError_t e = hipHostMalloc((void **)&c->views_host, sizeof(aaa::ViewDev) * kMaxViews, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(AAA_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
     for (int s_ = 0; s_ < 2; ++s_) {
         c->pending[s_] = false;
         for (int k = 0; k < aaa_ctx::kEvents; ++k) {
-            hipError_t e = hipEventCreate(&c->ev[s_][k]);
+            e = hipEventCreate(&c->ev[s_][k]);
             if (e != hipSuccess) {
+                (void)hipHostFree(c->views_host);
                 delete c;
                 return fail(AAA_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
             }
@@ -228,8 +296,10 @@ int aaa_create(aaa_ctx **out, int device)
 void aaa_destroy(aaa_ctx *ctx)
 {
     if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
     for (int s_ = 0; s_ < 2; ++s_)
         for (int k = 0; k < aaa_ctx::kEvents; ++k) (void)hipEventDestroy(ctx->ev[s_][k]);
+    (void)hipHostFree(ctx->views_host);
     delete ctx;
 }
 
@@ -251,34 +321,42 @@ int aaa_stage_times(aaa_ctx *ctx, double *ms, uint64_t *frames, int reset)
     return AAA_OK;
 }
 
-int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, uint64_t max_pairs,
-                       size_t *bytes_out)
+int aaa_workspace_size_batch(const aaa_scene *scene, int n_views, const aaa_camera *cams, const aaa_settings *settings,
+                             uint64_t max_pairs, size_t *bytes_out)
 {
-    int rc = check_common(scene, cam, settings);
+    int rc = check_common(scene, n_views, cams, settings);
     if (rc) return rc;
     if (!bytes_out) return fail(AAA_ERR_INVALID, "null bytes_out");
     if (max_pairs >= (1ull << 32)) return fail(AAA_ERR_INVALID, "max_pairs must be < 2^32");
-    *bytes_out = layout(scene->n, cam, max_pairs).total;
+    *bytes_out = layout(shape_of(scene, n_views, cams), max_pairs).total;
     return AAA_OK;
 }
 
-int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, void *ws,
-               size_t ws_bytes, uint64_t max_pairs, void *stream, float *out_rgb, float *out_T, aaa_stats *stats)
+int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, uint64_t max_pairs,
+                       size_t *bytes_out)
+{
+    return aaa_workspace_size_batch(scene, 1, cam, settings, max_pairs, bytes_out);
+}
+
+int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                     const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream,
+                     float *const *out_rgb, float *const *out_T, aaa_stats *stats)
 {
     if (!ctx) return fail(AAA_ERR_INVALID, "null context");
-    int rc = check_common(scene, cam, settings);
+    int rc = check_common(scene, n_views, cams, settings);
     if (rc) return rc;
     if (max_pairs >= (1ull << 32)) return fail(AAA_ERR_INVALID, "max_pairs must be < 2^32");
     if (!ws || !out_rgb || !out_T) return fail(AAA_ERR_INVALID, "null workspace or output");
+    for (int v = 0; v < n_views; ++v)
+        if (!out_rgb[v] || !out_T[v]) return fail(AAA_ERR_INVALID, "null output of view %d", v);
     if (((uintptr_t)ws & 255) != 0) return fail(AAA_ERR_INVALID, "workspace must be 256-byte aligned");
-    Layout L = layout(scene->n, cam, max_pairs);
+    const Shape sh = shape_of(scene, n_views, cams);
+    Layout L = layout(sh, max_pairs);
     if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(ctx->device));
     const int64_t n = scene->n;
-    int tx, ty;
-    const int ntiles = tiles_of(cam, &tx, &ty);
-    aaa::CamDev cd = cam_dev(cam);
+    const int64_t ntiles = sh.total_tiles;
     const bool want_stats = (settings->flags & AAA_STATS) != 0;
     unsigned long long *ctr = at<unsigned long long>(ws, L.hdr);  // [0] visible [1] tests [2] evals [3] contribs [4] near
     const bool timing = (settings->flags & AAA_TIMING) != 0;
@@ -291,21 +369,27 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     }
 #define STAGE_MARK(k) \
     do { if (timing) HIP_TRY(hipEventRecord(ev[k], s)); } while (0)
+    // view table: pinned staging -> workspace (the previous call's copy has
+    // completed: every call waits on its stream once before returning)
+    fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
+                           hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(ctr, 0, 64, s));
 
-    aaa::PreArgs pa = pre_args(scene, cam, settings, ws, L);
+    aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
     STAGE_MARK(1);
 
     const bool tile_cull = (settings->flags & AAA_NO_TILE_CULL) == 0;
+    const int64_t items = n * n_views;
     uint32_t *counts = at<uint32_t>(ws, L.counts);
     uint64_t *offsets = at<uint64_t>(ws, L.offsets);
-    HIP_TRY(aaa::launch_count_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, cd, tile_cull, counts, ctr, s));
+    HIP_TRY(aaa::launch_count_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, pa.views, n_views, tile_cull, counts, ctr, s));
     STAGE_MARK(2);
-    HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, n, at<void>(ws, L.scan_tmp), s));
+    HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, items, at<void>(ws, L.scan_tmp), s));
     STAGE_MARK(3);
     uint64_t P = 0;
-    HIP_TRY(hipMemcpyAsync(&P, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&P, offsets + items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -316,8 +400,8 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
     uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
     STAGE_MARK(4);
-    HIP_TRY(aaa::launch_write_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, cd, tile_cull, offsets, max_pairs, keys,
-                                    vals, s));
+    HIP_TRY(aaa::launch_write_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, pa.views, n_views, tile_cull, offsets,
+                                    max_pairs, keys, vals, s));
     STAGE_MARK(5);
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,
@@ -334,25 +418,21 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     }
     STAGE_MARK(6);
     uint32_t *ranges = at<uint32_t>(ws, L.ranges);
-    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, ntiles, s));
+    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)ntiles, s));
     STAGE_MARK(7);
 
     aaa::BlendArgs ba;
     ba.rec = pa.rec;
-    ba.keys = skeys;
     ba.vals = svals;
     ba.ranges = ranges;
-    ba.cam = cd;
+    ba.views = pa.views;
+    ba.nviews = n_views;
+    ba.total_tiles = (int)ntiles;
     ba.alpha_min = (float)settings->alpha_min;
     ba.alpha_max = (float)settings->alpha_max;
     ba.t_min = (float)settings->t_min;
-    ba.znear = (float)cam->znear;
-    for (int k = 0; k < 3; ++k) ba.bg[k] = (float)cam->bg[k];
-    ba.out_rgb = out_rgb;
-    ba.out_T = out_T;
     ba.n_done = at<uint32_t>(ws, L.n_done);
     ba.counters = ctr + 2;
-    ba.dL_drgb = nullptr;
     ba.grad_rec = nullptr;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, false, s));
     if (timing) {
@@ -374,12 +454,79 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     return AAA_OK;
 }
 
+int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings, void *ws,
+               size_t ws_bytes, uint64_t max_pairs, void *stream, float *out_rgb, float *out_T, aaa_stats *stats)
+{
+    return aaa_render_batch(ctx, scene, 1, cam, settings, ws, ws_bytes, max_pairs, stream, &out_rgb, &out_T, stats);
+}
+
+int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                              const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                              void *stream, const float *const *out_rgb, const float *const *dL_drgb,
+                              aaa_scene_grad *grad)
+{
+    if (!ctx) return fail(AAA_ERR_INVALID, "null context");
+    int rc = check_common(scene, n_views, cams, settings);
+    if (rc) return rc;
+    if (!ws || !out_rgb || !dL_drgb || !grad) return fail(AAA_ERR_INVALID, "null workspace, image or gradient");
+    for (int v = 0; v < n_views; ++v)
+        if (!out_rgb[v] || !dL_drgb[v]) return fail(AAA_ERR_INVALID, "null image or gradient of view %d", v);
+    const Shape sh = shape_of(scene, n_views, cams);
+    Layout L = layout(sh, max_pairs);
+    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t n = scene->n;
+    if (n == 0) return AAA_OK;
+    const int64_t ntiles = sh.total_tiles;
+    float *grad_rec = at<float>(ws, L.grad_rec);
+    HIP_TRY(hipMemsetAsync(grad_rec, 0, (size_t)n * n_views * 4 * aaa::kGradStride, s));
+    // the view table gains the backward's image and gradient pointers
+    fill_views(n_views, cams, const_cast<float *const *>(out_rgb), nullptr, dL_drgb, ctx->views_host);
+    HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
+                           hipMemcpyHostToDevice, s));
+    aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
+    const bool alt = sorted_in_alt(ntiles);
+    aaa::BlendArgs ba;
+    ba.rec = pa.rec;
+    ba.vals = at<uint32_t>(ws, alt ? L.vals_alt : L.vals);
+    ba.ranges = at<uint32_t>(ws, L.ranges);
+    ba.views = pa.views;
+    ba.nviews = n_views;
+    ba.total_tiles = (int)ntiles;
+    ba.alpha_min = (float)settings->alpha_min;
+    ba.alpha_max = (float)settings->alpha_max;
+    ba.t_min = (float)settings->t_min;
+    ba.n_done = at<uint32_t>(ws, L.n_done);
+    ba.counters = nullptr;
+    ba.grad_rec = grad_rec;
+    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));
+    aaa::GradOut go;
+    go.means = grad->means;
+    go.log_scales = grad->log_scales;
+    go.quats = grad->quats;
+    go.logits = grad->opacity_logits;
+    go.sh = grad->sh;
+    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, s));
+    // the pinned view table is reused by the next call on this context
+    HIP_TRY(hipStreamSynchronize(s));
+    return AAA_OK;
+}
+
+int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
+                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
+                        const float *dL_drgb, aaa_scene_grad *grad)
+{
+    return aaa_render_backward_batch(ctx, scene, 1, cam, settings, ws, ws_bytes, max_pairs, stream, &out_rgb, &dL_drgb,
+                                     grad);
+}
+
 int aaa_read_gaussians(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_pairs, const void *ws,
                        size_t ws_bytes, void *stream, int32_t *status, float *alpha_t, float *tau, float *color,
                        int32_t *rect)
 {
     if (!scene || !cam || !ws) return fail(AAA_ERR_INVALID, "null argument");
-    Layout L = layout(scene->n, cam, max_pairs);
+    Layout L = layout(shape_of(scene, 1, cam), max_pairs);
     if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = scene->n;
@@ -404,7 +551,8 @@ int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_p
                    void *stream, uint64_t *keys, uint32_t *values, uint32_t *ranges, uint64_t cap, uint64_t *n_pairs)
 {
     if (!scene || !cam || !ws || !n_pairs) return fail(AAA_ERR_INVALID, "null argument");
-    Layout L = layout(scene->n, cam, max_pairs);
+    const Shape sh = shape_of(scene, 1, cam);
+    Layout L = layout(sh, max_pairs);
     if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
     const char *w = (const char *)ws;
@@ -414,12 +562,10 @@ int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_p
     *n_pairs = P;
     if (P > max_pairs) return fail(AAA_ERR_PAIR_OVERFLOW, "last frame overflowed");
     if (P > cap) return fail(AAA_ERR_INVALID, "cap %llu < %llu pairs", (unsigned long long)cap, (unsigned long long)P);
-    int tx, ty;
-    int ntiles = tiles_of(cam, &tx, &ty);
-    bool alt = sorted_in_alt(ntiles);
+    const bool alt = sorted_in_alt(sh.total_tiles);
     if (keys && P) HIP_TRY(hipMemcpyAsync(keys, w + (alt ? L.keys_alt : L.keys), P * 8, hipMemcpyDeviceToDevice, s));
     if (values && P) HIP_TRY(hipMemcpyAsync(values, w + (alt ? L.vals_alt : L.vals), P * 4, hipMemcpyDeviceToDevice, s));
-    if (ranges) HIP_TRY(hipMemcpyAsync(ranges, w + L.ranges, (size_t)ntiles * 8, hipMemcpyDeviceToDevice, s));
+    if (ranges) HIP_TRY(hipMemcpyAsync(ranges, w + L.ranges, (size_t)sh.total_tiles * 8, hipMemcpyDeviceToDevice, s));
     return AAA_OK;
 }
 
@@ -452,54 +598,6 @@ int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits_, 
         HIP_TRY(hipMemcpyAsync(keys, ka, n * 8, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(values, va, n * 4, hipMemcpyDeviceToDevice, s));
     }
-    return AAA_OK;
-}
-
-int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
-                        void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
-                        const float *dL_drgb, aaa_scene_grad *grad)
-{
-    if (!ctx) return fail(AAA_ERR_INVALID, "null context");
-    int rc = check_common(scene, cam, settings);
-    if (rc) return rc;
-    if (!ws || !out_rgb || !dL_drgb || !grad) return fail(AAA_ERR_INVALID, "null workspace, image or gradient");
-    Layout L = layout(scene->n, cam, max_pairs);
-    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
-    hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipSetDevice(ctx->device));
-    const int64_t n = scene->n;
-    if (n == 0) return AAA_OK;
-    int tx, ty;
-    const int ntiles = tiles_of(cam, &tx, &ty);
-    float *grad_rec = at<float>(ws, L.grad_rec);
-    HIP_TRY(hipMemsetAsync(grad_rec, 0, (size_t)n * 4 * aaa::kGradStride, s));
-    aaa::PreArgs pa = pre_args(scene, cam, settings, ws, L);
-    const bool alt = sorted_in_alt(ntiles);
-    aaa::BlendArgs ba;
-    ba.rec = pa.rec;
-    ba.keys = at<uint64_t>(ws, alt ? L.keys_alt : L.keys);
-    ba.vals = at<uint32_t>(ws, alt ? L.vals_alt : L.vals);
-    ba.ranges = at<uint32_t>(ws, L.ranges);
-    ba.cam = cam_dev(cam);
-    ba.alpha_min = (float)settings->alpha_min;
-    ba.alpha_max = (float)settings->alpha_max;
-    ba.t_min = (float)settings->t_min;
-    ba.znear = (float)cam->znear;
-    for (int k = 0; k < 3; ++k) ba.bg[k] = (float)cam->bg[k];
-    ba.out_rgb = const_cast<float *>(out_rgb);
-    ba.out_T = nullptr;
-    ba.n_done = at<uint32_t>(ws, L.n_done);
-    ba.counters = nullptr;
-    ba.dL_drgb = dL_drgb;
-    ba.grad_rec = grad_rec;
-    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));
-    aaa::GradOut go;
-    go.means = grad->means;
-    go.log_scales = grad->log_scales;
-    go.quats = grad->quats;
-    go.logits = grad->opacity_logits;
-    go.sh = grad->sh;
-    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, s));
     return AAA_OK;
 }
 

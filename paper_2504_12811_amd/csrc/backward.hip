@@ -17,26 +17,21 @@ namespace {
 
 __device__ __forceinline__ void cross3(const double *a, const double *b, double *c) { cross3d(a, b, c); }
 
-__global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *__restrict__ grad_rec, GradOut go)
+// Adjoint of the preparation of Gaussian i for view v; adds into the
+// per-Gaussian sums (gsh_out is [(deg+1)^2][3], coefficient-major).
+__device__ void preprocess_bwd_item(const PreArgs &a, int64_t i, int v, const float *gv, double *gmu_out,
+                                    double *gls_out, double *gq_out, double &glogit_out, double *gsh_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n || a.status[i] != kVisible) return;
     const int64_t n = a.n;
-    const float *gr = grad_rec + (size_t)i * kGradStride;
-    float gv[22];
-    bool any = false;
-    for (int k = 0; k < 22; ++k) {
-        gv[k] = gr[k];
-        any |= gv[k] != 0.0f;
-    }
-    if (!any) return;
+    const ViewDev &vw = a.views[v];
+    const int64_t item = i * a.nviews + v;
     Setup S;
-    if (setup_gaussian(a, i, S) != kVisible) return;
+    if (setup_gaussian(a, i, vw, S) != kVisible) return;
     const double *A = S.A, *R = S.R, *muv = S.muv, *og = S.og, *d = S.d;
-    const float4 q5 = a.rec[(size_t)i * kRecQuads + 5];
+    const float4 q5 = a.rec[(size_t)item * kRecQuads + 5];
     const double xa = q5.y, ya = q5.z;
-    const double ua = (xa - a.cam.cx) / a.cam.fx, va = (ya - a.cam.cy) / a.cam.fy;
-    const double b[3][3] = {{ua, va, 1.0}, {1.0 / a.cam.fx, 0.0, 0.0}, {0.0, 1.0 / a.cam.fy, 0.0}};
+    const double ua = (xa - vw.cam.cx) / vw.cam.fx, va = (ya - vw.cam.cy) / vw.cam.fy;
+    const double b[3][3] = {{ua, va, 1.0}, {1.0 / vw.cam.fx, 0.0, 0.0}, {0.0, 1.0 / vw.cam.fy, 0.0}};
     double c[3][3];
     for (int j = 0; j < 3; ++j)
         for (int r = 0; r < 3; ++r) c[j][r] = A[3 * r] * b[j][0] + A[3 * r + 1] * b[j][1] + A[3 * r + 2] * b[j][2];
@@ -72,7 +67,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
         for (int col = 0; col < 3; ++col) {
             gst[r] -= gA[3 * r + col] * A[3 * r + col] / S.st[r];
             const double gB = gA[3 * r + col] / S.st[r];
-            for (int k = 0; k < 3; ++k) gR[3 * k + r] += gB * a.RV[3 * col + k];
+            for (int k = 0; k < 3; ++k) gR[3 * k + r] += gB * vw.RV[3 * col + k];
         }
 
     // alpha~ (Sec. 3.2)
@@ -114,7 +109,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
         gfa += gshat[k];
         gls[k] = 2.0 * S.s2[k] * gs2[k];
     }
-    if (S.fa_moves) gmuv[2] += gfa * 2.0 * a.filter_k * muv[2] / (a.cam.fx * a.cam.fx);
+    if (S.fa_moves) gmuv[2] += gfa * 2.0 * a.filter_k * muv[2] / (vw.cam.fx * vw.cam.fx);
     const double glogit = galpha * S.alpha * (1.0 - S.alpha);
 
     // colour: c = max(0, 0.5 + sum_b Y_b(d) sh_b)
@@ -129,7 +124,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
         if (!(acc > 0.0) || gcol == 0.0) continue;
         for (int k = 0; k < nb; ++k) {
             gY[k] += (double)a.sh[((int64_t)k * 3 + ch) * n + i] * gcol;
-            if (go.sh) go.sh[((int64_t)k * 3 + ch) * n + i] += (float)(Y[k] * gcol);
+            gsh_out[3 * k + ch] += Y[k] * gcol;
         }
     }
     double gdY[3];
@@ -141,7 +136,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
     const double dg = dot3(d, gd);
     for (int k = 0; k < 3; ++k) gmu[k] = (gd[k] - d[k] * dg) / S.dn;
     for (int k = 0; k < 3; ++k)
-        for (int r = 0; r < 3; ++r) gmu[k] += a.RV[3 * r + k] * gmuv[r];
+        for (int r = 0; r < 3; ++r) gmu[k] += vw.RV[3 * r + k] * gmuv[r];
 
     // rotation of the unit quaternion (w, x, y, z), then the normalisation
     const double w = S.qh[0], x = S.qh[1], y = S.qh[2], z = S.qh[3];
@@ -153,13 +148,51 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
     gq[3] = 2.0 * (-2.0 * z * g[0] - w * g[1] + x * g[2] + w * g[3] - 2.0 * z * g[4] + y * g[5] + x * g[6] + y * g[7]);
     const double qg = S.qh[0] * gq[0] + S.qh[1] * gq[1] + S.qh[2] * gq[2] + S.qh[3] * gq[3];
 
+    for (int k = 0; k < 3; ++k) {
+        gmu_out[k] += gmu[k];
+        gls_out[k] += gls[k];
+    }
+    for (int k = 0; k < 4; ++k) gq_out[k] += (gq[k] - S.qh[k] * qg) / S.qn;
+    glogit_out += glogit;
+}
+
+// One thread per Gaussian: sums the adjoint over the views of the batch and
+// adds it to the caller's gradient arrays (no atomics needed).
+__global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *__restrict__ grad_rec, GradOut go)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n;
+    double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
+    double gsh[48];
+    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    for (int k = 0; k < 3 * nb; ++k) gsh[k] = 0.0;
+    bool touched = false;
+    for (int v = 0; v < a.nviews; ++v) {
+        const int64_t item = i * a.nviews + v;
+        if (a.status[item] != kVisible) continue;
+        const float *gr = grad_rec + (size_t)item * kGradStride;
+        float gv[22];
+        bool any = false;
+        for (int k = 0; k < 22; ++k) {
+            gv[k] = gr[k];
+            any |= gv[k] != 0.0f;
+        }
+        if (!any) continue;
+        touched = true;
+        preprocess_bwd_item(a, i, v, gv, gmu, gls, gq, glogit, gsh);
+    }
+    if (!touched) return;
     if (go.means)
         for (int k = 0; k < 3; ++k) go.means[k * n + i] += (float)gmu[k];
     if (go.log_scales)
         for (int k = 0; k < 3; ++k) go.log_scales[k * n + i] += (float)gls[k];
     if (go.quats)
-        for (int k = 0; k < 4; ++k) go.quats[k * n + i] += (float)((gq[k] - S.qh[k] * qg) / S.qn);
+        for (int k = 0; k < 4; ++k) go.quats[k * n + i] += (float)gq[k];
     if (go.logits) go.logits[i] += (float)glogit;
+    if (go.sh)
+        for (int k = 0; k < nb; ++k)
+            for (int ch = 0; ch < 3; ++ch) go.sh[((int64_t)k * 3 + ch) * n + i] += (float)gsh[3 * k + ch];
 }
 
 }  // namespace

@@ -155,21 +155,26 @@ __device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__rest
 template <int K, bool STATS, bool BWD>
 __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
 {
-    const int ntiles = a.cam.tiles_x * a.cam.tiles_y;
+    const int ntiles = a.total_tiles;
     // XCD-aware order: consecutive workgroups land on different XCDs, so hand
     // each XCD a contiguous band of tiles (neighbouring tiles share records).
     const int per = (ntiles + 7) / 8;
     const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
     if (tile >= ntiles) return;
-    const int tx = tile % a.cam.tiles_x, ty = tile / a.cam.tiles_x;
+    int v = 0;  // the view owning this tile (views are ordered by tile_base)
+    while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
+    const ViewDev &vw = a.views[v];
+    const int nv = a.nviews;
+    const int lt = tile - vw.tile_base;
+    const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
-    const bool inside = px < a.cam.width && py < a.cam.height;
+    const bool inside = px < vw.cam.width && py < vw.cam.height;
     const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    const size_t hw = (size_t)a.cam.width * a.cam.height;
-    const size_t pix = inside ? (size_t)py * a.cam.width + px : 0;
+    const size_t hw = (size_t)vw.cam.width * vw.cam.height;
+    const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
 
     float wz[K > 0 ? K : 1];
     uint32_t wid[K > 0 ? K : 1];
@@ -189,16 +194,16 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     bp.fy = fyp;
     for (int c = 0; c < 3; ++c) {
         bp.A[c] = 0.0f;
-        bp.Cout[c] = (BWD && inside) ? a.out_rgb[c * hw + pix] : 0.0f;
-        bp.g[c] = (BWD && inside) ? a.dL_drgb[c * hw + pix] : 0.0f;
+        bp.Cout[c] = (BWD && inside) ? vw.out_rgb[c * hw + pix] : 0.0f;
+        bp.g[c] = (BWD && inside) ? vw.dL_drgb[c * hw + pix] : 0.0f;
     }
     uint32_t consumed = 0;
     uint32_t n_eval = 0, n_contrib = 0, n_near = 0;
-    const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = a.znear;
+    const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
 
     for (uint32_t i = start; i < end; ++i) {
         if (__ballot(!ps.done) == 0ull) break;
-        const uint32_t id = a.vals[i];
+        const uint32_t id = a.vals[i] * (uint32_t)nv + (uint32_t)v;  // item of (Gaussian, view)
         const float4 *r = a.rec + (size_t)id * kRecQuads;
         const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
         if (STATS && !ps.done) ++n_eval;
@@ -250,11 +255,11 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     }
     if (draining) consumed = end - start;
     if (!BWD && inside) {
-        a.out_rgb[pix] = ps.C[0] + ps.T * a.bg[0];
-        a.out_rgb[hw + pix] = ps.C[1] + ps.T * a.bg[1];
-        a.out_rgb[2 * hw + pix] = ps.C[2] + ps.T * a.bg[2];
-        a.out_T[pix] = ps.T;
-        a.n_done[pix] = consumed;
+        vw.out_rgb[pix] = ps.C[0] + ps.T * vw.bg[0];
+        vw.out_rgb[hw + pix] = ps.C[1] + ps.T * vw.bg[1];
+        vw.out_rgb[2 * hw + pix] = ps.C[2] + ps.T * vw.bg[2];
+        vw.out_T[pix] = ps.T;
+        a.n_done[vw.pix_base + pix] = consumed;
     }
     if (STATS) {
         unsigned long long e = n_eval, c = n_contrib, nr = n_near;
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
 template <int K>
 hipError_t launch_k(const BlendArgs &a, bool stats, bool bwd, hipStream_t s)
 {
-    const int ntiles = a.cam.tiles_x * a.cam.tiles_y;
+    const int ntiles = a.total_tiles;
     const int per = (ntiles + 7) / 8;
     dim3 grid((unsigned)(per * 8));
     if (bwd)
@@ -290,7 +295,7 @@ hipError_t launch_k(const BlendArgs &a, bool stats, bool bwd, hipStream_t s)
 
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool bwd, hipStream_t s)
 {
-    if (a.cam.tiles_x * a.cam.tiles_y <= 0) return hipSuccess;
+    if (a.total_tiles <= 0) return hipSuccess;
     switch (K) {
     case 0: return launch_k<0>(a, stats, bwd, s);
     case 1: return launch_k<1>(a, stats, bwd, s);

@@ -42,15 +42,19 @@ __device__ __forceinline__ uint64_t lane_mask_lt()
 }
 
 // Pass 1 (count) and pass 2 (write) share one body.
+// Items are (Gaussian, view) pairs, item = i * nviews + v; pairs are emitted
+// in item order, so within a view they come in Gaussian order.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_pairs(const int32_t *__restrict__ status, const int4 *__restrict__ rects,
                                                const float4 *__restrict__ recs, const float4 *__restrict__ culls,
-                                               int64_t n, CamDev cam, bool tile_cull, uint32_t *__restrict__ counts,
+                                               int64_t nitems, const ViewDev *__restrict__ views, int nviews,
+                                               bool tile_cull, uint32_t *__restrict__ counts,
                                                unsigned long long *__restrict__ tests, const uint64_t *__restrict__ offsets,
                                                uint64_t max_pairs, uint64_t *__restrict__ keys,
                                                uint32_t *__restrict__ vals)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = nitems;
     const bool live = i < n && status[i] == kVisible;
     int4 rc = live ? rects[i] : make_int4(0, 0, 0, 0);
     const int rw = rc.y - rc.x, rh = rc.w - rc.z;
@@ -62,6 +66,8 @@ __global__ __launch_bounds__(256) void k_pairs(const int32_t *__restrict__ statu
     unsigned long long ntests = 0;
     // small rectangles: one lane each
     if (live && !big) {
+        const ViewDev &vw = views[i % nviews];
+        const CamDev &cam = vw.cam;
         TileGeom<float> g;
         load_tile_geom(recs + (size_t)i * kRecQuads, culls + (size_t)i * kCullQuads, g);
         const float tau = recs[(size_t)i * kRecQuads + 6].y;
@@ -72,9 +78,9 @@ __global__ __launch_bounds__(256) void k_pairs(const int32_t *__restrict__ statu
                     if (WRITE) {
                         uint64_t slot = base + my_count;
                         if (slot < max_pairs) {
-                            uint32_t tile = (uint32_t)(ty * cam.tiles_x + tx);
+                            uint32_t tile = (uint32_t)(vw.tile_base + ty * cam.tiles_x + tx);
                             keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(g, tx, ty));
-                            vals[slot] = (uint32_t)i;
+                            vals[slot] = (uint32_t)(i / nviews);
                         }
                     }
                     ++my_count;
@@ -90,6 +96,8 @@ __global__ __launch_bounds__(256) void k_pairs(const int32_t *__restrict__ statu
         const int64_t j = __shfl(i, src);
         const int4 r = make_int4(__shfl(rc.x, src), __shfl(rc.y, src), __shfl(rc.z, src), __shfl(rc.w, src));
         const uint64_t jbase = WRITE ? (uint64_t)__shfl((long long)base, src) : 0ull;
+        const ViewDev &vw = views[j % nviews];
+        const CamDev &cam = vw.cam;
         TileGeom<float> g;
         load_tile_geom(recs + (size_t)j * kRecQuads, culls + (size_t)j * kCullQuads, g);
         const float tau = recs[(size_t)j * kRecQuads + 6].y;
@@ -110,9 +118,9 @@ __global__ __launch_bounds__(256) void k_pairs(const int32_t *__restrict__ statu
             if (WRITE && keep) {
                 uint64_t slot = jbase + running + __popcll(m & lane_mask_lt());
                 if (slot < max_pairs) {
-                    uint32_t tile = (uint32_t)(ty * cam.tiles_x + tx);
+                    uint32_t tile = (uint32_t)(vw.tile_base + ty * cam.tiles_x + tx);
                     keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(g, tx, ty));
-                    vals[slot] = (uint32_t)j;
+                    vals[slot] = (uint32_t)(j / nviews);
                 }
             }
             running += (uint32_t)__popcll(m);
@@ -219,23 +227,26 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 }  // namespace
 
 hipError_t launch_count_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              CamDev cam, bool tile_cull, uint32_t *counts, unsigned long long *tests, hipStream_t s)
+                              const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
+                              unsigned long long *tests, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, status, rect, rec, cull, n,
-                       cam, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0, (uint64_t *)nullptr,
-                       (uint32_t *)nullptr);
+    const int64_t items = n * nviews;
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, status, rect, rec, cull,
+                       items, views, nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0,
+                       (uint64_t *)nullptr, (uint32_t *)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_write_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              CamDev cam, bool tile_cull, const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys,
-                              uint32_t *vals, hipStream_t s)
+                              const ViewDev *views, int nviews, bool tile_cull, const uint64_t *offsets,
+                              uint64_t max_pairs, uint64_t *keys, uint32_t *vals, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, status, rect, rec, cull, n,
-                       cam, tile_cull, (uint32_t *)nullptr, (unsigned long long *)nullptr, offsets, max_pairs, keys,
-                       vals);
+    const int64_t items = n * nviews;
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, status, rect, rec, cull,
+                       items, views, nviews, tile_cull, (uint32_t *)nullptr, (unsigned long long *)nullptr, offsets,
+                       max_pairs, keys, vals);
     return hipGetLastError();
 }
 

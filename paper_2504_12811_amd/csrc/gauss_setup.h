@@ -91,7 +91,7 @@ struct Setup {
 // Sec. 3.1 Eq. 1-3 activations, Sec. 3.2 filter (Eq. 6-13), tau, and the
 // maps between normalised Gaussian space and view space.  Returns kInvalid,
 // kLowOpacity or kVisible (later culls are the caller's).
-__device__ __forceinline__ int setup_gaussian(const PreArgs &a, int64_t i, Setup &G)
+__device__ __forceinline__ int setup_gaussian(const PreArgs &a, int64_t i, const ViewDev &vw, Setup &G)
 {
     const int64_t n = a.n;
     double ls[3], q[4];
@@ -118,11 +118,11 @@ __device__ __forceinline__ int setup_gaussian(const PreArgs &a, int64_t i, Setup
     R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
     R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
     for (int r = 0; r < 3; ++r)
-        G.muv[r] = a.RV[3 * r] * G.mu[0] + a.RV[3 * r + 1] * G.mu[1] + a.RV[3 * r + 2] * G.mu[2] + a.tV[r];
+        G.muv[r] = vw.RV[3 * r] * G.mu[0] + vw.RV[3 * r + 1] * G.mu[1] + vw.RV[3 * r + 2] * G.mu[2] + vw.tV[r];
     // filter variance k / v'^2 with v = fx / max(z, znear), v' = min(v_train, v)
-    G.dz = fmax(G.muv[2], a.cam.znear);
-    G.v = a.cam.fx / G.dz;
-    G.fa_moves = a.filter_mode != 1 && G.muv[2] > a.cam.znear;
+    G.dz = fmax(G.muv[2], vw.cam.znear);
+    G.v = vw.cam.fx / G.dz;
+    G.fa_moves = a.filter_mode != 1 && G.muv[2] > vw.cam.znear;
     if (a.v_train) {
         double vt = (double)a.v_train[i];
         if (vt < G.v) {
@@ -136,7 +136,7 @@ __device__ __forceinline__ int setup_gaussian(const PreArgs &a, int64_t i, Setup
         G.shat[k] = G.s2[k] + G.fa;
         G.st[k] = sqrt(G.shat[k]);
     }
-    for (int k = 0; k < 3; ++k) G.d[k] = G.mu[k] - a.o[k];
+    for (int k = 0; k < 3; ++k) G.d[k] = G.mu[k] - vw.o[k];
     G.dn = sqrt(dot3(G.d, G.d));
     for (int k = 0; k < 3; ++k) G.d[k] /= G.dn;
     for (int k = 0; k < 3; ++k) G.dp[k] = R[k] * G.d[0] + R[3 + k] * G.d[1] + R[6 + k] * G.d[2];
@@ -155,7 +155,7 @@ __device__ __forceinline__ int setup_gaussian(const PreArgs &a, int64_t i, Setup
     // M = R_V R S~ (normalised Gaussian space -> view); A = M^-1 = S~^-1 R^T R_V^T
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) {
-            double acc = a.RV[3 * r] * R[c] + a.RV[3 * r + 1] * R[3 + c] + a.RV[3 * r + 2] * R[6 + c];
+            double acc = vw.RV[3 * r] * R[c] + vw.RV[3 * r + 1] * R[3 + c] + vw.RV[3 * r + 2] * R[6 + c];
             G.M[3 * r + c] = acc * G.st[c];
             G.A[3 * c + r] = acc / G.st[c];
         }

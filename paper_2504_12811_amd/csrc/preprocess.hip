@@ -62,32 +62,38 @@ __device__ bool view_bounds(const double *Ma, const double *Mc, double ma, doubl
     return true;
 }
 
+// One thread per item (Gaussian i, view v), item = i * nviews + v: the
+// threads of a Gaussian's views are adjacent, so its parameters are fetched
+// from HBM once per batch.
 __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= a.n * a.nviews) return;
+    const int64_t i = item / a.nviews;
+    const int v = (int)(item - i * a.nviews);
+    const ViewDev &vw = a.views[v];
     const int64_t n = a.n;
-    a.rect[i] = make_int4(0, 0, 0, 0);
+    a.rect[item] = make_int4(0, 0, 0, 0);
     Setup S;
-    const int st0 = setup_gaussian(a, i, S);
+    const int st0 = setup_gaussian(a, i, vw, S);
     if (st0 != kVisible) {
-        a.status[i] = st0;
+        a.status[item] = st0;
         return;
     }
     const double *muv = S.muv, *M = S.M, *A = S.A, *og = S.og, *d = S.d;
     const double alpha_t = S.alpha_t, tau = S.tau, og2 = S.og2;
     if (og2 < tau) {  // Sec. 3.3: camera inside the ellipsoid
-        a.status[i] = kCamInside;
+        a.status[item] = kCamInside;
         return;
     }
     // Sec. 3.3 bounds in the x-z and y-z view planes
-    const CamDev &cam = a.cam;
+    const CamDev &cam = vw.cam;
     double tx_lo, tx_hi, ty_lo, ty_hi;
     bool fullx, fully;
     bool okx = view_bounds(&M[0], &M[6], muv[0], muv[2], tau, tx_lo, tx_hi, fullx);
     bool oky = view_bounds(&M[3], &M[6], muv[1], muv[2], tau, ty_lo, ty_hi, fully);
     if (!okx || !oky) {
-        a.status[i] = kOutside;
+        a.status[item] = kOutside;
         return;
     }
     int x0 = 0, x1 = cam.tiles_x, y0 = 0, y1 = cam.tiles_y;
@@ -102,7 +108,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
         y1 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_hi / kTile) + 1.0));
     }
     if (x0 >= x1 || y0 >= y1) {
-        a.status[i] = kOutside;
+        a.status[item] = kOutside;
         return;
     }
     // anchor: the pixel centre nearest the projected mean, kept inside the
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     // Sec. 3.4: cull against the whole view frustum
     double mview = tile_min_rho2<double>(g, 0.0, (double)cam.width, 0.0, (double)cam.height, cam);
     if (!(mview < tau)) {
-        a.status[i] = kOutside;
+        a.status[item] = kOutside;
         return;
     }
     // colour from real SH along the camera->mean direction
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
         for (int b = 0; b < nb; ++b) acc += Y[b] * (double)a.sh[((int64_t)b * 3 + ch) * n + i];
         col[ch] = (float)fmax(acc, 0.0);
     }
-    float4 *rec = a.rec + (size_t)i * kRecQuads;
+    float4 *rec = a.rec + (size_t)item * kRecQuads;
     rec[0] = make_float4(g.c0[0], g.c0[1], g.c0[2], g.c1[0]);
     rec[1] = make_float4(g.c1[1], g.c1[2], g.c2[0], g.c2[1]);
     rec[2] = make_float4(g.c2[2], g.w0[0], g.w0[1], g.w0[2]);
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     // evaluation the exact alpha test would accept
     rec[6] = make_float4((float)(tau * (1.0 + 1e-4) + 1e-6), (float)tau, (float)og2, 0.f);
     rec[7] = make_float4(col[0], col[1], col[2], 0.f);
-    float4 *cu = a.cull + (size_t)i * kCullQuads;
+    float4 *cu = a.cull + (size_t)item * kCullQuads;
     cu[0] = make_float4(g.dx0, g.dx1, g.dy0, g.dy1);
     cu[1] = make_float4(g.nx0[0], g.nx0[1], g.nx0[2], g.nx1[0]);
     cu[2] = make_float4(g.nx1[1], g.nx1[2], g.ny0[0], g.ny0[1]);
@@ -195,16 +201,16 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     cu[5] = make_float4(g.qx1[1], g.qx1[2], g.qy0[0], g.qy0[1]);
     cu[6] = make_float4(g.qy0[2], g.qy1[0], g.qy1[1], g.qy1[2]);
     cu[7] = make_float4(muv[0], muv[1], muv[2], 0.f);
-    a.rect[i] = make_int4(x0, x1, y0, y1);
-    a.status[i] = kVisible;
+    a.rect[item] = make_int4(x0, x1, y0, y1);
+    a.status[item] = kVisible;
 }
 
 }  // namespace
 
 hipError_t launch_preprocess(const PreArgs &a, hipStream_t s)
 {
-    if (a.n <= 0) return hipSuccess;
-    int64_t blocks = (a.n + 255) / 256;
+    if (a.n <= 0 || a.nviews <= 0) return hipSuccess;
+    int64_t blocks = (a.n * a.nviews + 255) / 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

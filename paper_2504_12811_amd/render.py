@@ -143,6 +143,63 @@ class Rasterizer:
             return rgb, T, out
         raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
 
+    def render_batch(self, scene: DeviceScene, cams, settings, stats: bool = False, max_pairs: Optional[int] = None,
+                     fresh_ws: bool = False):
+        """Render several views of one scene in one launch sequence; returns
+        ([rgb_v], [T_v], Stats).  Each view equals its single-view render."""
+        sc = scene.abi()
+        V = len(cams)
+        carr = (L.Camera * V)(*[L.make_camera(c) for c in cams])
+        st = L.make_settings(settings, L.AAA_STATS if stats else 0)
+        rgbs = [torch.empty((3, int(c.height), int(c.width)), dtype=torch.float32, device=self.device) for c in cams]
+        Ts = [torch.empty((int(c.height), int(c.width)), dtype=torch.float32, device=self.device) for c in cams]
+        prgb = (C.c_void_p * V)(*[t.data_ptr() for t in rgbs])
+        pT = (C.c_void_p * V)(*[t.data_ptr() for t in Ts])
+        own = not fresh_ws
+        cur = self._ws if own else None
+        npix = sum(int(c.width) * int(c.height) for c in cams)
+        mp = max_pairs or max(self.max_pairs, 2 * npix, 1 << 16)
+        for _ in range(4):
+            need = C.c_size_t()
+            L.check(L.lib().aaa_workspace_size_batch(C.byref(sc), V, carr, C.byref(st), mp, C.byref(need)))
+            if cur is None or cur.nbytes < need.value:
+                if cur is not None and own:
+                    torch.cuda.current_stream(self.device).synchronize()
+                cur = Workspace(self.device, int(need.value * 1.1) + 4096, mp)
+            cur.max_pairs = mp
+            if own:
+                self._ws = cur
+            out = L.Stats()
+            rc = L.lib().aaa_render_batch(self._ctx, C.byref(sc), V, carr, C.byref(st), cur.ptr, cur.nbytes, mp,
+                                          _stream_ptr(self.device), prgb, pT, C.byref(out))
+            if rc == L.AAA_ERR_PAIR_OVERFLOW:
+                mp = min(int(out.pairs * 1.25) + 1024, (1 << 32) - 1)
+                continue
+            L.check(rc)
+            self.last_pairs = int(out.pairs)
+            self.max_pairs = max(self.max_pairs, mp)
+            self.last_ws = cur
+            return rgbs, Ts, out
+        raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
+
+    def backward_batch(self, scene: DeviceScene, cams, settings, ws: Workspace, out_rgbs, grad_rgbs) -> dict:
+        """Gradients of sum_v sum(grad_rgbs[v] * rgb_v) for the batch held in `ws`."""
+        sc = scene.abi()
+        V = len(cams)
+        carr = (L.Camera * V)(*[L.make_camera(c) for c in cams])
+        st = L.make_settings(settings)
+        grads = {k: torch.zeros_like(t) for k, t in zip(["means", "log_scales", "quats", "opacity_logits", "sh"],
+                                                        scene.tensors())}
+        g = L.SceneGrad()
+        g.means, g.log_scales, g.quats = grads["means"].data_ptr(), grads["log_scales"].data_ptr(), grads["quats"].data_ptr()
+        g.opacity_logits, g.sh = grads["opacity_logits"].data_ptr(), grads["sh"].data_ptr()
+        grs = [t.contiguous().float() for t in grad_rgbs]
+        prgb = (C.c_void_p * V)(*[t.data_ptr() for t in out_rgbs])
+        pg = (C.c_void_p * V)(*[t.data_ptr() for t in grs])
+        L.check(L.lib().aaa_render_backward_batch(self._ctx, C.byref(sc), V, carr, C.byref(st), ws.ptr, ws.nbytes,
+                                                  ws.max_pairs, _stream_ptr(self.device), prgb, pg, C.byref(g)))
+        return grads
+
     def backward(self, scene: DeviceScene, cam, settings, ws: Workspace, out_rgb: torch.Tensor,
                  grad_rgb: torch.Tensor) -> dict:
         """Gradients of sum(grad_rgb * rgb) for the frame held in `ws`."""
