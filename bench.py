@@ -53,6 +53,10 @@ def main():
     ap.add_argument("--cpu-poses", type=int, default=4)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB once (counter calibration)")
+    ap.add_argument("--bwd-steps", type=int, default=32)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rates", type=str, default="100,200")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -162,6 +166,52 @@ def main():
         "per_frame": {"pairs": P.mean(), "visible": VIS.mean(), "evaluations": E.mean(),
                       "prefilter_passes": NE.mean(), "contributors": CT.mean()},
     }
+
+    # forward + backward: L1 loss against a seeded noise target, one pose per step
+    if args.bwd_steps > 0:
+        target = torch.from_numpy(S.noise_target(1080, 1920)).to("cuda:0")
+        for k in range(4):
+            rgb, T, _ = ras.render(ds, cams[k % len(cams)], st)
+            g = torch.sign(rgb - target) / rgb.numel()
+            ras.backward(ds, cams[k % len(cams)], st, ras.last_ws, rgb, g)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        bwd_ms = 0.0
+        t0 = time.perf_counter()
+        for k in range(args.bwd_steps):
+            cam = cams[k % len(cams)]
+            rgb, T, _ = ras.render(ds, cam, st)
+            g = torch.sign(rgb - target) / rgb.numel()
+            ev0.record()
+            ras.backward(ds, cam, st, ras.last_ws, rgb, g)
+            ev1.record()
+            ev1.synchronize()
+            bwd_ms += ev0.elapsed_time(ev1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res["fwd_bwd"] = {"value": round(args.bwd_steps / el, 3), "unit": "frames/s", "steps": args.bwd_steps,
+                          "ms_per_step": round(1000 * el / args.bwd_steps, 4),
+                          "backward_ms": round(bwd_ms / args.bwd_steps, 4),
+                          "loss": "L1 vs seeded U[0,1] noise image"}
+
+    # serving: Poisson arrivals, mixed resolution / FoV / zoom, 1M resident scene
+    if not args.no_serving:
+        from paper_2504_12811_amd.serve import Server, gpu_render_batch, run_load
+        serving = {}
+        for mode, (workers, maxb) in {"batched": (2, 8), "one_at_a_time": (1, 1)}.items():
+            fn = gpu_render_batch(ds, st, n_workers=workers)
+            for rate in [float(r) for r in args.serve_rates.split(",")]:
+                with Server(fn, n_gaussians=ds.n, mem_cap=16 << 30, max_batch=maxb, n_workers=workers) as srv:
+                    run_load(srv, rate, 0.5, seed=99)  # warm-up (allocations, code paths)
+                    lat, frames, wall, rej = run_load(srv, rate, args.serve_seconds, seed=int(rate))
+                    batches = list(srv.batches)
+                serving[f"{mode}@{int(rate)}"] = {
+                    "rate_req_s": rate, "requests": int(len(lat)), "rejected": rej,
+                    "p50_ms": round(1000 * float(np.percentile(lat, 50)), 2) if len(lat) else None,
+                    "p99_ms": round(1000 * float(np.percentile(lat, 99)), 2) if len(lat) else None,
+                    "frames_per_s": round(frames / wall, 2), "mean_batch": round(float(np.mean(batches)), 2)}
+                print(f"# serving {mode} {rate}: {serving[f'{mode}@{int(rate)}']}", file=sys.stderr, flush=True)
+        res["serving"] = serving
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O

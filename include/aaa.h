@@ -156,13 +156,21 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
  * is that render's output (DEVICE, read).  Accumulates (+=) into `grad`
  * (DEVICE arrays, same layouts as the scene; any pointer may be NULL to skip
  * it).  The blend state is recomputed per tile from the stored sorted pairs
- * (no per-pixel lists are stored).  Decisions (culls, thresholds, the window
- * order, the alpha clamp, min(v_train, v), the colour clamp) are held fixed;
- * their gradients are zero or one-sided.  Uses the workspace's gradient
- * region; the forward state is left intact (backward may be called again). */
+ * (no per-pixel lists are kept by the forward).  `scratch` (DEVICE, 256-byte
+ * aligned) holds one 8-byte slot per (pixel, contributor) of the forward; its
+ * size comes from aaa_backward_scratch_size.  Decisions (culls, thresholds,
+ * the window order, the alpha clamp, min(v_train, v), the colour clamp) are
+ * held fixed; their gradients are zero or one-sided.  The forward state is
+ * left intact (backward may be called again).  Synchronises `stream`. */
 int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
                         void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
-                        const float *dL_drgb, aaa_scene_grad *grad);
+                        const float *dL_drgb, void *scratch, size_t scratch_bytes, aaa_scene_grad *grad);
+
+/* Bytes of backward scratch for the last render into `ws` (single view:
+ * n_views = 1, cams = &cam).  Runs a scan on `stream` and synchronises it. */
+int aaa_backward_scratch_size(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                              const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                              void *stream, size_t *bytes_out);
 
 /* ---- batches of views (serving, multi-view steps) ---------------------- */
 
@@ -184,7 +192,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
 int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
                               const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
                               void *stream, const float *const *out_rgb, const float *const *dL_drgb,
-                              aaa_scene_grad *grad);
+                              void *scratch, size_t scratch_bytes, aaa_scene_grad *grad);
 
 /* Accumulated stage times (milliseconds, HIP events on the render stream) of
  * every aaa_render with AAA_TIMING since the last reset, and the number of

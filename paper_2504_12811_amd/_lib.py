@@ -20,6 +20,7 @@ STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "fr
 EXPORTS = [
     "aaa_create", "aaa_destroy", "aaa_last_error", "aaa_version", "aaa_workspace_size", "aaa_render",
     "aaa_stage_times", "aaa_workspace_size_batch", "aaa_render_batch", "aaa_render_backward_batch",
+    "aaa_backward_scratch_size",
     "aaa_render_backward", "aaa_read_gaussians", "aaa_read_pairs", "aaa_sort_tmp_size", "aaa_sort_pairs",
 ]
 
@@ -79,7 +80,9 @@ def lib():
         L.aaa_render.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t, u64,
                                  vp, vp, vp, C.POINTER(Stats)]
         L.aaa_render_backward.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t,
-                                          u64, vp, vp, vp, C.POINTER(SceneGrad)]
+                                          u64, vp, vp, vp, vp, C.c_size_t, C.POINTER(SceneGrad)]
+        L.aaa_backward_scratch_size.argtypes = [vp, C.POINTER(Scene), C.c_int, C.POINTER(Camera), C.POINTER(Settings),
+                                                vp, C.c_size_t, u64, vp, C.POINTER(C.c_size_t)]
         L.aaa_read_gaussians.argtypes = [C.POINTER(Scene), C.POINTER(Camera), u64, vp, C.c_size_t, vp, vp, vp, vp, vp,
                                          vp]
         L.aaa_read_pairs.argtypes = [C.POINTER(Scene), C.POINTER(Camera), u64, vp, C.c_size_t, vp, vp, vp, vp, u64,
@@ -89,7 +92,7 @@ def lib():
         L.aaa_render_batch.argtypes = [vp, C.POINTER(Scene), C.c_int, C.POINTER(Camera), C.POINTER(Settings), vp,
                                        C.c_size_t, u64, vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(Stats)]
         L.aaa_render_backward_batch.argtypes = [vp, C.POINTER(Scene), C.c_int, C.POINTER(Camera), C.POINTER(Settings),
-                                                vp, C.c_size_t, u64, vp, C.POINTER(vp), C.POINTER(vp),
+                                                vp, C.c_size_t, u64, vp, C.POINTER(vp), C.POINTER(vp), vp, C.c_size_t,
                                                 C.POINTER(SceneGrad)]
         L.aaa_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_int]
         L.aaa_sort_tmp_size.argtypes = [u64, C.POINTER(C.c_size_t)]

@@ -227,10 +227,15 @@ struct BlendArgs {
     int total_tiles;
     float alpha_min, alpha_max, t_min;
     uint32_t *n_done;              // per pixel (view pix_base + y * W + x): list entries consumed
+    uint32_t *n_ins;               // per pixel: contributors inserted (forward output)
     unsigned long long *counters;  // [0] evaluations, [1] contributors, [2] prefilter passes
-    float *grad_rec;               // backward only: per item, kGradStride floats
+    // backward only
+    float *grad_rec;               // per item, kGradStride floats
+    const uint64_t *pix_off;       // per pixel: first slot (exclusive scan of n_ins)
+    float2 *slots;                 // per (pixel, contributor rank): dL/dalpha, T alpha
 };
-hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool bwd, hipStream_t s);
+hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);
+hipError_t launch_grad(const BlendArgs &a, hipStream_t s);
 
 struct GradOut {
     float *means, *log_scales, *quats, *logits, *sh;

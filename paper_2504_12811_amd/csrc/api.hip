@@ -70,7 +70,7 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 
 struct Layout {
     size_t hdr, views, status, rect, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
-        ranges, n_done, grad_rec, total;
+        ranges, n_done, n_ins, pix_off, pix_scan_tmp, grad_rec, total;
 };
 
 Layout layout(const Shape &sh, uint64_t max_pairs)
@@ -100,6 +100,9 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
     L.ranges = take((size_t)sh.total_tiles * 8);
     L.n_done = take((size_t)sh.total_pixels * 4);
+    L.n_ins = take((size_t)sh.total_pixels * 4);
+    L.pix_off = take(((size_t)sh.total_pixels + 1) * 8);
+    L.pix_scan_tmp = take(aaa::scan_tmp_bytes(sh.total_pixels > 0 ? sh.total_pixels : 1));
     L.grad_rec = take(items * 4 * aaa::kGradStride);
     L.total = o;
     return L;
@@ -432,8 +435,11 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.alpha_max = (float)settings->alpha_max;
     ba.t_min = (float)settings->t_min;
     ba.n_done = at<uint32_t>(ws, L.n_done);
+    ba.n_ins = at<uint32_t>(ws, L.n_ins);
     ba.counters = ctr + 2;
     ba.grad_rec = nullptr;
+    ba.pix_off = nullptr;
+    ba.slots = nullptr;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, false, s));
     if (timing) {
         STAGE_MARK(8);
@@ -460,10 +466,40 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     return aaa_render_batch(ctx, scene, 1, cam, settings, ws, ws_bytes, max_pairs, stream, &out_rgb, &out_T, stats);
 }
 
+// Slots of the backward: one per (pixel, contributor) of the last forward,
+// placed by an exclusive scan of the per-pixel contributor counts.
+static int backward_slots(const Shape &sh, const Layout &L, void *ws, hipStream_t s, uint64_t *total)
+{
+    HIP_TRY(aaa::launch_exclusive_scan(at<uint32_t>(ws, L.n_ins), at<uint64_t>(ws, L.pix_off), sh.total_pixels,
+                                       at<void>(ws, L.pix_scan_tmp), s));
+    HIP_TRY(hipMemcpyAsync(total, at<uint64_t>(ws, L.pix_off) + sh.total_pixels, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return AAA_OK;
+}
+
+int aaa_backward_scratch_size(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                              const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                              void *stream, size_t *bytes_out)
+{
+    if (!ctx || !bytes_out) return fail(AAA_ERR_INVALID, "null context or bytes_out");
+    int rc = check_common(scene, n_views, cams, settings);
+    if (rc) return rc;
+    if (!ws) return fail(AAA_ERR_INVALID, "null workspace");
+    const Shape sh = shape_of(scene, n_views, cams);
+    Layout L = layout(sh, max_pairs);
+    if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+    HIP_TRY(hipSetDevice(ctx->device));
+    uint64_t total = 0;
+    rc = backward_slots(sh, L, ws, (hipStream_t)stream, &total);
+    if (rc) return rc;
+    *bytes_out = (size_t)total * sizeof(float2) + 256;
+    return AAA_OK;
+}
+
 int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
                               const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
                               void *stream, const float *const *out_rgb, const float *const *dL_drgb,
-                              aaa_scene_grad *grad)
+                              void *scratch, size_t scratch_bytes, aaa_scene_grad *grad)
 {
     if (!ctx) return fail(AAA_ERR_INVALID, "null context");
     int rc = check_common(scene, n_views, cams, settings);
@@ -478,9 +514,16 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     HIP_TRY(hipSetDevice(ctx->device));
     const int64_t n = scene->n;
     if (n == 0) return AAA_OK;
+    uint64_t total = 0;
+    rc = backward_slots(sh, L, ws, s, &total);
+    if (rc) return rc;
+    if (total > 0 && (!scratch || scratch_bytes < total * sizeof(float2)))
+        return fail(AAA_ERR_WORKSPACE, "backward scratch %zu < %zu bytes (aaa_backward_scratch_size)", scratch_bytes,
+                    (size_t)(total * sizeof(float2)));
     const int64_t ntiles = sh.total_tiles;
     float *grad_rec = at<float>(ws, L.grad_rec);
     HIP_TRY(hipMemsetAsync(grad_rec, 0, (size_t)n * n_views * 4 * aaa::kGradStride, s));
+    if (total) HIP_TRY(hipMemsetAsync(scratch, 0, total * sizeof(float2), s));  // never-blended contributors stay 0
     // the view table gains the backward's image and gradient pointers
     fill_views(n_views, cams, const_cast<float *const *>(out_rgb), nullptr, dL_drgb, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
@@ -498,9 +541,13 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     ba.alpha_max = (float)settings->alpha_max;
     ba.t_min = (float)settings->t_min;
     ba.n_done = at<uint32_t>(ws, L.n_done);
+    ba.n_ins = at<uint32_t>(ws, L.n_ins);
     ba.counters = nullptr;
     ba.grad_rec = grad_rec;
-    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));
+    ba.pix_off = at<uint64_t>(ws, L.pix_off);
+    ba.slots = (float2 *)scratch;
+    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));  // pass 1: window replay
+    HIP_TRY(aaa::launch_grad(ba, s));                                     // pass 2: list order, wave sums
     aaa::GradOut go;
     go.means = grad->means;
     go.log_scales = grad->log_scales;
@@ -515,10 +562,10 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
 
 int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
                         void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, const float *out_rgb,
-                        const float *dL_drgb, aaa_scene_grad *grad)
+                        const float *dL_drgb, void *scratch, size_t scratch_bytes, aaa_scene_grad *grad)
 {
     return aaa_render_backward_batch(ctx, scene, 1, cam, settings, ws, ws_bytes, max_pairs, stream, &out_rgb, &dL_drgb,
-                                     grad);
+                                     scratch, scratch_bytes, grad);
 }
 
 int aaa_read_gaussians(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_pairs, const void *ws,

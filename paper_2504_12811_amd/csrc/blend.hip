@@ -1,4 +1,4 @@
-// K5: per-tile blending, and K6a: its adjoint (the same kernel replayed).
+// K5: per-tile blending, and K6a: its adjoint in two passes.
 //
 // One workgroup per 16x16 tile; each wavefront owns an 8x8 quadrant and walks
 // the tile's sorted list on its own (no barriers, per-wave early exit).  Every
@@ -14,13 +14,17 @@
 // overflows its front is blended front to back; blending stops before the
 // first entry that would take the transmittance below t_min.
 //
-// The adjoint replays exactly the same decisions (same code, explicit FMAs)
-// and, at every blended entry k with transmittance T_k, uses the
-// front-to-back form of the blend derivative:
-//   dC/dalpha_k = T_k c_k - (C_out - A_k) / (1 - alpha_k),  A_k = sum_{j<=k} T_j alpha_j c_j,
-// so no per-pixel list is stored: the state is recomputed per tile.  The 22
-// record gradients of an entry (line coefficients, alpha~, colour) are summed
-// over the lanes that blended the same Gaussian and added atomically.
+// Adjoint.  Pass 1 replays the forward exactly (same code, explicit FMAs)
+// and, at every blended entry k, evaluates the front-to-back derivative
+//   dL/dalpha_k = T_k (c_k . g) - ((C_out - A_k) . g) / (1 - alpha_k),
+//   A_k = sum_{j <= k} T_j alpha_j c_j,
+// so no per-pixel list is kept from the forward: the state is recomputed per
+// tile.  It stores (dL/dalpha_k, T_k alpha_k) in the pixel's slot for the
+// entry's contributor rank (its position among the pixel's contributors in
+// list order).  Pass 2 walks the list in list order again, so that all lanes
+// look at the same Gaussian: each contributing lane turns its two scalars into
+// the 22 record gradients (line coefficients, alpha~, colour), the wave sums
+// them with DPP row reductions, and one instruction adds them atomically.
 #include "aaa_internal.h"
 
 namespace aaa {
@@ -37,7 +41,7 @@ struct Eval {
 };
 
 // Line direction r and o_g x r at a pixel offset, with explicit FMAs so that
-// the forward pass and its replay take identical decisions.
+// the forward pass and its replays take identical decisions.
 __device__ __forceinline__ Eval eval_line(float dx, float dy, float4 q0, float4 q1, float4 q2, float4 q3, float4 q4)
 {
     Eval e;
@@ -52,107 +56,44 @@ __device__ __forceinline__ Eval eval_line(float dx, float dy, float4 q0, float4 
     return e;
 }
 
-__device__ __forceinline__ float wave_sum(float v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 struct BwdPixel {
     float A[3];     // front colour accumulated so far
     float Cout[3];  // forward output of the pixel
     float g[3];     // dL / d out_rgb
-    float fx, fy;   // pixel centre
+    float2 *slots;  // this pixel's scratch slots, indexed by contributor rank
 };
 
-// Gradients of one blended entry at one pixel (22 values) for Gaussian id.
-__device__ __forceinline__ void entry_grad(const float4 *__restrict__ rec, uint32_t id, float T, float a, float amax,
-                                           BwdPixel &bp, float *v)
+// Blend (forward) or replay (pass 1) one popped entry.
+template <bool PASS1>
+__device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t item, uint32_t rank,
+                                            float a, float t_min, BwdPixel &bp, uint32_t cap)
 {
-    const float4 *r = rec + (size_t)id * kRecQuads;
-    const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q7 = r[7];
-    const float W = T * a;
-    bp.A[0] += W * q7.x;
-    bp.A[1] += W * q7.y;
-    bp.A[2] += W * q7.z;
-    const float cg = q7.x * bp.g[0] + q7.y * bp.g[1] + q7.z * bp.g[2];
-    const float Sg = (bp.Cout[0] - bp.A[0]) * bp.g[0] + (bp.Cout[1] - bp.A[1]) * bp.g[1] +
-                     (bp.Cout[2] - bp.A[2]) * bp.g[2];
-    const float ga = T * cg - Sg / (1.0f - a);
-    v[19] = W * bp.g[0];
-    v[20] = W * bp.g[1];
-    v[21] = W * bp.g[2];
-    if (a >= amax) {  // clamped: alpha does not move with rho^2 or alpha~
-        for (int k = 0; k < 19; ++k) v[k] = 0.0f;
-        return;
-    }
-    v[18] = ga * a / q5.w;
-    const float gr2 = -0.5f * ga * a;
-    const float dx = bp.fx - q5.y, dy = bp.fy - q5.z;
-    const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
-    const float invD = 1.0f / e.D;
-    const float rho2 = e.N * invD;
-    const float kw = 2.0f * gr2 * invD, kr = -2.0f * gr2 * rho2 * invD;
-    const float gr[3] = {kr * e.rx, kr * e.ry, kr * e.rz};
-    const float gw[3] = {kw * e.wx, kw * e.wy, kw * e.wz};
-    for (int k = 0; k < 3; ++k) {
-        v[k] = gr[k];
-        v[3 + k] = dx * gr[k];
-        v[6 + k] = dy * gr[k];
-        v[9 + k] = gw[k];
-        v[12 + k] = dx * gw[k];
-        v[15 + k] = dy * gw[k];
-    }
-}
-
-// Sum the pending entry gradients of lanes that blended the same Gaussian
-// and add them to the record-gradient buffer (one atomic per value and group).
-__device__ __forceinline__ void flush_grads(bool pending, uint32_t id, const float *v, float *__restrict__ grad_rec)
-{
-    uint64_t left = __ballot(pending);
-    while (left) {
-        const int leader = __ffsll((unsigned long long)left) - 1;
-        const uint32_t gid = (uint32_t)__shfl((int)id, leader);
-        const bool mine = pending && id == gid;
-        float *dst = grad_rec + (size_t)gid * kGradStride;
-#pragma unroll
-        for (int k = 0; k < 22; ++k) {
-            const float s = wave_sum(mine ? v[k] : 0.0f);
-            if ((int)__lane_id() == leader && s != 0.0f) atomicAdd(&dst[k], s);
-        }
-        left &= ~__ballot(mine);
-    }
-}
-
-template <bool BWD>
-__device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t id, float a,
-                                            float t_min, float amax, BwdPixel &bp, float *__restrict__ grad_rec)
-{
-    bool pending = false;
-    float v[BWD ? 22 : 1];
     if (a > 0.0f && !ps.done) {  // window fillers and idle lanes carry alpha 0
         const float Tn = ps.T * (1.0f - a);
         if (Tn < t_min) {
             ps.done = true;
         } else {
-            if (BWD) {
-                entry_grad(rec, id, ps.T, a, amax, bp, v);
-                pending = true;
+            const float4 c = rec[(size_t)item * kRecQuads + 7];
+            const float W = ps.T * a;
+            if (PASS1) {
+                bp.A[0] += W * c.x;
+                bp.A[1] += W * c.y;
+                bp.A[2] += W * c.z;
+                const float cg = c.x * bp.g[0] + c.y * bp.g[1] + c.z * bp.g[2];
+                const float Sg = (bp.Cout[0] - bp.A[0]) * bp.g[0] + (bp.Cout[1] - bp.A[1]) * bp.g[1] +
+                                 (bp.Cout[2] - bp.A[2]) * bp.g[2];
+                if (rank < cap) bp.slots[rank] = make_float2(ps.T * cg - Sg / (1.0f - a), W);
             } else {
-                const float4 c = rec[(size_t)id * kRecQuads + 7];
-                const float wgt = ps.T * a;
-                ps.C[0] += wgt * c.x;
-                ps.C[1] += wgt * c.y;
-                ps.C[2] += wgt * c.z;
+                ps.C[0] += W * c.x;
+                ps.C[1] += W * c.y;
+                ps.C[2] += W * c.z;
             }
             ps.T = Tn;
         }
     }
-    if (BWD) flush_grads(pending, id, v, grad_rec);
 }
 
-template <int K, bool STATS, bool BWD>
+template <int K, bool STATS, bool PASS1>
 __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
 {
     const int ntiles = a.total_tiles;
@@ -175,14 +116,16 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
     const size_t hw = (size_t)vw.cam.width * vw.cam.height;
     const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
+    const size_t gpix = vw.pix_base + pix;
 
     float wz[K > 0 ? K : 1];
-    uint32_t wid[K > 0 ? K : 1];
+    uint32_t wid[K > 0 ? K : 1], wrk[K > 0 ? K : 1];
     float wa[K > 0 ? K : 1];
 #pragma unroll
     for (int k = 0; k < (K > 0 ? K : 1); ++k) {
         wz[k] = -INFINITY;
         wid[k] = 0u;
+        wrk[k] = 0u;
         wa[k] = 0.0f;
     }
     PixelState ps;
@@ -190,15 +133,19 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     ps.C[0] = ps.C[1] = ps.C[2] = 0.0f;
     ps.done = !inside;
     BwdPixel bp;
-    bp.fx = fxp;
-    bp.fy = fyp;
+    bp.slots = nullptr;
     for (int c = 0; c < 3; ++c) {
         bp.A[c] = 0.0f;
-        bp.Cout[c] = (BWD && inside) ? vw.out_rgb[c * hw + pix] : 0.0f;
-        bp.g[c] = (BWD && inside) ? vw.dL_drgb[c * hw + pix] : 0.0f;
+        bp.Cout[c] = (PASS1 && inside) ? vw.out_rgb[c * hw + pix] : 0.0f;
+        bp.g[c] = (PASS1 && inside) ? vw.dL_drgb[c * hw + pix] : 0.0f;
     }
-    uint32_t consumed = 0;
-    uint32_t n_eval = 0, n_contrib = 0, n_near = 0;
+    uint32_t cap = 0;  // pass 1: slots of this pixel (its contributor count in the forward)
+    if (PASS1 && inside) {
+        bp.slots = a.slots + a.pix_off[gpix];
+        cap = a.n_ins[gpix];
+    }
+    uint32_t consumed = 0, rank = 0;
+    uint32_t n_eval = 0, n_near = 0;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
 
     for (uint32_t i = start; i < end; ++i) {
@@ -220,9 +167,10 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
         const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
         const bool contrib = near && al >= amin && z >= znear;
         if (__ballot(contrib) == 0ull) continue;
-        if (STATS && contrib) ++n_contrib;
+        const uint32_t my_rank = rank;
+        if (contrib) ++rank;
         if (K == 0) {
-            blend_entry<BWD>(ps, a.rec, id, contrib ? al : 0.0f, tmin, amax, bp, a.grad_rec);
+            blend_entry<PASS1>(ps, a.rec, id, my_rank, contrib ? al : 0.0f, tmin, bp, cap);
         } else {
             // Non-contributing lanes insert a NaN depth: every comparison is
             // false, the window stays as it is and the popped entry is the
@@ -233,6 +181,7 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
             bool gcur = wz[0] <= zk;
             const float pop_a = gcur ? wa[0] : ak;
             const uint32_t pop_id = gcur ? wid[0] : id;
+            const uint32_t pop_rk = gcur ? wrk[0] : my_rank;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int kn = k + 1 < K ? k + 1 : k;
@@ -240,9 +189,10 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
                 wz[k] = gnext ? wz[kn] : (gcur ? zk : wz[k]);
                 wid[k] = gnext ? wid[kn] : (gcur ? id : wid[k]);
                 wa[k] = gnext ? wa[kn] : (gcur ? ak : wa[k]);
+                if (PASS1) wrk[k] = gnext ? wrk[kn] : (gcur ? my_rank : wrk[k]);
                 gcur = gnext;
             }
-            blend_entry<BWD>(ps, a.rec, pop_id, pop_a, tmin, amax, bp, a.grad_rec);
+            blend_entry<PASS1>(ps, a.rec, pop_id, pop_rk, pop_a, tmin, bp, cap);
         }
         if (contrib && ps.done && consumed == 0) consumed = i - start + 1;
     }
@@ -251,18 +201,19 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     if (K > 0) {
 #pragma unroll
         for (int k = 0; k < (K > 0 ? K : 1); ++k)
-            blend_entry<BWD>(ps, a.rec, wid[k], ps.done ? 0.0f : wa[k], tmin, amax, bp, a.grad_rec);
+            blend_entry<PASS1>(ps, a.rec, wid[k], wrk[k], ps.done ? 0.0f : wa[k], tmin, bp, cap);
     }
     if (draining) consumed = end - start;
-    if (!BWD && inside) {
+    if (!PASS1 && inside) {
         vw.out_rgb[pix] = ps.C[0] + ps.T * vw.bg[0];
         vw.out_rgb[hw + pix] = ps.C[1] + ps.T * vw.bg[1];
         vw.out_rgb[2 * hw + pix] = ps.C[2] + ps.T * vw.bg[2];
         vw.out_T[pix] = ps.T;
-        a.n_done[vw.pix_base + pix] = consumed;
+        a.n_done[gpix] = consumed;
+        a.n_ins[gpix] = rank;
     }
     if (STATS) {
-        unsigned long long e = n_eval, c = n_contrib, nr = n_near;
+        unsigned long long e = n_eval, c = rank, nr = n_near;
         for (int off = 32; off > 0; off >>= 1) {
             e += __shfl_down(e, off);
             c += __shfl_down(c, off);
@@ -276,13 +227,112 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     }
 }
 
+// ----------------------------------------------------------------- pass 2
+
+// Sum over the 64 lanes of a wavefront: DPP steps inside each row of 16
+// lanes (quad swaps, half-row mirror, row mirror leave every lane holding its
+// row's sum), then the four row sums read back as scalars.
+__device__ __forceinline__ float wave_total(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
+    const int b = __float_as_int(v);
+    return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) + __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+           (__int_as_float(__builtin_amdgcn_readlane(b, 32)) + __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+}
+
+__global__ __launch_bounds__(256) void k_grad(BlendArgs a)
+{
+    const int ntiles = a.total_tiles;
+    const int per = (ntiles + 7) / 8;
+    const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (tile >= ntiles) return;
+    int v = 0;
+    while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
+    const ViewDev &vw = a.views[v];
+    const int nv = a.nviews;
+    const int lt = tile - vw.tile_base;
+    const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+    const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+    const bool inside = px < vw.cam.width && py < vw.cam.height;
+    const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
+    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    const size_t hw = (size_t)vw.cam.width * vw.cam.height;
+    const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
+    const size_t gpix = vw.pix_base + pix;
+    // entries this pixel consumed in the forward, and its slots
+    const uint32_t limit = inside ? start + a.n_done[gpix] : start;
+    const uint32_t cap = inside ? a.n_ins[gpix] : 0;
+    const float2 *slots = a.slots + (inside ? a.pix_off[gpix] : 0);
+    float g[3];
+    for (int c = 0; c < 3; ++c) g[c] = inside ? vw.dL_drgb[c * hw + pix] : 0.0f;
+    const float amin = a.alpha_min, amax = a.alpha_max, znear = (float)vw.cam.znear;
+    uint32_t rank = 0;
+
+    for (uint32_t i = start; i < end; ++i) {
+        const bool active = i < limit;
+        if (__ballot(active) == 0ull) break;
+        const uint32_t item = a.vals[i] * (uint32_t)nv + (uint32_t)v;
+        const float4 *r = a.rec + (size_t)item * kRecQuads;
+        const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
+        const float dx = fxp - q5.y, dy = fyp - q5.z;
+        const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
+        const bool near = active && e.N <= q6.x * e.D;
+        if (__ballot(near) == 0ull) continue;
+        const float inv = __builtin_amdgcn_rcpf(e.D);
+        const float rho2 = e.N * inv;
+        const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
+        const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
+        const bool contrib = near && al >= amin && z >= znear;
+        if (__ballot(contrib) == 0ull) continue;
+        float2 s = make_float2(0.0f, 0.0f);
+        if (contrib) {
+            if (rank < cap) s = slots[rank];
+            ++rank;
+        }
+        // 22 record gradients of this lane (zero when not blended)
+        const float ga = s.x, W = s.y;
+        const bool moves = contrib && al < amax && W > 0.0f;  // a clamped alpha does not move
+        const float gat = moves ? ga * al / q5.w : 0.0f;
+        const float gr2 = moves ? -0.5f * ga * al : 0.0f;
+        const float invD = 1.0f / e.D;
+        const float kw = 2.0f * gr2 * invD, kr = -2.0f * gr2 * rho2 * invD;
+        float vals[22];
+        const float gr[3] = {kr * e.rx, kr * e.ry, kr * e.rz};
+        const float gw[3] = {kw * e.wx, kw * e.wy, kw * e.wz};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            vals[k] = gr[k];
+            vals[3 + k] = dx * gr[k];
+            vals[6 + k] = dy * gr[k];
+            vals[9 + k] = gw[k];
+            vals[12 + k] = dx * gw[k];
+            vals[15 + k] = dy * gw[k];
+            vals[19 + k] = W * g[k];
+        }
+        vals[18] = gat;
+        // wave sums; lane k then adds value k (one atomic instruction)
+        float mine = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 22; ++k) {
+            const float t = wave_total(vals[k]);
+            mine = lane == k ? t : mine;
+        }
+        if (lane < 22 && mine != 0.0f) atomicAdd(&a.grad_rec[(size_t)item * kGradStride + lane], mine);
+    }
+}
+
 template <int K>
-hipError_t launch_k(const BlendArgs &a, bool stats, bool bwd, hipStream_t s)
+hipError_t launch_k(const BlendArgs &a, bool stats, bool pass1, hipStream_t s)
 {
     const int ntiles = a.total_tiles;
     const int per = (ntiles + 7) / 8;
     dim3 grid((unsigned)(per * 8));
-    if (bwd)
+    if (pass1)
         hipLaunchKernelGGL((k_blend<K, false, true>), grid, dim3(256), 0, s, a);
     else if (stats)
         hipLaunchKernelGGL((k_blend<K, true, false>), grid, dim3(256), 0, s, a);
@@ -293,19 +343,27 @@ hipError_t launch_k(const BlendArgs &a, bool stats, bool bwd, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool bwd, hipStream_t s)
+hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s)
 {
     if (a.total_tiles <= 0) return hipSuccess;
     switch (K) {
-    case 0: return launch_k<0>(a, stats, bwd, s);
-    case 1: return launch_k<1>(a, stats, bwd, s);
-    case 2: return launch_k<2>(a, stats, bwd, s);
-    case 4: return launch_k<4>(a, stats, bwd, s);
-    case 8: return launch_k<8>(a, stats, bwd, s);
-    case 16: return launch_k<16>(a, stats, bwd, s);
-    case 32: return launch_k<32>(a, stats, bwd, s);
+    case 0: return launch_k<0>(a, stats, pass1, s);
+    case 1: return launch_k<1>(a, stats, pass1, s);
+    case 2: return launch_k<2>(a, stats, pass1, s);
+    case 4: return launch_k<4>(a, stats, pass1, s);
+    case 8: return launch_k<8>(a, stats, pass1, s);
+    case 16: return launch_k<16>(a, stats, pass1, s);
+    case 32: return launch_k<32>(a, stats, pass1, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_grad(const BlendArgs &a, hipStream_t s)
+{
+    if (a.total_tiles <= 0) return hipSuccess;
+    const int per = (a.total_tiles + 7) / 8;
+    hipLaunchKernelGGL(k_grad, dim3((unsigned)(per * 8)), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace aaa

@@ -196,9 +196,21 @@ class Rasterizer:
         grs = [t.contiguous().float() for t in grad_rgbs]
         prgb = (C.c_void_p * V)(*[t.data_ptr() for t in out_rgbs])
         pg = (C.c_void_p * V)(*[t.data_ptr() for t in grs])
+        scr, nscr = self._backward_scratch(sc, V, carr, st, ws)
         L.check(L.lib().aaa_render_backward_batch(self._ctx, C.byref(sc), V, carr, C.byref(st), ws.ptr, ws.nbytes,
-                                                  ws.max_pairs, _stream_ptr(self.device), prgb, pg, C.byref(g)))
+                                                  ws.max_pairs, _stream_ptr(self.device), prgb, pg, scr, nscr,
+                                                  C.byref(g)))
         return grads
+
+    def _backward_scratch(self, sc, V, carr, st, ws: Workspace):
+        need = C.c_size_t()
+        L.check(L.lib().aaa_backward_scratch_size(self._ctx, C.byref(sc), V, carr, C.byref(st), ws.ptr, ws.nbytes,
+                                                  ws.max_pairs, _stream_ptr(self.device), C.byref(need)))
+        buf = getattr(self, "_bwd_scratch", None)
+        if buf is None or buf.numel() < need.value + 256:
+            self._bwd_scratch = buf = torch.empty(int(need.value * 1.2) + 512, dtype=torch.uint8, device=self.device)
+        ptr = buf.data_ptr() + ((-buf.data_ptr()) % 256)
+        return ptr, int(need.value)
 
     def backward(self, scene: DeviceScene, cam, settings, ws: Workspace, out_rgb: torch.Tensor,
                  grad_rgb: torch.Tensor) -> dict:
@@ -212,9 +224,10 @@ class Rasterizer:
         g.means, g.log_scales, g.quats = grads["means"].data_ptr(), grads["log_scales"].data_ptr(), grads["quats"].data_ptr()
         g.opacity_logits, g.sh = grads["opacity_logits"].data_ptr(), grads["sh"].data_ptr()
         gr = grad_rgb.contiguous().float()
+        scr, nscr = self._backward_scratch(sc, 1, C.pointer(c), st, ws)
         L.check(L.lib().aaa_render_backward(self._ctx, C.byref(sc), C.byref(c), C.byref(st), ws.ptr, ws.nbytes,
                                             ws.max_pairs, _stream_ptr(self.device), out_rgb.data_ptr(), gr.data_ptr(),
-                                            C.byref(g)))
+                                            scr, nscr, C.byref(g)))
         return grads
 
     def stage_times(self, reset: bool = True):
