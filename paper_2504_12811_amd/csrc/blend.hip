@@ -56,6 +56,49 @@ __device__ __forceinline__ Eval eval_line(float dx, float dy, float4 q0, float4 
     return e;
 }
 
+// What the evaluation of one list entry reads from its record (line
+// coefficients, depth numerator, anchor, alpha~, prefilter threshold): 25
+// scalars, fetched one list entry ahead.
+struct Hot {
+    float4 q0, q1, q2, q3;
+    float w2y, w2z, l0, l1, l2, xa, ya, at, tp;
+};
+
+__device__ __forceinline__ Hot load_hot(const float4 *__restrict__ rec, uint32_t item)
+{
+    const float4 *r = rec + (size_t)item * kRecQuads;
+    const float *f = (const float *)r;
+    Hot h;
+    h.q0 = r[0];
+    h.q1 = r[1];
+    h.q2 = r[2];
+    h.q3 = r[3];
+    h.w2y = f[16];
+    h.w2z = f[17];
+    h.l0 = f[18];
+    h.l1 = f[19];
+    h.l2 = f[20];
+    h.xa = f[21];
+    h.ya = f[22];
+    h.at = f[23];
+    h.tp = f[24];
+    return h;
+}
+
+__device__ __forceinline__ Eval eval_line(float dx, float dy, const Hot &h)
+{
+    Eval e;
+    e.rx = __fmaf_rn(dy, h.q1.z, __fmaf_rn(dx, h.q0.w, h.q0.x));
+    e.ry = __fmaf_rn(dy, h.q1.w, __fmaf_rn(dx, h.q1.x, h.q0.y));
+    e.rz = __fmaf_rn(dy, h.q2.x, __fmaf_rn(dx, h.q1.y, h.q0.z));
+    e.wx = __fmaf_rn(dy, h.q3.w, __fmaf_rn(dx, h.q3.x, h.q2.y));
+    e.wy = __fmaf_rn(dy, h.w2y, __fmaf_rn(dx, h.q3.y, h.q2.z));
+    e.wz = __fmaf_rn(dy, h.w2z, __fmaf_rn(dx, h.q3.z, h.q2.w));
+    e.D = __fmaf_rn(e.rz, e.rz, __fmaf_rn(e.ry, e.ry, e.rx * e.rx));
+    e.N = __fmaf_rn(e.wz, e.wz, __fmaf_rn(e.wy, e.wy, e.wx * e.wx));
+    return e;
+}
+
 struct BwdPixel {
     float A[3];     // front colour accumulated so far
     float Cout[3];  // forward output of the pixel
@@ -94,7 +137,8 @@ __device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__rest
 }
 
 template <int K, bool STATS, bool PASS1>
-__global__ __launch_bounds__(256) void k_blend(BlendArgs a)
+__global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                               BlendArgs a)
 {
     const int ntiles = a.total_tiles;
     // XCD-aware order: consecutive workgroups land on different XCDs, so hand
@@ -118,15 +162,21 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
     const size_t gpix = vw.pix_base + pix;
 
-    float wz[K > 0 ? K : 1];
-    uint32_t wid[K > 0 ? K : 1], wrk[K > 0 ? K : 1];
-    float wa[K > 0 ? K : 1];
+    // Per-ray window: depths and slot numbers in registers, kept sorted by
+    // depth; each slot's payload (item, alpha and, in pass 1, the
+    // contributor rank) sits in LDS at [wave][slot][lane] and never moves.
+    // A popped entry's slot takes the entry inserted in its place, so only
+    // two registers per position take part in the sorting network.
+    constexpr int KS = K > 0 ? K : 1;
+    __shared__ uint2 pay[K > 0 ? 4 : 1][KS][64];
+    __shared__ uint32_t pay_rank[PASS1 && K > 0 ? 4 : 1][PASS1 ? KS : 1][64];
+    float wz[KS];
+    uint32_t ws[KS];
 #pragma unroll
-    for (int k = 0; k < (K > 0 ? K : 1); ++k) {
-        wz[k] = -INFINITY;
-        wid[k] = 0u;
-        wrk[k] = 0u;
-        wa[k] = 0.0f;
+    for (int k = 0; k < KS; ++k) {
+        wz[k] = -INFINITY;  // fillers: popped first, with alpha 0
+        ws[k] = (uint32_t)k;
+        if constexpr (K > 0) pay[wave][k][lane] = make_uint2(0u, 0u);
     }
     PixelState ps;
     ps.T = 1.0f;
@@ -149,9 +199,9 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
 
     for (uint32_t i = start; i < end; ++i) {
-        if (__ballot(!ps.done) == 0ull) break;
-        const uint32_t id = a.vals[i] * (uint32_t)nv + (uint32_t)v;  // item of (Gaussian, view)
-        const float4 *r = a.rec + (size_t)id * kRecQuads;
+        if (__builtin_amdgcn_ballot_w64(!ps.done) == 0ull) break;
+        const uint32_t id = vals[i] * (uint32_t)nv + (uint32_t)v;  // item of (Gaussian, view)
+        const float4 *r = rec + (size_t)id * kRecQuads;
         const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
         if (STATS && !ps.done) ++n_eval;
         const float dx = fxp - q5.y, dy = fyp - q5.z;
@@ -159,49 +209,61 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
         const bool near = !ps.done && e.N <= q6.x * e.D;
         // wave-uniform branches from here on: the window registers are only
         // ever updated with all lanes active (no divergent copies)
-        if (__ballot(near) == 0ull) continue;
+        if (__builtin_amdgcn_ballot_w64(near) == 0ull) continue;
         if (STATS && near) ++n_near;
         const float inv = __builtin_amdgcn_rcpf(e.D);
         const float rho2 = e.N * inv;
         const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
         const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
         const bool contrib = near && al >= amin && z >= znear;
-        if (__ballot(contrib) == 0ull) continue;
+        if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
         const uint32_t my_rank = rank;
         if (contrib) ++rank;
-        if (K == 0) {
-            blend_entry<PASS1>(ps, a.rec, id, my_rank, contrib ? al : 0.0f, tmin, bp, cap);
+        if constexpr (K == 0) {
+            blend_entry<PASS1>(ps, rec, id, my_rank, contrib ? al : 0.0f, tmin, bp, cap);
         } else {
             // Non-contributing lanes insert a NaN depth: every comparison is
             // false, the window stays as it is and the popped entry is the
             // NaN one with alpha 0 (a no-op blend).
             const float zk = contrib ? z : __builtin_nanf("");
             const float ak = contrib ? al : 0.0f;
-            // pop min(new, front); insert new behind equal depths
-            bool gcur = wz[0] <= zk;
-            const float pop_a = gcur ? wa[0] : ak;
-            const uint32_t pop_id = gcur ? wid[0] : id;
-            const uint32_t pop_rk = gcur ? wrk[0] : my_rank;
+            // pop min(new, front); insert new behind equal depths, into the
+            // slot the front leaves
+            const uint32_t fs = ws[0];
+            const uint2 fp = pay[wave][fs][lane];
+            const uint32_t frk = PASS1 ? pay_rank[wave][fs][lane] : 0u;
+            const bool front_out = wz[0] <= zk;
+            {
+                bool gcur = front_out;
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int kn = k + 1 < K ? k + 1 : k;
-                const bool gnext = (k + 1 < K) ? (wz[kn] <= zk) : false;
-                wz[k] = gnext ? wz[kn] : (gcur ? zk : wz[k]);
-                wid[k] = gnext ? wid[kn] : (gcur ? id : wid[k]);
-                wa[k] = gnext ? wa[kn] : (gcur ? ak : wa[k]);
-                if (PASS1) wrk[k] = gnext ? wrk[kn] : (gcur ? my_rank : wrk[k]);
-                gcur = gnext;
+                for (int k = 0; k < K; ++k) {
+                    const int kn = k + 1 < K ? k + 1 : k;
+                    const bool gnext = (k + 1 < K) ? (wz[kn] <= zk) : false;
+                    wz[k] = gnext ? wz[kn] : (gcur ? zk : wz[k]);
+                    ws[k] = gnext ? ws[kn] : (gcur ? fs : ws[k]);
+                    gcur = gnext;
+                }
             }
-            blend_entry<PASS1>(ps, a.rec, pop_id, pop_rk, pop_a, tmin, bp, cap);
+            const float pop_a = front_out ? __uint_as_float(fp.y) : ak;
+            const uint32_t pop_id = front_out ? fp.x : id;
+            const uint32_t pop_rk = front_out ? frk : my_rank;
+            if (front_out) {
+                pay[wave][fs][lane] = make_uint2(id, __float_as_uint(ak));
+                if (PASS1) pay_rank[wave][fs][lane] = my_rank;
+            }
+            blend_entry<PASS1>(ps, rec, pop_id, pop_rk, pop_a, tmin, bp, cap);
         }
         if (contrib && ps.done && consumed == 0) consumed = i - start + 1;
     }
     // drain the window in depth order (lanes already done pass alpha 0)
     const bool draining = !ps.done;
-    if (K > 0) {
+    if constexpr (K > 0) {
 #pragma unroll
-        for (int k = 0; k < (K > 0 ? K : 1); ++k)
-            blend_entry<PASS1>(ps, a.rec, wid[k], wrk[k], ps.done ? 0.0f : wa[k], tmin, bp, cap);
+        for (int k = 0; k < KS; ++k) {
+            const uint2 q = pay[wave][ws[k]][lane];
+            const uint32_t rk = PASS1 ? pay_rank[wave][ws[k]][lane] : 0u;
+            blend_entry<PASS1>(ps, rec, q.x, rk, ps.done ? 0.0f : __uint_as_float(q.y), tmin, bp, cap);
+        }
     }
     if (draining) consumed = end - start;
     if (!PASS1 && inside) {
@@ -229,21 +291,59 @@ __global__ __launch_bounds__(256) void k_blend(BlendArgs a)
 
 // ----------------------------------------------------------------- pass 2
 
-// Sum over the 64 lanes of a wavefront: DPP steps inside each row of 16
-// lanes (quad swaps, half-row mirror, row mirror leave every lane holding its
-// row's sum), then the four row sums read back as scalars.
-__device__ __forceinline__ float wave_total(float v)
+// Reduce-scatter of 22 per-lane values over a wavefront (gfx950 lane
+// swaps, then DPP inside rows of 16 lanes).
+//   1. v_permlane32_swap pairs values (2j, 2j+1): one register then holds
+//      value 2j summed over lanes l and l+32 in lanes 0-31 and value 2j+1 in
+//      lanes 32-63.
+//   2. v_permlane16_swap pairs two such registers: each row of 16 lanes then
+//      holds one value summed over 4 lanes; register m holds values
+//      4m, 4m+2, 4m+1, 4m+3 in rows 0..3 (register 5: values 20 and 21 in rows
+//      0 and 2).
+//   3. DPP steps (quad swaps, half-row mirror, row mirror) leave every lane
+//      of a row holding the row's total.
+// Lane 16 r + t (t < 6) then returns register t's total of row r and the
+// index of that value; other lanes return index -1.
+__device__ __forceinline__ float swap32_add(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_add(float a, float b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float row_total(float v)
 {
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
     v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
-    const int b = __float_as_int(v);
-    return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) + __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
-           (__int_as_float(__builtin_amdgcn_readlane(b, 32)) + __int_as_float(__builtin_amdgcn_readlane(b, 48)));
+    return v;
 }
 
-__global__ __launch_bounds__(256) void k_grad(BlendArgs a)
+__device__ __forceinline__ float reduce22(const float (&x)[22], int lane, int &idx)
+{
+    float u[11];
+#pragma unroll
+    for (int j = 0; j < 11; ++j) u[j] = swap32_add(x[2 * j], x[2 * j + 1]);
+    float X[6];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) X[m] = row_total(swap16_add(u[2 * m], u[2 * m + 1]));
+    X[5] = row_total(swap16_add(u[10], 0.0f));
+    const int t = lane & 15, r = lane >> 4;
+    float mine = X[0];
+#pragma unroll
+    for (int m = 1; m < 6; ++m) mine = t == m ? X[m] : mine;
+    idx = t < 5 ? 4 * t + ((r & 1) << 1) + (r >> 1) : (t == 5 && (r & 1) == 0) ? 20 + (r >> 1) : -1;
+    return mine;
+}
+
+__global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                              BlendArgs a)
 {
     const int ntiles = a.total_tiles;
     const int per = (ntiles + 7) / 8;
@@ -252,7 +352,7 @@ __global__ __launch_bounds__(256) void k_grad(BlendArgs a)
     int v = 0;
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
     const ViewDev &vw = a.views[v];
-    const int nv = a.nviews;
+    const uint32_t nv = (uint32_t)a.nviews;
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -273,22 +373,18 @@ __global__ __launch_bounds__(256) void k_grad(BlendArgs a)
     const float amin = a.alpha_min, amax = a.alpha_max, znear = (float)vw.cam.znear;
     uint32_t rank = 0;
 
-    for (uint32_t i = start; i < end; ++i) {
+    auto step = [&](uint32_t i, uint32_t item, const Hot &h) {
         const bool active = i < limit;
-        if (__ballot(active) == 0ull) break;
-        const uint32_t item = a.vals[i] * (uint32_t)nv + (uint32_t)v;
-        const float4 *r = a.rec + (size_t)item * kRecQuads;
-        const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
-        const float dx = fxp - q5.y, dy = fyp - q5.z;
-        const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
-        const bool near = active && e.N <= q6.x * e.D;
-        if (__ballot(near) == 0ull) continue;
+        const float dx = fxp - h.xa, dy = fyp - h.ya;
+        const Eval e = eval_line(dx, dy, h);
+        const bool near = active && e.N <= h.tp * e.D;
+        if (__builtin_amdgcn_ballot_w64(near) == 0ull) return;
         const float inv = __builtin_amdgcn_rcpf(e.D);
         const float rho2 = e.N * inv;
-        const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
-        const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
+        const float al = fminf(amax, h.at * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
+        const float z = __fmaf_rn(dy, h.l2, __fmaf_rn(dx, h.l1, h.l0)) * inv;
         const bool contrib = near && al >= amin && z >= znear;
-        if (__ballot(contrib) == 0ull) continue;
+        if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) return;
         float2 s = make_float2(0.0f, 0.0f);
         if (contrib) {
             if (rank < cap) s = slots[rank];
@@ -297,32 +393,44 @@ __global__ __launch_bounds__(256) void k_grad(BlendArgs a)
         // 22 record gradients of this lane (zero when not blended)
         const float ga = s.x, W = s.y;
         const bool moves = contrib && al < amax && W > 0.0f;  // a clamped alpha does not move
-        const float gat = moves ? ga * al / q5.w : 0.0f;
+        const float gat = moves ? ga * al / h.at : 0.0f;
         const float gr2 = moves ? -0.5f * ga * al : 0.0f;
         const float invD = 1.0f / e.D;
         const float kw = 2.0f * gr2 * invD, kr = -2.0f * gr2 * rho2 * invD;
-        float vals[22];
+        float vals22[22];
         const float gr[3] = {kr * e.rx, kr * e.ry, kr * e.rz};
         const float gw[3] = {kw * e.wx, kw * e.wy, kw * e.wz};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            vals[k] = gr[k];
-            vals[3 + k] = dx * gr[k];
-            vals[6 + k] = dy * gr[k];
-            vals[9 + k] = gw[k];
-            vals[12 + k] = dx * gw[k];
-            vals[15 + k] = dy * gw[k];
-            vals[19 + k] = W * g[k];
+            vals22[k] = gr[k];
+            vals22[3 + k] = dx * gr[k];
+            vals22[6 + k] = dy * gr[k];
+            vals22[9 + k] = gw[k];
+            vals22[12 + k] = dx * gw[k];
+            vals22[15 + k] = dy * gw[k];
+            vals22[19 + k] = W * g[k];
         }
-        vals[18] = gat;
-        // wave sums; lane k then adds value k (one atomic instruction)
-        float mine = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 22; ++k) {
-            const float t = wave_total(vals[k]);
-            mine = lane == k ? t : mine;
+        vals22[18] = gat;
+        // wave totals, scattered over 22 lanes (one atomic instruction)
+        int idx;
+        const float mine = reduce22(vals22, lane, idx);
+        if (idx >= 0 && mine != 0.0f) atomicAdd(&a.grad_rec[(size_t)item * kGradStride + idx], mine);
+    };
+
+    if (start < end) {
+        // same software pipeline as the forward
+        uint32_t id = vals[start] * nv + (uint32_t)v;
+        uint32_t raw_next = vals[start + 1 < end ? start + 1 : end - 1];
+        Hot h = load_hot(rec, id);
+        for (uint32_t i = start; i < end; ++i) {
+            if (__builtin_amdgcn_ballot_w64(i < limit) == 0ull) break;
+            const uint32_t id_next = raw_next * nv + (uint32_t)v;
+            raw_next = vals[i + 2 < end ? i + 2 : end - 1];
+            const Hot h_next = load_hot(rec, id_next);
+            step(i, id, h);
+            id = id_next;
+            h = h_next;
         }
-        if (lane < 22 && mine != 0.0f) atomicAdd(&a.grad_rec[(size_t)item * kGradStride + lane], mine);
     }
 }
 
@@ -333,11 +441,11 @@ hipError_t launch_k(const BlendArgs &a, bool stats, bool pass1, hipStream_t s)
     const int per = (ntiles + 7) / 8;
     dim3 grid((unsigned)(per * 8));
     if (pass1)
-        hipLaunchKernelGGL((k_blend<K, false, true>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_blend<K, false, true>), grid, dim3(256), 0, s, a.rec, a.vals, a);
     else if (stats)
-        hipLaunchKernelGGL((k_blend<K, true, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_blend<K, true, false>), grid, dim3(256), 0, s, a.rec, a.vals, a);
     else
-        hipLaunchKernelGGL((k_blend<K, false, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_blend<K, false, false>), grid, dim3(256), 0, s, a.rec, a.vals, a);
     return hipGetLastError();
 }
 
@@ -362,7 +470,7 @@ hipError_t launch_grad(const BlendArgs &a, hipStream_t s)
 {
     if (a.total_tiles <= 0) return hipSuccess;
     const int per = (a.total_tiles + 7) / 8;
-    hipLaunchKernelGGL(k_grad, dim3((unsigned)(per * 8)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_grad, dim3((unsigned)(per * 8)), dim3(256), 0, s, a.rec, a.vals, a);
     return hipGetLastError();
 }
 
