@@ -199,17 +199,22 @@ struct PreArgs {
     int filter_mode;  // 0 adaptive, 1 off, 2 volume
     int32_t *status;  // per item
     int4 *rect;
+    uint32_t *area;   // tiles in the rectangle (0 unless visible)
     float4 *rec;
     float4 *cull;
 };
 hipError_t launch_preprocess(const PreArgs &a, hipStream_t s);
 
-hipError_t launch_count_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
+// Pair emission over the candidate tests numbered by area_off (exclusive
+// scan of the rectangle areas, items + 1 entries).  count: zeroes counts, then
+// adds the survivors per item.  write: takes slots by running counts down to 0.
+hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
+                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               unsigned long long *tests, hipStream_t s);
-hipError_t launch_write_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              const ViewDev *views, int nviews, bool tile_cull, const uint64_t *offsets,
-                              uint64_t max_pairs, uint64_t *keys, uint32_t *vals, hipStream_t s);
+hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
+                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
+                              const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
+                              hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s);
 

@@ -69,7 +69,7 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 }
 
 struct Layout {
-    size_t hdr, views, status, rect, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+    size_t hdr, views, status, rect, area, area_off, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
         ranges, n_done, n_ins, pix_off, pix_scan_tmp, grad_rec, total;
 };
 
@@ -87,6 +87,8 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.views = take(sizeof(aaa::ViewDev) * (size_t)(sh.nviews > 0 ? sh.nviews : 1));
     L.status = take(items * 4);
     L.rect = take(items * 16);
+    L.area = take(items * 4);
+    L.area_off = take((items + 1) * 8);
     L.rec = take(items * 16 * aaa::kRecQuads);
     L.cull = take(items * 16 * aaa::kCullQuads);
     L.counts = take(items * 4);
@@ -217,6 +219,7 @@ aaa::PreArgs pre_args(const aaa_scene *scene, int nviews, const aaa_settings *se
     pa.filter_mode = (settings->flags & AAA_FILTER_OFF) ? 1 : ((settings->flags & AAA_FILTER_VOLUME) ? 2 : 0);
     pa.status = at<int32_t>(ws, L.status);
     pa.rect = at<int4>(ws, L.rect);
+    pa.area = at<uint32_t>(ws, L.area);
     pa.rec = at<float4>(ws, L.rec);
     pa.cull = at<float4>(ws, L.cull);
     return pa;
@@ -387,7 +390,10 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const int64_t items = n * n_views;
     uint32_t *counts = at<uint32_t>(ws, L.counts);
     uint64_t *offsets = at<uint64_t>(ws, L.offsets);
-    HIP_TRY(aaa::launch_count_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, pa.views, n_views, tile_cull, counts, ctr, s));
+    uint64_t *area_off = at<uint64_t>(ws, L.area_off);
+    HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s));
+    HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts, ctr,
+                                    s));
     STAGE_MARK(2);
     HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, items, at<void>(ws, L.scan_tmp), s));
     STAGE_MARK(3);
@@ -403,8 +409,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
     uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
     STAGE_MARK(4);
-    HIP_TRY(aaa::launch_write_pairs(pa.status, pa.rect, pa.rec, pa.cull, n, pa.views, n_views, tile_cull, offsets,
-                                    max_pairs, keys, vals, s));
+    HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
+                                    offsets, max_pairs, keys, vals, s));
     STAGE_MARK(5);
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,

@@ -1,20 +1,31 @@
 // K2: tile-pair emission.  For every visible Gaussian, every tile of its
 // bounding rectangle is tested in 3D (Sec. 3.4, Eq. 18); the pair counter
 // counts survivors, an exclusive scan turns counts into offsets, and the
-// writer emits (tile << 32 | order key of the tile depth, Gaussian index) in
-// Gaussian order, so that a stable sort breaks key ties by index.
+// writer emits (tile << 32 | order key of the tile depth, Gaussian index).
 //
-// Work split: one lane per Gaussian for small rectangles; rectangles with
-// more than kWaveRect tiles are handed to a whole wavefront, whose lanes
-// stride over the tiles (ballot + popcount give the wave's count and each
-// lane's write slot, preserving the row-major tile order).
+// Work split: the candidate (item, rectangle tile) tests are numbered through
+// an exclusive scan of the rectangle areas, and every lane takes one test
+// (grid-stride), so lanes stay busy whatever the mix of rectangle sizes.  A
+// lane finds its item by binary search over the area offsets.  The lanes of
+// one item inside a wave form a contiguous segment; its first lane adds the
+// segment's survivors to the item's count with one atomic.
+//
+// The writer places an item's pairs in the item's slot range [offset,
+// offset + count) in whatever order its segments arrive (each segment's
+// leader takes a block of slots by an atomic on the item's count, which
+// runs down to 0).  Items occupy increasing ranges, so the stable sort still
+// breaks key ties by item, i.e. by Gaussian index within a view; within one
+// item all keys differ (one pair per tile), so the order inside its range
+// does not change the sorted result.
+#include <algorithm>
+
 #include "aaa_internal.h"
 
 namespace aaa {
 
 namespace {
 
-constexpr int kWaveRect = 64;
+constexpr int kEmitBlocks = 2048;  // grid of the balanced emitter (grid-stride)
 
 __device__ __forceinline__ bool tile_keep(const TileGeom<float> &g, int tx, int ty, float tau, const CamDev &cam)
 {
@@ -35,109 +46,86 @@ __device__ __forceinline__ float tile_depth(const TileGeom<float> &g, int tx, in
     return l / dot3(r, r);
 }
 
-__device__ __forceinline__ uint64_t lane_mask_lt()
+__device__ __forceinline__ uint64_t bits_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+__global__ __launch_bounds__(256) void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
 {
-    unsigned lane = __lane_id();
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
 }
 
-// Pass 1 (count) and pass 2 (write) share one body.
-// Items are (Gaussian, view) pairs, item = i * nviews + v; pairs are emitted
-// in item order, so within a view they come in Gaussian order.
+// Pass 1 (count) and pass 2 (write) share one body.  Items are (Gaussian,
+// view) pairs, item = i * nviews + v.
 template <bool WRITE>
-__global__ __launch_bounds__(256) void k_pairs(const int32_t *__restrict__ status, const int4 *__restrict__ rects,
-                                               const float4 *__restrict__ recs, const float4 *__restrict__ culls,
+__global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, const float4 *__restrict__ recs,
+                                               const float4 *__restrict__ culls, const uint64_t *__restrict__ area_off,
                                                int64_t nitems, const ViewDev *__restrict__ views, int nviews,
                                                bool tile_cull, uint32_t *__restrict__ counts,
-                                               unsigned long long *__restrict__ tests, const uint64_t *__restrict__ offsets,
-                                               uint64_t max_pairs, uint64_t *__restrict__ keys,
-                                               uint32_t *__restrict__ vals)
+                                               unsigned long long *__restrict__ tests,
+                                               const uint64_t *__restrict__ offsets, uint64_t max_pairs,
+                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n = nitems;
-    const bool live = i < n && status[i] == kVisible;
-    int4 rc = live ? rects[i] : make_int4(0, 0, 0, 0);
-    const int rw = rc.y - rc.x, rh = rc.w - rc.z;
-    const int area = rw * rh;
-    const bool big = live && area > kWaveRect;
-    uint32_t my_count = 0;
-    uint64_t base = 0;
-    if (WRITE && live) base = offsets[i];
-    unsigned long long ntests = 0;
-    // small rectangles: one lane each
-    if (live && !big) {
-        const ViewDev &vw = views[i % nviews];
-        const CamDev &cam = vw.cam;
-        TileGeom<float> g;
-        load_tile_geom(recs + (size_t)i * kRecQuads, culls + (size_t)i * kCullQuads, g);
-        const float tau = recs[(size_t)i * kRecQuads + 6].y;
-        for (int ty = rc.z; ty < rc.w; ++ty)
-            for (int tx = rc.x; tx < rc.y; ++tx) {
-                ++ntests;
-                if (!tile_cull || tile_keep(g, tx, ty, tau, cam)) {
-                    if (WRITE) {
-                        uint64_t slot = base + my_count;
-                        if (slot < max_pairs) {
-                            uint32_t tile = (uint32_t)(vw.tile_base + ty * cam.tiles_x + tx);
-                            keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(g, tx, ty));
-                            vals[slot] = (uint32_t)(i / nviews);
-                        }
-                    }
-                    ++my_count;
-                }
-            }
-        if (!WRITE) counts[i] = my_count;
-    }
-    // big rectangles: the whole wave walks each one in turn
-    uint64_t bigmask = __ballot(big);
-    while (bigmask) {
-        const int src = __ffsll((unsigned long long)bigmask) - 1;
-        bigmask &= bigmask - 1;
-        const int64_t j = __shfl(i, src);
-        const int4 r = make_int4(__shfl(rc.x, src), __shfl(rc.y, src), __shfl(rc.z, src), __shfl(rc.w, src));
-        const uint64_t jbase = WRITE ? (uint64_t)__shfl((long long)base, src) : 0ull;
-        const ViewDev &vw = views[j % nviews];
-        const CamDev &cam = vw.cam;
-        TileGeom<float> g;
-        load_tile_geom(recs + (size_t)j * kRecQuads, culls + (size_t)j * kCullQuads, g);
-        const float tau = recs[(size_t)j * kRecQuads + 6].y;
+    const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
+    const int lane = (int)__lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long n_first = 0, n_tests = 0;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); t0 < C; t0 += stride) {
+        const uint64_t t = t0 + (uint64_t)lane;
+        const bool valid = t < C;
+        const uint64_t tq = valid ? t : C - 1;
+        // largest g with area_off[g] <= tq (its area is then > 0)
+        int64_t lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo + 1) / 2;
+            if (area_off[mid] <= tq)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t g = lo;
+        const uint64_t g0 = area_off[g], g1 = area_off[g + 1];
+        const int j = (int)(tq - g0);
+        const int4 r = rects[g];
         const int w = r.y - r.x;
-        const int tot = w * (r.w - r.z);
-        uint32_t running = 0;
-        for (int t0 = 0; t0 < tot; t0 += 64) {
-            const int t = t0 + (int)__lane_id();
-            bool keep = false;
-            int tx = 0, ty = 0;
-            if (t < tot) {
-                tx = r.x + t % w;
-                ty = r.z + t / w;
-                ++ntests;
-                keep = !tile_cull || tile_keep(g, tx, ty, tau, cam);
-            }
-            uint64_t m = __ballot(keep);
-            if (WRITE && keep) {
-                uint64_t slot = jbase + running + __popcll(m & lane_mask_lt());
+        const int tx = r.x + j % w, ty = r.z + j / w;
+        const ViewDev &vw = views[g % nviews];
+        TileGeom<float> geo;
+        load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
+        const float tau = recs[(size_t)g * kRecQuads + 6].y;
+        const bool keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
+        // this item's lanes in the wave: [s0, s1)
+        const int s0 = g0 > t0 ? (int)(g0 - t0) : 0;
+        const int s1 = g1 - t0 < 64 ? (int)(g1 - t0) : 64;
+        const uint64_t seg = (s1 >= 64 ? ~0ull : ((1ull << s1) - 1ull)) & ~bits_below(s0);
+        const uint64_t km = __ballot(keep) & seg;
+        const uint32_t nk = (uint32_t)__popcll(km);
+        if (!WRITE) {
+            if (valid && lane == s0 && nk) atomicAdd(&counts[g], nk);
+            n_tests += valid ? 1 : 0;
+            n_first += (valid && j == 0) ? 1 : 0;
+        } else {
+            uint32_t base = 0;
+            if (valid && lane == s0 && nk) base = atomicSub(&counts[g], nk) - nk;
+            base = (uint32_t)__shfl((int)base, s0);
+            if (keep) {
+                const uint64_t slot = offsets[g] + base + (uint64_t)__popcll(km & bits_below(lane));
                 if (slot < max_pairs) {
-                    uint32_t tile = (uint32_t)(vw.tile_base + ty * cam.tiles_x + tx);
-                    keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(g, tx, ty));
-                    vals[slot] = (uint32_t)(j / nviews);
+                    const uint32_t tile = (uint32_t)(vw.tile_base + ty * vw.cam.tiles_x + tx);
+                    keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(geo, tx, ty));
+                    vals[slot] = (uint32_t)(g / nviews);
                 }
             }
-            running += (uint32_t)__popcll(m);
         }
-        if (!WRITE && (int)__lane_id() == src) counts[j] = running;
     }
-    if (!WRITE && i < n && !live) counts[i] = 0;
     if (!WRITE && tests) {
-        // one atomic per wave: tests[0] += visible Gaussians, tests[1] += tile tests
-        unsigned long long v = ntests, c = live ? 1ull : 0ull;
+        // one atomic per wave: tests[0] += visible items, tests[1] += tile tests
         for (int off = 32; off > 0; off >>= 1) {
-            v += __shfl_down(v, off);
-            c += __shfl_down(c, off);
+            n_tests += __shfl_down(n_tests, off);
+            n_first += __shfl_down(n_first, off);
         }
-        if (__lane_id() == 0) {
-            if (c) atomicAdd(&tests[0], c);
-            if (v) atomicAdd(&tests[1], v);
+        if (lane == 0) {
+            if (n_first) atomicAdd(&tests[0], n_first);
+            if (n_tests) atomicAdd(&tests[1], n_tests);
         }
     }
 }
@@ -226,27 +214,27 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 
 }  // namespace
 
-hipError_t launch_count_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
+hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
+                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               unsigned long long *tests, hipStream_t s)
 {
-    const int64_t items = n * nviews;
     if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<false>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, status, rect, rec, cull,
-                       items, views, nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0,
-                       (uint64_t *)nullptr, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 1024)), dim3(256), 0, s,
+                       counts, items);
+    hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
+                       nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0, (uint64_t *)nullptr,
+                       (uint32_t *)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_write_pairs(const int32_t *status, const int4 *rect, const float4 *rec, const float4 *cull, int64_t n,
-                              const ViewDev *views, int nviews, bool tile_cull, const uint64_t *offsets,
-                              uint64_t max_pairs, uint64_t *keys, uint32_t *vals, hipStream_t s)
+hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
+                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
+                              const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
+                              hipStream_t s)
 {
-    const int64_t items = n * nviews;
     if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<true>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, status, rect, rec, cull,
-                       items, views, nviews, tile_cull, (uint32_t *)nullptr, (unsigned long long *)nullptr, offsets,
-                       max_pairs, keys, vals);
+    hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
+                       nviews, tile_cull, counts, (unsigned long long *)nullptr, offsets, max_pairs, keys, vals);
     return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     const ViewDev &vw = a.views[v];
     const int64_t n = a.n;
     a.rect[item] = make_int4(0, 0, 0, 0);
+    a.area[item] = 0u;
     Setup S;
     const int st0 = setup_gaussian(a, i, vw, S);
     if (st0 != kVisible) {
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     cu[6] = make_float4(g.qy0[2], g.qy1[0], g.qy1[1], g.qy1[2]);
     cu[7] = make_float4(muv[0], muv[1], muv[2], 0.f);
     a.rect[item] = make_int4(x0, x1, y0, y1);
+    a.area[item] = (uint32_t)((x1 - x0) * (y1 - y0));
     a.status[item] = kVisible;
 }
 
