@@ -23,10 +23,10 @@
  *     per-ray window keyed by the per-pixel depth of maximum response.
  *   - Front-to-back alpha blending with early termination (3DGS lineage).
  *
- * Readings where the paper is silent are listed in the design doc and restated at
- * each use below.  Candidate lists are a conservative bounding sphere (its own
- * acceleration); extra candidates are filtered out by the per-pixel test and
- * cannot change the result.
+ * Where the paper is silent, the reading taken is stated at its use below.
+ * Candidate lists are a conservative bounding sphere (its own acceleration);
+ * extra candidates are filtered out by the per-pixel test and cannot change
+ * the result.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1153,4 +1153,45 @@ int or_prepare_values(const or_scene *sc, const or_camera *cam, const or_setting
     out16[12] = g.alpha_t;
     for (int k = 0; k < 3; ++k) out16[13 + k] = g.color[k];
     return g.status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Training sampling frequency (Sec. 3.2): the filter's stored per-Gaussian
+ * maximum of f / d over the N_c training cameras, f the focal length in
+ * pixels, d the view-space depth of the mean; Eq.(13) clamps the render-time
+ * frequency to it.  Reading: a camera counts when the mean lies in front of
+ * its near plane and projects inside the image (border included); when no
+ * camera sees the mean, every camera with depth > znear counts; with none of
+ * those either the value is +inf (no clamp).  f = fx.
+ * Arithmetic order (fixed; the oracle is built without fused multiply-add):
+ * X = ((R0 mu0 + R1 mu1) + R2 mu2) + t per row, x = cx + (fx X0) / z,
+ * y = cy + (fy X1) / z, v = fx / z.
+ * flags[i] = 1 when a frustum decision of some camera lies within 1e-9
+ * (relative to the image size or znear) of its boundary. */
+void or_training_frequency(const double *means, int64_t n, int ncam, const or_camera *cams, double *out,
+                           uint8_t *flags)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double mu[3] = {means[i], means[n + i], means[2 * n + i]};
+        double best_in = 0.0, best_any = 0.0;
+        int near_edge = 0;
+        for (int c = 0; c < ncam; ++c) {
+            const double *V = cams[c].viewmat;
+            double X[3];
+            for (int r = 0; r < 3; ++r) X[r] = ((V[4 * r] * mu[0] + V[4 * r + 1] * mu[1]) + V[4 * r + 2] * mu[2]) + V[4 * r + 3];
+            const double z = X[2], zn = cams[c].znear;
+            if (fabs(z - zn) <= 1e-9 * fmax(1.0, zn)) near_edge = 1;
+            if (!(z > zn)) continue;
+            const double x = cams[c].cx + (cams[c].fx * X[0]) / z, y = cams[c].cy + (cams[c].fy * X[1]) / z;
+            const double v = cams[c].fx / z;
+            const double W = cams[c].width, H = cams[c].height;
+            if (fabs(x) <= 1e-9 * W || fabs(x - W) <= 1e-9 * W || fabs(y) <= 1e-9 * H || fabs(y - H) <= 1e-9 * H)
+                near_edge = 1;
+            if (v > best_any) best_any = v;
+            if (x >= 0.0 && x <= W && y >= 0.0 && y <= H && v > best_in) best_in = v;
+        }
+        out[i] = best_in > 0.0 ? best_in : (best_any > 0.0 ? best_any : INFINITY);
+        if (flags) flags[i] = (uint8_t)near_edge;
+    }
 }

@@ -30,10 +30,11 @@ BAND_T = 1e-3
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    """Compile the oracle with gcc (-O2, no fast-math, no fused multiply-add, OpenMP)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-o", tmp,
+                               SRC, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -294,3 +295,18 @@ def render_backward(scene, cam, settings, dL_drgb) -> GradResult:
                               _p(gl), _p(gq), _p(go), _p(gs))
     assert rc == 0
     return GradResult(rgb, T, flags, gm, gl, gq, go, gs)
+
+
+def training_frequency(means, cams):
+    """Training sampling frequency per Gaussian (Sec. 3.2): the maximum of
+    fx / depth over the cameras that see the mean (fallback: cameras with the
+    mean in front of the near plane; else +inf).  Returns (values float64 [n],
+    flags uint8 [n]); a flag marks a frustum decision within 1e-9 of its
+    boundary."""
+    m = _f64(means)
+    n = m.shape[1]
+    arr = (_Camera * max(len(cams), 1))(*[_camera(c) for c in cams])
+    out = np.empty(n, np.float64)
+    fl = np.zeros(n, np.uint8)
+    lib().or_training_frequency(_p(m), C.c_int64(n), C.c_int(len(cams)), arr, _p(out), _p(fl))
+    return out, fl
