@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rates", type=str, default="100,200")
+    ap.add_argument("--suite", action="store_true",
+                    help="also time the other workloads: 500k 1080p, 3M 2064x2208 120deg with its zoom sweep, "
+                         "1M 1280x720 16-view forward+backward steps (adds a few minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -213,6 +216,9 @@ def main():
                 print(f"# serving {mode} {rate}: {serving[f'{mode}@{int(rate)}']}", file=sys.stderr, flush=True)
         res["serving"] = serving
 
+    if args.suite:
+        res["suite"] = run_suite(ras, st, args)
+
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         k = max(1, args.cpu_poses)
@@ -225,6 +231,77 @@ def main():
                                "sample": f"{k} full 1920x1080 frames (poses 0..{k - 1}) of the same 1M scene, "
                                          f"FP64 oracle, {cpu_s:.1f}s wall"}
     print(json.dumps(res), flush=True)
+
+
+def _time_frames(ras, ds, cams, st, steps, warmup):
+    """Forward frames over `cams` (cycled): frames/s, per-stage ms (HIP events)."""
+    import torch
+    for k in range(warmup):
+        ras.render(ds, cams[k % len(cams)], st)
+    torch.cuda.synchronize()
+    ras.stage_times(reset=True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ras.render(ds, cams[k % len(cams)], st, timing=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, frames = ras.stage_times(reset=True)
+    _, _, s0 = ras.render(ds, cams[0], st, stats=True)
+    c = cams[0]
+    return {"frames_per_s": round(steps / el, 3), "ms_per_frame": round(1000 * el / steps, 4),
+            "mpix_per_s": round(steps / el * c.width * c.height / 1e6, 2),
+            "stages_ms": {k: round(v / frames, 4) for k, v in ms.items()},
+            "pairs": int(s0.pairs), "evaluations": int(s0.evaluations), "contributors": int(s0.contributors)}
+
+
+def run_suite(ras, st, args):
+    """The other workloads of the benchmark family, each timed on its own."""
+    import torch
+    from paper_2504_12811_amd import scenes as S
+    from paper_2504_12811_amd.render import DeviceScene
+    out = {}
+    # 500k Gaussians, 1920x1080, 60 deg, the 32 poses
+    scene, cams = S.medium()
+    ds = DeviceScene.from_host(scene, "cuda:0")
+    out["500k_1080p"] = _time_frames(ras, ds, cams, st, steps=64, warmup=8)
+    print(f"# suite 500k: {out['500k_1080p']}", file=sys.stderr, flush=True)
+    del ds
+    # 3M Gaussians (10% straddling the near plane), 2064x2208, 120 deg; zoom sweep 2x..64x scene radius
+    scene, cam, zoom = S.ood_scene()
+    ds = DeviceScene.from_host(scene, "cuda:0")
+    out["3M_2064x2208_120deg"] = _time_frames(ras, ds, [cam], st, steps=8, warmup=2)
+    print(f"# suite 3M primary: {out['3M_2064x2208_120deg']}", file=sys.stderr, flush=True)
+    sweep = []
+    for z in zoom:
+        r = _time_frames(ras, ds, [z], st, steps=8, warmup=2)
+        sweep.append({"distance": round(float(np.linalg.norm(z.position)), 2), **r})
+        print(f"# suite 3M zoom {sweep[-1]['distance']}: {r['frames_per_s']} fps", file=sys.stderr, flush=True)
+    out["3M_zoom_sweep"] = sweep
+    del ds
+    # 1M Gaussians, 1280x720, 70 deg: one step = 16 views forward (one batch), L1 loss, 16 views backward
+    scene, cams = S.fwd_bwd_scene()
+    ds = DeviceScene.from_host(scene, "cuda:0")
+    target = torch.from_numpy(S.noise_target(720, 1280)).to("cuda:0")
+
+    def step():
+        rgbs, _, _ = ras.render_batch(ds, cams, st)
+        grads = [torch.sign(r - target) / (r.numel() * len(cams)) for r in rgbs]
+        return ras.backward_batch(ds, cams, st, ras.last_ws, rgbs, grads)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    n_steps = 6
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["1M_720p_16view_fwd_bwd"] = {"steps_per_s": round(n_steps / el, 3), "ms_per_step": round(1000 * el / n_steps, 3),
+                                     "views_per_s": round(16 * n_steps / el, 2), "views_per_step": 16,
+                                     "loss": "L1 vs seeded U[0,1] noise image"}
+    print(f"# suite 720p fwd+bwd: {out['1M_720p_16view_fwd_bwd']}", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

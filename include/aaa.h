@@ -118,6 +118,9 @@ typedef struct {
     uint64_t contributors;   /* evaluations that passed the contribution test (AAA_STATS) */
     uint64_t candidate_tiles;/* tile tests executed by the pair emitter (AAA_STATS) */
     uint64_t near;           /* evaluations that passed the rho^2 prefilter (AAA_STATS) */
+    uint64_t wave_steps;     /* list entries visited by 64-pixel wavefronts of the blend (AAA_STATS) */
+    uint64_t wave_near_steps;    /* ... of which some pixel passed the prefilter (AAA_STATS) */
+    uint64_t wave_contrib_steps; /* ... of which some pixel had a contribution (AAA_STATS) */
 } aaa_stats;
 
 /* Stages timed under AAA_TIMING, in launch order. */
@@ -227,6 +230,28 @@ int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_p
 int aaa_sort_tmp_size(uint64_t n, size_t *bytes_out);
 int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits, void *tmp, size_t tmp_bytes,
                    void *stream);
+
+/* ---- training sampling frequency (K7) ---------------------------------- */
+
+#define AAA_MAX_TRAIN_CAMERAS 4096
+
+/* The 3D smoothing filter's stored per-Gaussian frequency (Sec. 3.2: the
+ * maximum of f / d over the N_c training cameras, f the focal length in
+ * pixels, d the view-space depth of the mean; Eq. 13 clamps the render-time
+ * frequency to it).  A camera counts when the mean lies in front of its near
+ * plane and projects inside the image (border included); when no camera sees
+ * the mean, every camera with the mean in front of the near plane counts;
+ * with none of those the value is +inf (no clamp).  f = fx.
+ * means: [3][n] DEVICE float32 (read).  cams: HOST array of n_cams
+ * (0..AAA_MAX_TRAIN_CAMERAS) cameras; viewmat, fx, fy, cx, cy, width, height
+ * and znear are used.  v_train: [n] DEVICE float32, written (it may be passed
+ * as aaa_scene.v_train afterwards).  FP64 with a fixed operation order and no
+ * fused multiply-add, rounded to float once, so the result is reproducible
+ * bit for bit.  The camera table goes through the context's pinned staging;
+ * the call synchronises `stream`.  Errors: AAA_ERR_INVALID for null pointers,
+ * n < 0, too many cameras or an invalid camera. */
+int aaa_training_frequency(aaa_ctx *ctx, const float *means, int64_t n, const aaa_camera *cams, int n_cams,
+                           void *stream, float *v_train);
 
 #ifdef __cplusplus
 }

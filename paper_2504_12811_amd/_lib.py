@@ -14,13 +14,14 @@ LIB_PATH = os.path.join(HERE, "libaaa_hip.so")
 
 AAA_OK, AAA_ERR_INVALID, AAA_ERR_WORKSPACE, AAA_ERR_PAIR_OVERFLOW, AAA_ERR_HIP, AAA_ERR_UNSUPPORTED = range(6)
 AAA_FILTER_OFF, AAA_FILTER_VOLUME, AAA_NO_TILE_CULL, AAA_STATS, AAA_TIMING = 1, 2, 4, 8, 16
+AAA_MAX_TRAIN_CAMERAS = 4096
 STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "frame"]
 
 # Every symbol include/aaa.h declares (checked by the ABI test).
 EXPORTS = [
     "aaa_create", "aaa_destroy", "aaa_last_error", "aaa_version", "aaa_workspace_size", "aaa_render",
     "aaa_stage_times", "aaa_workspace_size_batch", "aaa_render_batch", "aaa_render_backward_batch",
-    "aaa_backward_scratch_size",
+    "aaa_backward_scratch_size", "aaa_training_frequency",
     "aaa_render_backward", "aaa_read_gaussians", "aaa_read_pairs", "aaa_sort_tmp_size", "aaa_sort_pairs",
 ]
 
@@ -55,7 +56,8 @@ class Settings(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("pairs", C.c_uint64), ("visible", C.c_uint64), ("evaluations", C.c_uint64),
-                ("contributors", C.c_uint64), ("candidate_tiles", C.c_uint64), ("near", C.c_uint64)]
+                ("contributors", C.c_uint64), ("candidate_tiles", C.c_uint64), ("near", C.c_uint64),
+                ("wave_steps", C.c_uint64), ("wave_near_steps", C.c_uint64), ("wave_contrib_steps", C.c_uint64)]
 
 
 _lib = None
@@ -81,6 +83,7 @@ def lib():
                                  vp, vp, vp, C.POINTER(Stats)]
         L.aaa_render_backward.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t,
                                           u64, vp, vp, vp, vp, C.c_size_t, C.POINTER(SceneGrad)]
+        L.aaa_training_frequency.argtypes = [vp, vp, C.c_int64, C.POINTER(Camera), C.c_int, vp, vp]
         L.aaa_backward_scratch_size.argtypes = [vp, C.POINTER(Scene), C.c_int, C.POINTER(Camera), C.POINTER(Settings),
                                                 vp, C.c_size_t, u64, vp, C.POINTER(C.c_size_t)]
         L.aaa_read_gaussians.argtypes = [C.POINTER(Scene), C.POINTER(Camera), u64, vp, C.c_size_t, vp, vp, vp, vp, vp,

@@ -205,6 +205,15 @@ struct PreArgs {
 };
 hipError_t launch_preprocess(const PreArgs &a, hipStream_t s);
 
+// One training camera of K7: world->view rows (3x4, row-major), intrinsics,
+// image size, near plane.
+struct TrainCam {
+    double V[12];
+    double fx, fy, cx, cy, w, h, znear;
+};
+hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams, int ncam, float *out,
+                             hipStream_t s);
+
 // Pair emission over the candidate tests numbered by area_off (exclusive
 // scan of the rectangle areas, items + 1 entries).  count: zeroes counts, then
 // adds the survivors per item.  write: takes slots by running counts down to 0.

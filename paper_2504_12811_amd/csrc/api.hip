@@ -231,6 +231,8 @@ struct aaa_ctx {
     int device;
     // pinned staging for the view table (copied to the workspace per call)
     aaa::ViewDev *views_host;
+    // training-camera table of K7: pinned staging and its device copy
+    aaa::TrainCam *train_host, *train_dev;
     // AAA_TIMING: two sets of stage events (frame i uses set i % 2); a set is
     // folded into the totals once a later frame has synchronised past it.
     static constexpr int kEvents = 9;
@@ -276,10 +278,17 @@ int aaa_create(aaa_ctx **out, int device)
     aaa_ctx *c = new aaa_ctx;
     c->device = device;
     c->views_host = nullptr;
+    c->train_host = nullptr;
+    c->train_dev = nullptr;
     hipError_t e = hipHostMalloc((void **)&c->views_host, sizeof(aaa::ViewDev) * kMaxViews, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->train_host, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->train_dev, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS);
     if (e != hipSuccess) {
+        if (c->views_host) (void)hipHostFree(c->views_host);
+        if (c->train_host) (void)hipHostFree(c->train_host);
         delete c;
-        return fail(AAA_ERR_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
+        return fail(AAA_ERR_HIP, "context allocation: %s", hipGetErrorString(e));
     }
     for (int s_ = 0; s_ < 2; ++s_) {
         c->pending[s_] = false;
@@ -287,6 +296,8 @@ int aaa_create(aaa_ctx **out, int device)
             e = hipEventCreate(&c->ev[s_][k]);
             if (e != hipSuccess) {
                 (void)hipHostFree(c->views_host);
+                (void)hipHostFree(c->train_host);
+                (void)hipFree(c->train_dev);
                 delete c;
                 return fail(AAA_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
             }
@@ -306,6 +317,8 @@ void aaa_destroy(aaa_ctx *ctx)
     for (int s_ = 0; s_ < 2; ++s_)
         for (int k = 0; k < aaa_ctx::kEvents; ++k) (void)hipEventDestroy(ctx->ev[s_][k]);
     (void)hipHostFree(ctx->views_host);
+    (void)hipHostFree(ctx->train_host);
+    (void)hipFree(ctx->train_dev);
     delete ctx;
 }
 
@@ -364,7 +377,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const int64_t n = scene->n;
     const int64_t ntiles = sh.total_tiles;
     const bool want_stats = (settings->flags & AAA_STATS) != 0;
-    unsigned long long *ctr = at<unsigned long long>(ws, L.hdr);  // [0] visible [1] tests [2] evals [3] contribs [4] near
+    unsigned long long *ctr = at<unsigned long long>(ws, L.hdr);  // [0] visible [1] tests [2] evals [3] contribs [4] near [5..7] wave steps
     const bool timing = (settings->flags & AAA_TIMING) != 0;
     hipEvent_t *ev = ctx->ev[ctx->cur];
     if (timing) {
@@ -454,7 +467,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     }
 #undef STAGE_MARK
     if (stats && want_stats) {
-        unsigned long long h[5];
+        unsigned long long h[8];
         HIP_TRY(hipMemcpyAsync(h, ctr, sizeof h, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         stats->visible = h[0];
@@ -462,6 +475,9 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
         stats->evaluations = h[2];
         stats->contributors = h[3];
         stats->near = h[4];
+        stats->wave_steps = h[5];
+        stats->wave_near_steps = h[6];
+        stats->wave_contrib_steps = h[7];
     }
     return AAA_OK;
 }
@@ -655,3 +671,36 @@ int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits_, 
 }
 
 }  // extern "C"
+
+int aaa_training_frequency(aaa_ctx *ctx, const float *means, int64_t n, const aaa_camera *cams, int n_cams,
+                           void *stream, float *v_train)
+{
+    if (!ctx || (n > 0 && (!means || !v_train)) || (n_cams > 0 && !cams))
+        return fail(AAA_ERR_INVALID, "null context, means, cameras or output");
+    if (n < 0) return fail(AAA_ERR_INVALID, "n must be >= 0");
+    if (n_cams < 0 || n_cams > AAA_MAX_TRAIN_CAMERAS)
+        return fail(AAA_ERR_INVALID, "n_cams %d not in 0..%d", n_cams, AAA_MAX_TRAIN_CAMERAS);
+    for (int c = 0; c < n_cams; ++c) {
+        int rc = check_camera(&cams[c]);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    for (int c = 0; c < n_cams; ++c) {
+        aaa::TrainCam &t = ctx->train_host[c];
+        for (int k = 0; k < 12; ++k) t.V[k] = cams[c].viewmat[k];
+        t.fx = cams[c].fx;
+        t.fy = cams[c].fy;
+        t.cx = cams[c].cx;
+        t.cy = cams[c].cy;
+        t.w = (double)cams[c].width;
+        t.h = (double)cams[c].height;
+        t.znear = cams[c].znear;
+    }
+    if (n_cams > 0)
+        HIP_TRY(hipMemcpyAsync(ctx->train_dev, ctx->train_host, sizeof(aaa::TrainCam) * n_cams, hipMemcpyHostToDevice, s));
+    HIP_TRY(aaa::launch_train_freq(means, n, ctx->train_dev, n_cams, v_train, s));
+    // the pinned staging is reused by the next call
+    HIP_TRY(hipStreamSynchronize(s));
+    return AAA_OK;
+}

@@ -196,6 +196,7 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     }
     uint32_t consumed = 0, rank = 0;
     uint32_t n_eval = 0, n_near = 0;
+    uint32_t w_steps = 0, w_near = 0, w_contrib = 0;  // wave-uniform
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
 
     for (uint32_t i = start; i < end; ++i) {
@@ -204,6 +205,7 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
         const float4 *r = rec + (size_t)id * kRecQuads;
         const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
         if (STATS && !ps.done) ++n_eval;
+        if (STATS) ++w_steps;
         const float dx = fxp - q5.y, dy = fyp - q5.z;
         const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
         const bool near = !ps.done && e.N <= q6.x * e.D;
@@ -211,12 +213,14 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
         // ever updated with all lanes active (no divergent copies)
         if (__builtin_amdgcn_ballot_w64(near) == 0ull) continue;
         if (STATS && near) ++n_near;
+        if (STATS) ++w_near;
         const float inv = __builtin_amdgcn_rcpf(e.D);
         const float rho2 = e.N * inv;
         const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
         const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
         const bool contrib = near && al >= amin && z >= znear;
         if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) continue;
+        if (STATS) ++w_contrib;
         const uint32_t my_rank = rank;
         if (contrib) ++rank;
         if constexpr (K == 0) {
@@ -285,6 +289,9 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
             atomicAdd(&a.counters[0], e);
             atomicAdd(&a.counters[1], c);
             atomicAdd(&a.counters[2], nr);
+            atomicAdd(&a.counters[3], (unsigned long long)w_steps);
+            atomicAdd(&a.counters[4], (unsigned long long)w_near);
+            atomicAdd(&a.counters[5], (unsigned long long)w_contrib);
         }
     }
 }

@@ -230,6 +230,18 @@ class Rasterizer:
                                             scr, nscr, C.byref(g)))
         return grads
 
+    def training_frequency(self, means: torch.Tensor, cams) -> torch.Tensor:
+        """Per-Gaussian training sampling frequency over `cams` (float32 [n]);
+        means: device float32 [3, n]."""
+        m = means.contiguous().float()
+        assert m.is_cuda and m.dim() == 2 and m.shape[0] == 3
+        n = m.shape[1]
+        out = torch.empty(n, dtype=torch.float32, device=m.device)
+        arr = (L.Camera * max(len(cams), 1))(*[L.make_camera(c) for c in cams])
+        L.check(L.lib().aaa_training_frequency(self._ctx, m.data_ptr(), n, arr, len(cams), _stream_ptr(self.device),
+                                               out.data_ptr()))
+        return out
+
     def stage_times(self, reset: bool = True):
         """(dict stage -> accumulated ms, frames) of the renders made with timing=True."""
         ms = (C.c_double * len(L.STAGES))()
