@@ -2,8 +2,10 @@
 gradient (itself pinned to central differences), through the C ABI and the
 autograd wrapper.  dL/drgb is zeroed at pixels the oracle flags, so that
 both sides differentiate the same blend order.  Bar: per parameter group,
-max |g_gpu - g_oracle| <= 2e-3 * max |g_oracle| (FP32 record arithmetic and
-atomic accumulation)."""
+max |g_gpu - g_oracle| <= 1e-4 * max |g_oracle|: the record gradients are
+FP32 sums of up to ~10^4 terms per Gaussian accumulated by atomics in any
+order (relative rounding ~ sqrt(terms) * 6e-8 ≈ 1e-5 at worst), then an FP64
+chain; the measured worst case is ~4e-6."""
 import numpy as np
 import pytest
 import torch
@@ -22,7 +24,7 @@ def ras():
     return Rasterizer(0)
 
 
-def compare_grads(ras, scene, cam, st, seed=0, label="", tol=2e-3):
+def compare_grads(ras, scene, cam, st, seed=0, label="", tol=1e-4):
     from paper_2504_12811_amd.render import DeviceScene
     rng = np.random.default_rng(seed)
     g = rng.normal(size=(3, cam.height, cam.width))
@@ -105,7 +107,7 @@ def test_autograd_l1_loss(ras):
     for k in GROUPS:
         a = p[k].grad.cpu().numpy().astype(np.float64)
         b = getattr(ref, k)
-        assert np.abs(a - b).max() <= 2e-3 * np.abs(b).max() + 1e-9, k
+        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max() + 1e-9, k
 
 
 def test_backward_twice_is_deterministic_up_to_atomics(ras):
