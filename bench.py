@@ -40,6 +40,34 @@ FLOPS_CONTRIB_BASE = 10
 # 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6
 PEAK_HBM_GBS = 8000.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_blend_1M_1080p_counters.txt")
+BLEND_SRC = os.path.join(ROOT, "paper_2504_12811_amd", "csrc", "blend.hip")
+
+
+def blend_traffic_bytes():
+    """HBM bytes per blend launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
+    counter reads for a copy of known size), or None when the summary is
+    missing or was taken on a different blend source."""
+    import hashlib
+    try:
+        kv = {}
+        with open(COUNTERS_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(BLEND_SRC, "rb") as f:
+            sha = hashlib.sha1(f.read()).hexdigest()
+        if kv.get("source_sha1") != sha:
+            return None
+        probe = float(kv["copy_probe_bytes"])
+        f_scale = probe / (float(kv["copy_fetch_kib"]) * 1024.0)
+        w_scale = probe / (float(kv["copy_write_kib"]) * 1024.0)
+        return (float(kv["fetch_kib_per_dispatch"]) * 1024.0 * f_scale
+                + float(kv["write_kib_per_dispatch"]) * 1024.0 * w_scale)
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -58,8 +86,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rates", type=str, default="100,200")
     ap.add_argument("--suite", action="store_true",
-                    help="also time the other workloads: 500k 1080p, 3M 2064x2208 120deg with its zoom sweep, "
-                         "1M 1280x720 16-view forward+backward steps (adds a few minutes)")
+                    help="also time the ablations (no tile culling, no per-ray window) and the other workloads: "
+                         "500k 1080p, 3M 2064x2208 120deg with its zoom sweep, 1M 1280x720 16-view training "
+                         "steps (adds a few minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -155,7 +184,8 @@ def main():
             "peak": round(PEAK_VALU_TFLOPS, 1),
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
-            "traffic": None,
+            "traffic": (lambda b: None if b is None else round(b))(blend_traffic_bytes()),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_ms": round(blend_ms, 4),
             "flops_per_launch": flops,
         },
@@ -260,6 +290,25 @@ def run_suite(ras, st, args):
     from paper_2504_12811_amd import scenes as S
     from paper_2504_12811_amd.render import DeviceScene
     out = {}
+    # ablations of Tab. 5 on the headline scene: without 3D tile culling
+    # (rectangles only) and without the per-ray window (K = 0: tile order)
+    scene, cams = S.headline()
+    ds = DeviceScene.from_host(scene, "cuda:0")
+    full = _time_frames(ras, ds, cams, st, steps=32, warmup=4)
+    no_cull = _time_frames(ras, ds, cams, S.Settings(ray_window=st.ray_window, tile_cull=False), steps=32, warmup=4)
+    no_sort = _time_frames(ras, ds, cams, S.Settings(ray_window=0), steps=32, warmup=4)
+    out["ablation_1M_1080p"] = {
+        "full_ms": full["ms_per_frame"], "no_tile_cull_ms": no_cull["ms_per_frame"],
+        "no_ray_window_ms": no_sort["ms_per_frame"],
+        "culling_speedup": round(no_cull["ms_per_frame"] / full["ms_per_frame"], 3),
+        "ray_window_cost": round(full["ms_per_frame"] / no_sort["ms_per_frame"], 3),
+        "pairs": {"full": full["pairs"], "no_tile_cull": no_cull["pairs"]},
+        "stages_ms": {"full": full["stages_ms"], "no_tile_cull": no_cull["stages_ms"],
+                      "no_ray_window": no_sort["stages_ms"]},
+        "paper_tab5_ratios": {"culling_speedup": [1.87, 2.16, 1.82, 1.53], "hier_sort_cost": [1.88, 1.69, 1.91, 1.67],
+                              "hardware": "RTX 4090, trained scenes"}}
+    print(f"# suite ablation: {out['ablation_1M_1080p']}", file=sys.stderr, flush=True)
+    del ds
     # 500k Gaussians, 1920x1080, 60 deg, the 32 poses
     scene, cams = S.medium()
     ds = DeviceScene.from_host(scene, "cuda:0")
@@ -278,15 +327,16 @@ def run_suite(ras, st, args):
         print(f"# suite 3M zoom {sweep[-1]['distance']}: {r['frames_per_s']} fps", file=sys.stderr, flush=True)
     out["3M_zoom_sweep"] = sweep
     del ds
-    # 1M Gaussians, 1280x720, 70 deg: one step = 16 views forward (one batch), L1 loss, 16 views backward
+    # 1M Gaussians, 1280x720, 70 deg: one training step = 16 views forward
+    # (one batch), L1 loss, 16 views backward, Adam update of every parameter
+    from paper_2504_12811_amd.train import Adam, train_step
     scene, cams = S.fwd_bwd_scene()
     ds = DeviceScene.from_host(scene, "cuda:0")
     target = torch.from_numpy(S.noise_target(720, 1280)).to("cuda:0")
+    opt = Adam(ds)
 
     def step():
-        rgbs, _, _ = ras.render_batch(ds, cams, st)
-        grads = [torch.sign(r - target) / (r.numel() * len(cams)) for r in rgbs]
-        return ras.backward_batch(ds, cams, st, ras.last_ws, rgbs, grads)
+        return train_step(ras, ds, cams, [target] * len(cams), st, opt)
 
     for _ in range(2):
         step()
@@ -299,7 +349,7 @@ def run_suite(ras, st, args):
     el = time.perf_counter() - t0
     out["1M_720p_16view_fwd_bwd"] = {"steps_per_s": round(n_steps / el, 3), "ms_per_step": round(1000 * el / n_steps, 3),
                                      "views_per_s": round(16 * n_steps / el, 2), "views_per_step": 16,
-                                     "loss": "L1 vs seeded U[0,1] noise image"}
+                                     "loss": "L1 vs seeded U[0,1] noise image", "optimizer": "Adam (fused kernel)"}
     print(f"# suite 720p fwd+bwd: {out['1M_720p_16view_fwd_bwd']}", file=sys.stderr, flush=True)
     return out
 

@@ -253,6 +253,19 @@ int aaa_sort_pairs(uint64_t *keys, uint32_t *values, uint64_t n, int key_bits, v
 int aaa_training_frequency(aaa_ctx *ctx, const float *means, int64_t n, const aaa_camera *cams, int n_cams,
                            void *stream, float *v_train);
 
+/* ---- optimiser step of a training step ---------------------------------- */
+
+/* Adam with bias correction (Kingma & Ba, Algorithm 1), in place on n float32
+ * parameters (DEVICE arrays param, m, v updated; grad read):
+ *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+ *   param -= lr (m / c1) / (sqrt(v / c2) + eps),  c1 = 1 - b1^step,
+ *   c2 = 1 - b2^step (computed in double on the host, applied in float).
+ * step counts from 1.  Enqueued on `stream` (no synchronisation).  Errors:
+ * AAA_ERR_INVALID for n < 0, null arrays, step < 1, betas outside [0, 1)
+ * or eps <= 0. */
+int aaa_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, int64_t step, double lr, double beta1,
+                  double beta2, double eps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -310,3 +310,14 @@ def training_frequency(means, cams):
     fl = np.zeros(n, np.uint8)
     lib().or_training_frequency(_p(m), C.c_int64(n), C.c_int(len(cams)), arr, _p(out), _p(fl))
     return out, fl
+
+
+def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-15):
+    """Adam with bias correction (Kingma & Ba, Algorithm 1), FP64: returns the
+    new (p, m, v) for step t (counting from 1)."""
+    p, g, m, v = (np.asarray(a, np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -21,7 +21,7 @@ STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "fr
 EXPORTS = [
     "aaa_create", "aaa_destroy", "aaa_last_error", "aaa_version", "aaa_workspace_size", "aaa_render",
     "aaa_stage_times", "aaa_workspace_size_batch", "aaa_render_batch", "aaa_render_backward_batch",
-    "aaa_backward_scratch_size", "aaa_training_frequency",
+    "aaa_backward_scratch_size", "aaa_training_frequency", "aaa_adam_step",
     "aaa_render_backward", "aaa_read_gaussians", "aaa_read_pairs", "aaa_sort_tmp_size", "aaa_sort_pairs",
 ]
 
@@ -83,6 +83,8 @@ def lib():
                                  vp, vp, vp, C.POINTER(Stats)]
         L.aaa_render_backward.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t,
                                           u64, vp, vp, vp, vp, C.c_size_t, C.POINTER(SceneGrad)]
+        L.aaa_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, vp]
         L.aaa_training_frequency.argtypes = [vp, vp, C.c_int64, C.POINTER(Camera), C.c_int, vp, vp]
         L.aaa_backward_scratch_size.argtypes = [vp, C.POINTER(Scene), C.c_int, C.POINTER(Camera), C.POINTER(Settings),
                                                 vp, C.c_size_t, u64, vp, C.POINTER(C.c_size_t)]

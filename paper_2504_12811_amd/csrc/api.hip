@@ -704,3 +704,17 @@ int aaa_training_frequency(aaa_ctx *ctx, const float *means, int64_t n, const aa
     HIP_TRY(hipStreamSynchronize(s));
     return AAA_OK;
 }
+
+int aaa_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, int64_t step, double lr, double beta1,
+                  double beta2, double eps, void *stream)
+{
+    if (n < 0) return fail(AAA_ERR_INVALID, "n must be >= 0");
+    if (n > 0 && (!param || !grad || !m || !v)) return fail(AAA_ERR_INVALID, "null array");
+    if (step < 1) return fail(AAA_ERR_INVALID, "step must be >= 1");
+    if (!(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0))
+        return fail(AAA_ERR_INVALID, "need 0 <= beta1, beta2 < 1 and eps > 0");
+    const double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
+    HIP_TRY(aaa::launch_adam(param, grad, m, v, n, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                             (float)c2, (hipStream_t)stream));
+    return AAA_OK;
+}

@@ -6,7 +6,9 @@
 // Work split: the candidate (item, rectangle tile) tests are numbered through
 // an exclusive scan of the rectangle areas, and every lane takes one test
 // (grid-stride), so lanes stay busy whatever the mix of rectangle sizes.  A
-// lane finds its item by binary search over the area offsets.  The lanes of
+// lane finds its item in the area offsets: the wave brackets its 64
+// candidates with two cooperative 64-way searches, then each lane searches
+// the bracket held across the lanes.  The lanes of
 // one item inside a wave form a contiguous segment; its first lane adds the
 // segment's survivors to the item's count with one atomic.
 //
@@ -48,6 +50,32 @@ __device__ __forceinline__ float tile_depth(const TileGeom<float> &g, int tx, in
 
 __device__ __forceinline__ uint64_t bits_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const int lo = __shfl((int)(uint32_t)v, src), hi = __shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Largest g in [lo, hi] with off[g] <= target, for a wave-uniform target and
+// non-decreasing off with off[lo] <= target: each round every lane probes one
+// of 64 evenly spaced points and a ballot keeps the stretch between the last
+// probe at or below the target and the next probe (4 rounds for 10^6 items).
+__device__ __forceinline__ int64_t wave_search(const uint64_t *__restrict__ off, int64_t lo, int64_t hi,
+                                               uint64_t target, int lane)
+{
+    while (hi > lo) {
+        const int64_t step = (hi - lo + 64) / 64;
+        const int64_t p = lo + (int64_t)lane * step;
+        const bool le = p <= hi && off[p] <= target;
+        const uint64_t b = __ballot(le);  // lanes 0..k, lane 0 probes lo
+        const int k = 63 - __builtin_clzll(b);
+        lo = lo + (int64_t)k * step;
+        hi = lo + step - 1 < hi ? lo + step - 1 : hi;
+        if (step == 1) break;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(256) void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -73,16 +101,35 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         const uint64_t t = t0 + (uint64_t)lane;
         const bool valid = t < C;
         const uint64_t tq = valid ? t : C - 1;
-        // largest g with area_off[g] <= tq (its area is then > 0)
-        int64_t lo = 0, hi = nitems - 1;
-        while (lo < hi) {
-            const int64_t mid = lo + (hi - lo + 1) / 2;
-            if (area_off[mid] <= tq)
-                lo = mid;
-            else
-                hi = mid - 1;
+        // this lane's item: the largest g with area_off[g] <= tq (its area is
+        // then > 0).  The wave first brackets its 64 candidates with two
+        // 64-way searches, then each lane searches the bracket.
+        const uint64_t t_last = t0 + 63 < C ? t0 + 63 : C - 1;
+        const int64_t g_lo = wave_search(area_off, 0, nitems - 1, t0, lane);
+        const int64_t g_hi = wave_search(area_off, g_lo, nitems - 1, t_last, lane);
+        int64_t g;
+        if (g_hi - g_lo < 64) {
+            // bracket held across the lanes: lane k has area_off[g_lo + k]
+            const int64_t span = g_hi - g_lo + 1;
+            const uint64_t mine = lane < span ? area_off[g_lo + lane] : ~0ull;
+            int k = 0;
+            for (int half = 32; half >= 1; half >>= 1) {
+                const int q = k + half < 64 ? k + half : 63;
+                const uint64_t x = shfl_u64(mine, q);
+                if (k + half < span && x <= tq) k += half;
+            }
+            g = g_lo + k;
+        } else {
+            int64_t lo = g_lo, hi = g_hi;
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo + 1) / 2;
+                if (area_off[mid] <= tq)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            g = lo;
         }
-        const int64_t g = lo;
         const uint64_t g0 = area_off[g], g1 = area_off[g + 1];
         const int j = (int)(tq - g0);
         const int4 r = rects[g];

@@ -6,9 +6,10 @@
 // consecutive keys; each of its four wavefronts ranks a contiguous quarter in
 // rounds of 64 with a ballot-based match on the digit bits (lanes with equal
 // digits see each other through eight ballots), so the rank of a key is the
-// number of equal digits before it in its wave's segment.  Wave segments are
-// then offset by the counts of the earlier waves and by the global prefix of
-// the block.
+// number of equal digits before it in its wave's segment.  The block then
+// stages its pairs in LDS in digit order (wave order, then rank: stable) and
+// writes each digit's run to consecutive global positions from the digit's
+// global prefix, so stores coalesce.
 #include "aaa_internal.h"
 
 namespace aaa {
@@ -54,19 +55,24 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
                                                       const uint64_t *__restrict__ offsets, uint32_t nblocks,
                                                       uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
 {
-    __shared__ uint32_t cnt[4][kBins];
-    __shared__ uint32_t off[4][kBins];
-    const int t = threadIdx.x, wave = t >> 6;
+    __shared__ uint32_t cnt[4][kBins];   // per-wave digit counts, then per-wave prefixes
+    __shared__ uint32_t lbase[kBins];    // block-local start of each digit
+    __shared__ uint32_t wsum[4];
+    __shared__ uint64_t gbase[kBins];    // global start of each digit for this block
+    __shared__ uint64_t skey[kPerBlock];
+    __shared__ uint32_t sval[kPerBlock];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     for (int k = t; k < 4 * kBins; k += kThreads) (&cnt[0][0])[k] = 0;
     __syncthreads();
-    const uint64_t seg = (uint64_t)blockIdx.x * kPerBlock + (uint64_t)wave * kPerWave;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kPerBlock;
+    const uint64_t seg = b0 + (uint64_t)wave * kPerWave;
     const uint64_t lt = lanemask_lt();
     uint64_t key[kItems];
     uint32_t val[kItems], rank[kItems], dig[kItems];
     bool valid[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
-        uint64_t idx = seg + (uint64_t)r * 64 + __lane_id();
+        uint64_t idx = seg + (uint64_t)r * 64 + lane;
         valid[r] = idx < n;
         key[r] = valid[r] ? keys_in[idx] : 0ull;
         val[r] = valid[r] ? vals_in[idx] : 0u;
@@ -87,22 +93,44 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        uint64_t g = offsets[(uint64_t)t * nblocks + blockIdx.x];
-        uint32_t run = 0;
-        for (int w = 0; w < 4; ++w) {
-            off[w][t] = (uint32_t)(g + run);
-            run += cnt[w][t];
-        }
+    // digit t: prefixes over the waves, block total, global start
+    uint32_t tot = 0;
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t c = cnt[w][t];
+        cnt[w][t] = tot;
+        tot += c;
     }
+    gbase[t] = offsets[(uint64_t)t * nblocks + blockIdx.x];
+    // exclusive scan of the block totals over the 256 digits
+    uint32_t x = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    lbase[t] = wpre + x - tot;
+    __syncthreads();
+    // stage the block's pairs in digit order (stable: wave order, then rank)
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
         if (valid[r]) {
-            uint32_t pos = off[wave][dig[r]] + rank[r];
-            keys_out[pos] = key[r];
-            vals_out[pos] = val[r];
+            const uint32_t lp = lbase[dig[r]] + cnt[wave][dig[r]] + rank[r];
+            skey[lp] = key[r];
+            sval[lp] = val[r];
         }
+    }
+    __syncthreads();
+    // write runs of equal digits to consecutive global positions
+    const uint32_t nloc = (uint32_t)(n - b0 < (uint64_t)kPerBlock ? n - b0 : (uint64_t)kPerBlock);
+    for (uint32_t i = t; i < nloc; i += kThreads) {
+        const uint64_t k = skey[i];
+        const uint32_t d = (uint32_t)(k >> shift) & (kBins - 1);
+        const uint64_t pos = gbase[d] + (i - lbase[d]);
+        keys_out[pos] = k;
+        vals_out[pos] = sval[i];
     }
 }
 

@@ -1,6 +1,7 @@
-"""Pins of the oracle's training sampling frequency (Sec. 3.2: the maximum of
-f / d over the training cameras, d the view-space depth of the mean) on
-constructed cases whose answer follows from the definition by hand."""
+"""Pins of the oracle's training-side functions on constructed cases whose
+answer follows from the definition by hand: the training sampling frequency
+(Sec. 3.2: the maximum of f / d over the training cameras, d the view-space
+depth of the mean) and the Adam step's bias correction."""
 import numpy as np
 
 from oracle import oracle as O
@@ -80,3 +81,28 @@ def test_near_plane_and_border_decisions_are_flagged():
 def test_no_cameras_gives_infinity():
     v, _ = O.training_frequency(np.zeros((3, 3)), [])
     assert np.all(np.isinf(v))
+
+
+# ---------------------------------------------------------------------------
+# Adam (optimiser of the multi-view training step): bias-correction pins
+
+
+def test_adam_first_step_is_lr_times_sign():
+    g = np.array([3.0, -0.5, 1e-3, -7.0])
+    p, m, v = O.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.01, eps=0.0)
+    np.testing.assert_allclose(p, -0.01 * np.sign(g), rtol=1e-13)
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    g = np.array([2.0, -4.0])
+    p, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    for t in range(1, 30):
+        p_new, m, v = O.adam_step(p, g, m, v, t, lr=0.05, eps=0.0)
+        np.testing.assert_allclose(p_new - p, -0.05 * np.sign(g), rtol=1e-10)
+        p = p_new
+
+
+def test_adam_zero_gradient_keeps_parameters():
+    p0 = np.array([1.0, -2.0])
+    p, m, v = O.adam_step(p0, np.zeros(2), np.zeros(2), np.zeros(2), 1, lr=0.1, eps=1e-8)
+    assert np.array_equal(p, p0)
