@@ -259,7 +259,8 @@ int aaa_training_frequency(aaa_ctx *ctx, const float *means, int64_t n, const aa
  * parameters (DEVICE arrays param, m, v updated; grad read):
  *   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
  *   param -= lr (m / c1) / (sqrt(v / c2) + eps),  c1 = 1 - b1^step,
- *   c2 = 1 - b2^step (computed in double on the host, applied in float).
+ *   c2 = 1 - b2^step (c1, c2, 1 - b1 and 1 - b2 computed in double on the host,
+ *   then applied in float).
  * step counts from 1.  Enqueued on `stream` (no synchronisation).  Errors:
  * AAA_ERR_INVALID for n < 0, null arrays, step < 1, betas outside [0, 1)
  * or eps <= 0. */

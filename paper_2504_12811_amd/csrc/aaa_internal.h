@@ -211,8 +211,8 @@ struct TrainCam {
     double V[12];
     double fx, fy, cx, cy, w, h, znear;
 };
-hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, double lr, double b1, double b2,
+                       double eps, double c1, double c2, hipStream_t s);
 hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams, int ncam, float *out,
                              hipStream_t s);
 

@@ -13,13 +13,13 @@ namespace aaa {
 namespace {
 
 struct AdamK {
-    float lr, b1, b2, eps, c1, c2;
+    float lr, b1, b2, omb1, omb2, eps, c1, c2;  // omb = 1 - beta, rounded once from double
 };
 
 __device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, const AdamK &k)
 {
-    m = k.b1 * m + (1.0f - k.b1) * g;
-    v = k.b2 * v + (1.0f - k.b2) * (g * g);
+    m = k.b1 * m + k.omb1 * g;
+    v = k.b2 * v + k.omb2 * (g * g);
     const float mh = m / k.c1;
     const float vh = v / k.c2;
     p = p - k.lr * mh / (sqrtf(vh) + k.eps);
@@ -55,11 +55,13 @@ __global__ __launch_bounds__(256) void k_adam1(float *__restrict__ p, const floa
 
 }  // namespace
 
-hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2, hipStream_t s)
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, double lr, double b1, double b2,
+                       double eps, double c1, double c2, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    const AdamK k{lr, b1, b2, eps, c1, c2};
+    // 1 - beta from the double values: (1 - (float)0.999) would be off by 1e-5
+    const AdamK k{(float)lr, (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), (float)eps, (float)c1,
+                  (float)c2};
     const bool aligned = (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15) == 0;
     int64_t head = 0;
     if (aligned) {

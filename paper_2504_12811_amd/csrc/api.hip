@@ -714,7 +714,6 @@ int aaa_adam_step(float *param, const float *grad, float *m, float *v, int64_t n
     if (!(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0))
         return fail(AAA_ERR_INVALID, "need 0 <= beta1, beta2 < 1 and eps > 0");
     const double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
-    HIP_TRY(aaa::launch_adam(param, grad, m, v, n, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
-                             (float)c2, (hipStream_t)stream));
+    HIP_TRY(aaa::launch_adam(param, grad, m, v, n, lr, beta1, beta2, eps, c1, c2, (hipStream_t)stream));
     return AAA_OK;
 }

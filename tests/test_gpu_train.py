@@ -29,8 +29,9 @@ def test_adam_kernel_matches_oracle(n, offset):
         pr, mr, vr = O.adam_step(pr, g, mr, vr, t, lr, eps=1e-15)
     torch.cuda.synchronize()
     got = P.cpu().numpy().astype(np.float64)
-    # float32 state: each update carries a relative error of a few ulps, the
-    # parameter itself is rounded to float32 after every step
+    # float32 state: each update carries a relative error of a few ulps
+    # (<= 4e-6 * lr with margin), the parameter is rounded to float32 after
+    # every step (<= 6e-8 |p|, taken twice)
     err = np.abs(got - pr)
     bound = 3 * (4e-6 * lr + 1.2e-7 * np.abs(pr))
     print(f"n={n} max err {err.max():.3e}")
