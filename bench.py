@@ -78,13 +78,15 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--window", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-poses", type=int, default=4)
+    ap.add_argument("--cpu-poses", type=int, default=12)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed region, copy this many MiB once (counter calibration)")
     ap.add_argument("--bwd-steps", type=int, default=32)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-rates", type=str, default="100,200")
+    ap.add_argument("--serve-rates", type=str, default="50,100,200,400")
+    ap.add_argument("--serve-rates-single", type=str, default="50,100,200",
+                    help="rates for the one-request-at-a-time baseline (its queue only grows beyond ~60 req/s)")
     ap.add_argument("--suite", action="store_true",
                     help="also time the ablations (no tile culling, no per-ray window) and the other workloads: "
                          "500k 1080p, 3M 2064x2208 120deg with its zoom sweep, 1M 1280x720 16-view training "
@@ -233,7 +235,8 @@ def main():
         serving = {}
         for mode, (workers, maxb) in {"batched": (2, 8), "one_at_a_time": (1, 1)}.items():
             fn = gpu_render_batch(ds, st, n_workers=workers)
-            for rate in [float(r) for r in args.serve_rates.split(",")]:
+            rates = args.serve_rates if mode == "batched" else args.serve_rates_single
+            for rate in [float(r) for r in rates.split(",")]:
                 with Server(fn, n_gaussians=ds.n, mem_cap=16 << 30, max_batch=maxb, n_workers=workers) as srv:
                     run_load(srv, rate, 0.5, seed=99)  # warm-up (allocations, code paths)
                     lat, frames, wall, rej = run_load(srv, rate, args.serve_seconds, seed=int(rate))

@@ -405,7 +405,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *offsets = at<uint64_t>(ws, L.offsets);
     uint64_t *area_off = at<uint64_t>(ws, L.area_off);
     HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s));
-    HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts, ctr,
+    HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
+                                    want_stats ? ctr : nullptr,
                                     s));
     STAGE_MARK(2);
     HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, items, at<void>(ws, L.scan_tmp), s));
