@@ -249,9 +249,22 @@ struct BlendArgs {
     float *grad_rec;               // per item, kGradStride floats
     const uint64_t *pix_off;       // per pixel: first slot (exclusive scan of n_ins)
     float2 *slots;                 // per (pixel, contributor rank): dL/dalpha, T alpha
+    // forward only: tiles with longer lists are left to k_blend_long
+    uint32_t long_list;
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s);
+// Long tile lists: k_find_long collects tiles with more than a.long_list
+// entries (n_long must be zero beforehand); launch_blend_long computes the
+// per-pixel entry masks (pixmask: (pairs / 64 + tiles + 2) * 256 words;
+// summary: summary_words >= ((pairs / 64 + tiles + 2) / 64 + 1) * 256, zeroed
+// here) and renders those tiles with one walk per pixel (K <= 16).  grid: an
+// upper bound of the number of long tiles.
+hipError_t launch_find_long(const BlendArgs &a, uint32_t *long_tiles, uint32_t *n_long, hipStream_t s);
+hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32_t *long_tiles, const uint32_t *n_long,
+                             unsigned grid, uint64_t *pixmask, uint64_t *summary, uint64_t summary_words,
+                             hipStream_t s);
+constexpr uint32_t kLongList = 4096;  // entries above which a forward tile is rendered by k_blend_long
 
 struct GradOut {
     float *means, *log_scales, *quats, *logits, *sh;

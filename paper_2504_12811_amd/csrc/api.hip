@@ -70,8 +70,10 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 
 struct Layout {
     size_t hdr, views, status, rect, area, area_off, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
-        ranges, n_done, n_ins, pix_off, pix_scan_tmp, grad_rec, total;
+        ranges, long_tiles, masks, summary, n_done, n_ins, pix_off, pix_scan_tmp, grad_rec, total;
 };
+
+uint64_t summary_words(const Shape &sh, uint64_t mp) { return ((mp / 64 + (uint64_t)sh.total_tiles + 2) / 64 + 1) * 256; }
 
 Layout layout(const Shape &sh, uint64_t max_pairs)
 {
@@ -101,6 +103,9 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.vals_alt = take(mp * 4);
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
     L.ranges = take((size_t)sh.total_tiles * 8);
+    L.long_tiles = take((size_t)sh.total_tiles * 4);
+    L.masks = take((mp / 64 + (uint64_t)sh.total_tiles + 2) * 256 * 8);  // per-pixel masks of long lists
+    L.summary = take(summary_words(sh, mp) * 8);
     L.n_done = take((size_t)sh.total_pixels * 4);
     L.n_ins = take((size_t)sh.total_pixels * 4);
     L.pix_off = take(((size_t)sh.total_pixels + 1) * 8);
@@ -233,6 +238,10 @@ struct aaa_ctx {
     aaa::ViewDev *views_host;
     // training-camera table of K7: pinned staging and its device copy
     aaa::TrainCam *train_host, *train_dev;
+    // second stream for the long-list blend, forked from and joined back to
+    // the caller's stream with these events
+    hipStream_t side;
+    hipEvent_t fork, join;
     // AAA_TIMING: two sets of stage events (frame i uses set i % 2); a set is
     // folded into the totals once a later frame has synchronised past it.
     static constexpr int kEvents = 9;
@@ -280,13 +289,21 @@ int aaa_create(aaa_ctx **out, int device)
     c->views_host = nullptr;
     c->train_host = nullptr;
     c->train_dev = nullptr;
+    c->side = nullptr;
+    c->fork = c->join = nullptr;
     hipError_t e = hipHostMalloc((void **)&c->views_host, sizeof(aaa::ViewDev) * kMaxViews, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->train_host, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&c->train_dev, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (c->views_host) (void)hipHostFree(c->views_host);
         if (c->train_host) (void)hipHostFree(c->train_host);
+        if (c->train_dev) (void)hipFree(c->train_dev);
+        if (c->fork) (void)hipEventDestroy(c->fork);
+        if (c->side) (void)hipStreamDestroy(c->side);
         delete c;
         return fail(AAA_ERR_HIP, "context allocation: %s", hipGetErrorString(e));
     }
@@ -298,6 +315,9 @@ int aaa_create(aaa_ctx **out, int device)
                 (void)hipHostFree(c->views_host);
                 (void)hipHostFree(c->train_host);
                 (void)hipFree(c->train_dev);
+                (void)hipEventDestroy(c->fork);
+                (void)hipEventDestroy(c->join);
+                (void)hipStreamDestroy(c->side);
                 delete c;
                 return fail(AAA_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
             }
@@ -319,6 +339,9 @@ void aaa_destroy(aaa_ctx *ctx)
     (void)hipHostFree(ctx->views_host);
     (void)hipHostFree(ctx->train_host);
     (void)hipFree(ctx->train_dev);
+    (void)hipEventDestroy(ctx->fork);
+    (void)hipEventDestroy(ctx->join);
+    (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -393,7 +416,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ctr, 0, 64, s));
+    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8]
 
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
@@ -460,7 +483,26 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.grad_rec = nullptr;
     ba.pix_off = nullptr;
     ba.slots = nullptr;
-    HIP_TRY(aaa::launch_blend(ba, settings->ray_window, want_stats, false, s));
+    const int K = settings->ray_window;
+    const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
+    ba.long_list = K > 16 ? 0xffffffffu : (long_all ? 0u : aaa::kLongList);
+    if (ba.long_list != 0xffffffffu && P > ba.long_list) {
+        // tiles with long lists render concurrently on the side stream
+        uint32_t *long_tiles = at<uint32_t>(ws, L.long_tiles);
+        uint32_t *n_long = (uint32_t *)(ctr + 8);
+        HIP_TRY(aaa::launch_find_long(ba, long_tiles, n_long, s));
+        const uint64_t bound = P / ((uint64_t)ba.long_list + 1);
+        const unsigned grid = (unsigned)(bound < (uint64_t)ntiles ? bound : (uint64_t)ntiles);
+        HIP_TRY(hipEventRecord(ctx->fork, s));
+        HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+        HIP_TRY(aaa::launch_blend_long(ba, K, want_stats, long_tiles, n_long, grid, at<uint64_t>(ws, L.masks),
+                                       at<uint64_t>(ws, L.summary), summary_words(sh, max_pairs), ctx->side));
+        HIP_TRY(hipEventRecord(ctx->join, ctx->side));
+        HIP_TRY(aaa::launch_blend(ba, K, want_stats, false, s));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->join, 0));
+    } else {
+        HIP_TRY(aaa::launch_blend(ba, K, want_stats, false, s));
+    }
     if (timing) {
         STAGE_MARK(8);
         ctx->pending[ctx->cur] = true;
@@ -569,6 +611,7 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     ba.grad_rec = grad_rec;
     ba.pix_off = at<uint64_t>(ws, L.pix_off);
     ba.slots = (float2 *)scratch;
+    ba.long_list = 0xffffffffu;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));  // pass 1: window replay
     HIP_TRY(aaa::launch_grad(ba, s));                                     // pass 2: list order, wave sums
     aaa::GradOut go;

@@ -25,6 +25,8 @@
 // look at the same Gaussian: each contributing lane turns its two scalars into
 // the 22 record gradients (line coefficients, alpha~, colour), the wave sums
 // them with DPP row reductions, and one instruction adds them atomically.
+#include <algorithm>
+
 #include "aaa_internal.h"
 
 namespace aaa {
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     const bool inside = px < vw.cam.width && py < vw.cam.height;
     const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    if (!PASS1 && end - start > a.long_list) return;  // k_blend_long renders it
     const size_t hw = (size_t)vw.cam.width * vw.cam.height;
     const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
     const size_t gpix = vw.pix_base + pix;
@@ -287,6 +290,296 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
         }
         if (lane == 0) {
             atomicAdd(&a.counters[0], e);
+            atomicAdd(&a.counters[1], c);
+            atomicAdd(&a.counters[2], nr);
+            atomicAdd(&a.counters[3], (unsigned long long)w_steps);
+            atomicAdd(&a.counters[4], (unsigned long long)w_near);
+            atomicAdd(&a.counters[5], (unsigned long long)w_contrib);
+        }
+    }
+}
+
+// ------------------------------------------------------ long tile lists
+//
+// A tile whose list is longer than a.long_list (far views: much of the scene
+// in a few tiles) takes a different route.  There every Gaussian covers a
+// pixel or two, so a wave that walks the list in lockstep finds one or two
+// contributing lanes per entry.  Instead:
+//   1. k_long_masks (many workgroups per long tile, one 64-entry word of the
+//      list at a time, staged in LDS): every lane evaluates its pixel for the
+//      word's entries and stores a 64-bit mask "entry contributes to this
+//      pixel" (the blend's own test, without the termination state);
+//   2. k_blend_long gives every lane its own walk over its pixel's set bits,
+//      in list order, with the next entry's record fetched while the current
+//      one is processed.  All lanes still run the window update together
+//      (lanes without an entry insert a NaN depth, a no-op), so a wave step
+//      serves one contribution of every pixel instead of one entry.
+// Entries whose bit is clear contribute nothing to that pixel, so the result
+// equals the regular kernel's.  The window slots carry alpha and colour.
+//
+// Mask layout: word w of the pair list for tile t sits at (w + t) * 256 +
+// pixel, pixel = quadrant * 64 + lane; tile lists are in tile order, so
+// (w + t) never collides between tiles.  A summary keeps one bit per
+// non-empty mask word, bit (w + t) % 64 of word ((w + t) / 64) * 256 + pixel,
+// so that a walk jumps over empty words with one load per 64 of them.
+
+constexpr unsigned kMaskBlocksPerTile = 64;
+
+__global__ void k_find_long(const uint32_t *__restrict__ ranges, int ntiles, uint32_t long_list,
+                            uint32_t *__restrict__ long_tiles, uint32_t *__restrict__ n_long)
+{
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= ntiles) return;
+    if (ranges[2 * t + 1] - ranges[2 * t] > long_list) long_tiles[atomicAdd(n_long, 1u)] = (uint32_t)t;
+}
+
+// geometric contribution test of one entry at one pixel (the blend's test
+// without the termination state; same arithmetic)
+__device__ __forceinline__ bool contributes(float fxp, float fyp, float4 q0, float4 q1, float4 q2, float4 q3,
+                                            float4 q4, float4 q5, float4 q6, float amin, float amax, float znear)
+{
+    const float dx = fxp - q5.y, dy = fyp - q5.z;
+    const Eval e = eval_line(dx, dy, q0, q1, q2, q3, q4);
+    const bool near = e.N <= q6.x * e.D;
+    const float inv = __builtin_amdgcn_rcpf(e.D);
+    const float rho2 = e.N * inv;
+    const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
+    const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
+    return near && al >= amin && z >= znear;
+}
+
+struct LongTile {
+    int tile, v;
+    const ViewDev *vw;
+    int px, py;
+    bool inside;
+    uint32_t start, end;
+};
+
+__device__ __forceinline__ LongTile long_tile_setup(const BlendArgs &a, int tile)
+{
+    LongTile L;
+    L.tile = tile;
+    int v = 0;
+    while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
+    L.v = v;
+    L.vw = &a.views[v];
+    const int lt = tile - L.vw->tile_base;
+    const int tx = lt % L.vw->cam.tiles_x, ty = lt / L.vw->cam.tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    L.px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+    L.py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+    L.inside = L.px < L.vw->cam.width && L.py < L.vw->cam.height;
+    L.start = a.ranges[2 * tile];
+    L.end = a.ranges[2 * tile + 1];
+    return L;
+}
+
+__global__ __launch_bounds__(256) void k_long_masks(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                    BlendArgs a, const uint32_t *__restrict__ long_tiles,
+                                                    const uint32_t *__restrict__ n_long, uint64_t *__restrict__ pixmask,
+                                                    uint64_t *__restrict__ summary)
+{
+    if (blockIdx.y >= *n_long) return;
+    const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.y]);
+    const uint32_t nv = (uint32_t)a.nviews;
+    const int t = threadIdx.x;
+    const float fxp = (float)L.px + 0.5f, fyp = (float)L.py + 0.5f;
+    const float amin = a.alpha_min, amax = a.alpha_max, znear = (float)L.vw->cam.znear;
+    __shared__ float4 srec[64][7];
+    for (uint32_t w = L.start / 64 + blockIdx.x; (uint64_t)w * 64 < L.end; w += gridDim.x) {
+        for (int idx = t; idx < 64 * 7; idx += 256) {
+            const uint32_t e = w * 64 + (uint32_t)(idx / 7);
+            if (e >= L.start && e < L.end)
+                srec[idx / 7][idx % 7] = rec[(size_t)(vals[e] * nv + (uint32_t)L.v) * kRecQuads + idx % 7];
+        }
+        __syncthreads();
+        uint64_t bits = 0;
+        for (int b = 0; b < 64; ++b) {
+            const uint32_t e = w * 64 + (uint32_t)b;
+            if (e < L.start || e >= L.end) continue;
+            const bool c = L.inside && contributes(fxp, fyp, srec[b][0], srec[b][1], srec[b][2], srec[b][3],
+                                                   srec[b][4], srec[b][5], srec[b][6], amin, amax, znear);
+            bits |= c ? (1ull << b) : 0ull;
+        }
+        const uint64_t i = (uint64_t)w + (uint64_t)L.tile;
+        pixmask[i * 256 + (uint64_t)t] = bits;
+        if (bits) atomicOr((unsigned long long *)&summary[(i / 64) * 256 + (uint64_t)t], 1ull << (i % 64));
+        __syncthreads();
+    }
+}
+
+template <int K, bool STATS>
+__global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                    BlendArgs a, const uint32_t *__restrict__ long_tiles,
+                                                    const uint32_t *__restrict__ n_long,
+                                                    const uint64_t *__restrict__ pixmask,
+                                                    const uint64_t *__restrict__ summary)
+{
+    if (blockIdx.x >= *n_long) return;
+    const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.x]);
+    const ViewDev &vw = *L.vw;
+    const uint32_t nv = (uint32_t)a.nviews;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const float fxp = (float)L.px + 0.5f, fyp = (float)L.py + 0.5f;
+    const uint32_t start = L.start, end = L.end;
+    const size_t hw = (size_t)vw.cam.width * vw.cam.height;
+    const size_t pix = L.inside ? (size_t)L.py * vw.cam.width + L.px : 0;
+    const size_t gpix = vw.pix_base + pix;
+
+    constexpr int KS = K > 0 ? K : 1;
+    __shared__ float4 pay[K > 0 ? 4 : 1][KS][64];  // (alpha, r, g, b) per slot
+    float wz[KS];
+    uint32_t ws[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        wz[k] = -INFINITY;
+        ws[k] = (uint32_t)k;
+        if constexpr (K > 0) pay[wave][k][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    bool done = !L.inside;
+    uint32_t consumed = 0, rank = 0;
+    uint32_t n_eval = 0, n_near = 0, w_steps = 0, w_near = 0, w_contrib = 0;
+    const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
+
+    auto blend = [&](float al, float cr, float cg, float cb) {
+        if (al > 0.0f && !done) {
+            const float Tn = T * (1.0f - al);
+            if (Tn < tmin) {
+                done = true;
+            } else {
+                const float W = T * al;
+                C0 += W * cr;
+                C1 += W * cg;
+                C2 += W * cb;
+                T = Tn;
+            }
+        }
+    };
+
+    // this lane's walk over its set bits: word w (global index), bits left;
+    // the summary word in hand covers positions sb * 64 .. sb * 64 + 63 of
+    // (w + tile)
+    const uint64_t tl = (uint64_t)L.tile;
+    const uint64_t i_last = (uint64_t)((end - 1) / 64) + tl;
+    uint64_t i_cur = (uint64_t)(start / 64) + tl;
+    uint64_t bits = 0;
+    auto word_bits = [&](uint64_t i) {
+        const uint64_t ww = i - tl;
+        uint64_t b = pixmask[i * 256 + (uint64_t)t];
+        if (ww * 64 < start) b &= ~0ull << (start - ww * 64);
+        if (i == i_last && (end & 63u)) b &= (1ull << (end & 63u)) - 1ull;
+        return b;
+    };
+    uint64_t sb = i_cur / 64;
+    uint64_t sw = summary[sb * 256 + (uint64_t)t];
+    bits = L.inside ? word_bits(i_cur) : 0ull;
+    // next entry of the walk, or end when the pixel has none left
+    auto advance = [&]() -> uint32_t {
+        while (bits == 0ull) {
+            if (i_cur >= i_last) return end;
+            // next non-empty word after i_cur, from the summary
+            uint64_t nxt = i_cur + 1;
+            if (nxt / 64 != sb) {
+                sb = nxt / 64;
+                sw = summary[sb * 256 + (uint64_t)t];
+            }
+            uint64_t m = sw & (~0ull << (nxt % 64));
+            while (m == 0ull) {
+                ++sb;
+                if (sb * 64 > i_last) return end;
+                sw = summary[sb * 256 + (uint64_t)t];
+                m = sw;
+            }
+            i_cur = sb * 64 + (uint64_t)__builtin_ctzll(m);
+            if (i_cur > i_last) return end;
+            bits = word_bits(i_cur);
+        }
+        const uint32_t e = (uint32_t)((i_cur - tl) * 64) + (uint32_t)__builtin_ctzll(bits);
+        bits &= bits - 1ull;
+        return e;
+    };
+    uint32_t e_cur = (L.inside && !done) ? advance() : end;
+    float4 r0, r1, r2, r3, r4, r5, r6, r7;
+    auto fetch = [&](uint32_t e) {
+        if (e < end) {
+            const float4 *r = rec + (size_t)(vals[e] * nv + (uint32_t)L.v) * kRecQuads;
+            r0 = r[0]; r1 = r[1]; r2 = r[2]; r3 = r[3]; r4 = r[4]; r5 = r[5]; r6 = r[6]; r7 = r[7];
+        }
+    };
+    fetch(e_cur);
+    while (__builtin_amdgcn_ballot_w64(e_cur < end && !done) != 0ull) {
+        const bool has = e_cur < end && !done;
+        const float4 q0 = r0, q1 = r1, q2 = r2, q3 = r3, q4 = r4, q5 = r5, q6 = r6, col = r7;
+        const uint32_t e_this = e_cur;
+        // the following entry of this pixel is fetched while this one is processed
+        e_cur = has ? advance() : end;
+        fetch(e_cur);
+        if (STATS && has) ++n_eval;
+        if (STATS) ++w_steps;
+        const float dx = fxp - q5.y, dy = fyp - q5.z;
+        const Eval ev = eval_line(dx, dy, q0, q1, q2, q3, q4);
+        const bool near = has && ev.N <= q6.x * ev.D;
+        if (STATS && near) ++n_near;
+        const float inv = __builtin_amdgcn_rcpf(ev.D);
+        const float rho2 = ev.N * inv;
+        const float al = fminf(amax, q5.w * __builtin_amdgcn_exp2f(-(rho2 * kLog2eHalf)));
+        const float z = __fmaf_rn(dy, q5.x, __fmaf_rn(dx, q4.w, q4.z)) * inv;
+        const bool contrib = near && al >= amin && z >= znear;
+        if (STATS) ++w_contrib;
+        if (contrib) ++rank;
+        if constexpr (K == 0) {
+            blend(contrib ? al : 0.0f, col.x, col.y, col.z);
+        } else {
+            const float zk = contrib ? z : __builtin_nanf("");
+            const float ak = contrib ? al : 0.0f;
+            const uint32_t fs = ws[0];
+            const float4 fp = pay[wave][fs][lane];
+            const bool front_out = wz[0] <= zk;
+            bool gcur = front_out;
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) {
+                const int kn = kk + 1 < K ? kk + 1 : kk;
+                const bool gnext = (kk + 1 < K) ? (wz[kn] <= zk) : false;
+                wz[kk] = gnext ? wz[kn] : (gcur ? zk : wz[kk]);
+                ws[kk] = gnext ? ws[kn] : (gcur ? fs : ws[kk]);
+                gcur = gnext;
+            }
+            if (front_out) pay[wave][fs][lane] = make_float4(ak, col.x, col.y, col.z);
+            if (front_out)
+                blend(fp.x, fp.y, fp.z, fp.w);
+            else
+                blend(ak, col.x, col.y, col.z);
+        }
+        if (contrib && done && consumed == 0) consumed = e_this - start + 1;
+    }
+    const bool draining = !done;
+    if constexpr (K > 0) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const float4 q = pay[wave][ws[k]][lane];
+            blend(done ? 0.0f : q.x, q.y, q.z, q.w);
+        }
+    }
+    if (draining) consumed = end - start;
+    if (L.inside) {
+        vw.out_rgb[pix] = C0 + T * vw.bg[0];
+        vw.out_rgb[hw + pix] = C1 + T * vw.bg[1];
+        vw.out_rgb[2 * hw + pix] = C2 + T * vw.bg[2];
+        vw.out_T[pix] = T;
+        a.n_done[gpix] = consumed;
+        a.n_ins[gpix] = rank;
+    }
+    if (STATS) {
+        unsigned long long ec = n_eval, c = rank, nr = n_near;
+        for (int off = 32; off > 0; off >>= 1) {
+            ec += __shfl_down(ec, off);
+            c += __shfl_down(c, off);
+            nr += __shfl_down(nr, off);
+        }
+        if (lane == 0) {
+            atomicAdd(&a.counters[0], ec);
             atomicAdd(&a.counters[1], c);
             atomicAdd(&a.counters[2], nr);
             atomicAdd(&a.counters[3], (unsigned long long)w_steps);
@@ -470,6 +763,52 @@ hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipSt
     case 16: return launch_k<16>(a, stats, pass1, s);
     case 32: return launch_k<32>(a, stats, pass1, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+template <int K>
+hipError_t launch_long_k(const BlendArgs &a, bool stats, const uint32_t *long_tiles, const uint32_t *n_long,
+                         unsigned grid, const uint64_t *pixmask, const uint64_t *summary, hipStream_t s)
+{
+    if (stats)
+        hipLaunchKernelGGL((k_blend_long<K, true>), dim3(grid), dim3(256), 0, s, a.rec, a.vals, a, long_tiles, n_long,
+                           pixmask, summary);
+    else
+        hipLaunchKernelGGL((k_blend_long<K, false>), dim3(grid), dim3(256), 0, s, a.rec, a.vals, a, long_tiles, n_long,
+                           pixmask, summary);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_u64(uint64_t *__restrict__ p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+hipError_t launch_find_long(const BlendArgs &a, uint32_t *long_tiles, uint32_t *n_long, hipStream_t s)
+{
+    if (a.total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_find_long, dim3((unsigned)((a.total_tiles + 255) / 256)), dim3(256), 0, s, a.ranges,
+                       a.total_tiles, a.long_list, long_tiles, n_long);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32_t *long_tiles, const uint32_t *n_long,
+                             unsigned grid, uint64_t *pixmask, uint64_t *summary, uint64_t summary_words, hipStream_t s)
+{
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)std::min<uint64_t>((summary_words + 255) / 256, 4096)), dim3(256), 0,
+                       s, summary, summary_words);
+    hipLaunchKernelGGL(k_long_masks, dim3(kMaskBlocksPerTile, grid), dim3(256), 0, s, a.rec, a.vals, a, long_tiles,
+                       n_long, pixmask, summary);
+    switch (K) {
+    case 0: return launch_long_k<0>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
+    case 1: return launch_long_k<1>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
+    case 2: return launch_long_k<2>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
+    case 4: return launch_long_k<4>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
+    case 8: return launch_long_k<8>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
+    case 16: return launch_long_k<16>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
+    default: return hipErrorInvalidValue;  // K = 32 keeps every tile in k_blend (long_list = max)
     }
 }
 

@@ -109,14 +109,15 @@ class Rasterizer:
 
     # forward ------------------------------------------------------------
     def render(self, scene: DeviceScene, cam, settings, stats: bool = False, timing: bool = False,
-               max_pairs: Optional[int] = None, ws: Optional[Workspace] = None, fresh_ws: bool = False):
+               max_pairs: Optional[int] = None, ws: Optional[Workspace] = None, fresh_ws: bool = False,
+               flags: int = 0):
         """Render one view; returns (rgb [3,H,W], T [H,W], Stats).  Uses the
         rasteriser's own workspace unless `ws` is given or `fresh_ws` asks for
         a new one; the frame state stays in that workspace (`last_ws`), e.g.
         for a later backward."""
         sc = scene.abi()
         c = L.make_camera(cam)
-        st = L.make_settings(settings, (L.AAA_STATS if stats else 0) | (L.AAA_TIMING if timing else 0))
+        st = L.make_settings(settings, (L.AAA_STATS if stats else 0) | (L.AAA_TIMING if timing else 0) | flags)
         H, W = int(cam.height), int(cam.width)
         rgb = torch.empty((3, H, W), dtype=torch.float32, device=self.device)
         T = torch.empty((H, W), dtype=torch.float32, device=self.device)

@@ -122,3 +122,24 @@ def test_backward_twice_is_deterministic_up_to_atomics(ras):
     b = ras.backward(ds, cam, st, ws, rgb, g)
     for k in GROUPS:
         assert torch.allclose(a[k], b[k], rtol=1e-4, atol=1e-6 * float(a[k].abs().max()) + 1e-12)
+
+
+def test_backward_after_long_list_forward(ras):
+    """Forward through the long-list kernel (every tile forced), backward
+    replay through the regular one: gradients still match the oracle."""
+    from paper_2504_12811_amd import _lib as L
+    from paper_2504_12811_amd.render import DeviceScene
+    scene, cam = S.fd_scene()
+    st = S.Settings()
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(3, cam.height, cam.width))
+    base = O.render_backward(scene, cam, st, g)
+    g = g * (base.flags == 0)
+    ref = O.render_backward(scene, cam, st, g)
+    ds = DeviceScene.from_host(scene, "cuda:0")
+    rgb, T, _ = ras.render(ds, cam, st, fresh_ws=True, flags=L.AAA_LONG_ALL)
+    grads = ras.backward(ds, cam, st, ras.last_ws, rgb, torch.from_numpy(g.astype(np.float32)).cuda())
+    for k in GROUPS:
+        a = grads[k].cpu().numpy().astype(np.float64)
+        b = getattr(ref, k)
+        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max() + 1e-7, k

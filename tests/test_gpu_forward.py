@@ -270,3 +270,47 @@ def test_headline_sampled_tiles(ras):
     sel = np.zeros(tx * ty, np.uint8)
     sel[rng.choice(tx * ty, 24, replace=False)] = 1
     compare_image(ras, scene, cam, S.Settings(), tile_sel=sel, label="1M 1080p sampled")
+
+
+# --------------------------------------------------------------------------
+# long tile lists (far views): the LDS-staged path
+
+
+def test_long_list_path_equals_regular_path(ras):
+    """Every tile forced through the long-list route (masks, LDS-staged
+    walk) gives bit-identical images, transmittance and contributor counts
+    (the route skips entries that contribute nowhere in a quadrant, so its
+    evaluation counts are smaller)."""
+    from paper_2504_12811_amd import _lib as L
+    scene, poses = S.cluster_scene(30_000, seed=1002, n_rig=8)
+    for K in (16, 4, 0):
+        st = S.Settings(ray_window=K)
+        cam = S.pinhole(poses[1], 250, 170, 60.0)
+        a = ras.render(dev(scene), cam, st, stats=True)
+        b = ras.render(dev(scene), cam, st, stats=True, flags=L.AAA_LONG_ALL)
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), K
+        assert a[2].contributors == b[2].contributors, K
+        assert b[2].evaluations <= a[2].evaluations, K
+
+
+def test_far_view_long_lists_sampled(ras):
+    """A far view puts the whole cluster scene into a few tiles with lists of
+    several thousand entries (the long-list path); oracle on those tiles."""
+    scene, poses = S.cluster_scene(120_000, seed=1002, n_rig=8)
+    d = poses[0] / np.linalg.norm(poses[0])
+    cam = S.pinhole(d * 16 * 10 * np.sqrt(3.0), 640, 360, 60.0)
+    st = S.Settings()
+    from paper_2504_12811_amd.render import DeviceScene
+    ds = DeviceScene.from_host(scene, "cuda:0")
+    ras.render(ds, cam, st)
+    _, _, ranges = ras.read_pairs(ds, cam)
+    rg = ranges.cpu().numpy().astype(np.int64)
+    ln = rg[:, 1] - rg[:, 0]
+    print("longest lists", np.sort(ln)[-6:].tolist())
+    assert ln.max() > 4096
+    sel = (ln > 4096).astype(np.uint8)
+    if sel.sum() > 6:
+        keep = np.argsort(-ln)[:6]
+        sel[:] = 0
+        sel[keep] = 1
+    compare_image(ras, scene, cam, st, tile_sel=sel, label="far view long lists")
