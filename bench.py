@@ -85,8 +85,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rates", type=str, default="50,100,200,400")
-    ap.add_argument("--serve-rates-single", type=str, default="50,100,200",
-                    help="rates for the one-request-at-a-time baseline (its queue only grows beyond ~60 req/s)")
+    ap.add_argument("--serve-rates-single", type=str, default="50,100,200,400",
+                    help="rates for the one-request-at-a-time baseline")
     ap.add_argument("--suite", action="store_true",
                     help="also time the ablations (no tile culling, no per-ray window) and the other workloads: "
                          "500k 1080p, 3M 2064x2208 120deg with its zoom sweep, 1M 1280x720 16-view training "

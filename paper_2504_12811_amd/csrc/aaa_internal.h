@@ -249,8 +249,10 @@ struct BlendArgs {
     float *grad_rec;               // per item, kGradStride floats
     const uint64_t *pix_off;       // per pixel: first slot (exclusive scan of n_ins)
     float2 *slots;                 // per (pixel, contributor rank): dL/dalpha, T alpha
-    // forward only: tiles with longer lists are left to k_blend_long
+    // forward only: tiles with longer lists are left to k_blend_long when
+    // *n_long (written by k_find_long) is at most kMaxLongTiles
     uint32_t long_list;
+    const uint32_t *n_long;
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s);
@@ -264,7 +266,8 @@ hipError_t launch_find_long(const BlendArgs &a, uint32_t *long_tiles, uint32_t *
 hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32_t *long_tiles, const uint32_t *n_long,
                              unsigned grid, uint64_t *pixmask, uint64_t *summary, uint64_t summary_words,
                              hipStream_t s);
-constexpr uint32_t kLongList = 4096;  // entries above which a forward tile is rendered by k_blend_long
+constexpr uint32_t kLongList = 4096;     // entries above which a forward tile is rendered by k_blend_long
+constexpr uint32_t kMaxLongTiles = 1024; // ... when at most this many tiles are that long
 
 struct GradOut {
     float *means, *log_scales, *quats, *logits, *sh;

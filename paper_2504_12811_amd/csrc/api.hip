@@ -486,13 +486,16 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const int K = settings->ray_window;
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
     ba.long_list = K > 16 ? 0xffffffffu : (long_all ? 0u : aaa::kLongList);
+    uint32_t *n_long = (uint32_t *)(ctr + 8);  // zeroed with the counters
+    ba.n_long = n_long;
     if (ba.long_list != 0xffffffffu && P > ba.long_list) {
         // tiles with long lists render concurrently on the side stream
         uint32_t *long_tiles = at<uint32_t>(ws, L.long_tiles);
-        uint32_t *n_long = (uint32_t *)(ctr + 8);
         HIP_TRY(aaa::launch_find_long(ba, long_tiles, n_long, s));
-        const uint64_t bound = P / ((uint64_t)ba.long_list + 1);
-        const unsigned grid = (unsigned)(bound < (uint64_t)ntiles ? bound : (uint64_t)ntiles);
+        uint64_t bound = P / ((uint64_t)ba.long_list + 1);
+        if (bound > (uint64_t)ntiles) bound = (uint64_t)ntiles;
+        if (bound > aaa::kMaxLongTiles) bound = aaa::kMaxLongTiles;
+        const unsigned grid = (unsigned)bound;
         HIP_TRY(hipEventRecord(ctx->fork, s));
         HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
         HIP_TRY(aaa::launch_blend_long(ba, K, want_stats, long_tiles, n_long, grid, at<uint64_t>(ws, L.masks),
@@ -612,6 +615,7 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     ba.pix_off = at<uint64_t>(ws, L.pix_off);
     ba.slots = (float2 *)scratch;
     ba.long_list = 0xffffffffu;
+    ba.n_long = nullptr;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));  // pass 1: window replay
     HIP_TRY(aaa::launch_grad(ba, s));                                     // pass 2: list order, wave sums
     aaa::GradOut go;

@@ -160,7 +160,8 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     const bool inside = px < vw.cam.width && py < vw.cam.height;
     const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
     const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
-    if (!PASS1 && end - start > a.long_list) return;  // k_blend_long renders it
+    // k_blend_long renders long lists when they are few (see k_find_long)
+    if (!PASS1 && end - start > a.long_list && *a.n_long <= kMaxLongTiles) return;
     const size_t hw = (size_t)vw.cam.width * vw.cam.height;
     const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
     const size_t gpix = vw.pix_base + pix;
@@ -325,12 +326,21 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
 
 constexpr unsigned kMaskBlocksPerTile = 64;
 
+// Collects the tiles with lists longer than long_list.  The long route is
+// taken only when there are at most kMaxLongTiles of them: then a few tiles
+// hold most of the work and the regular kernel would leave the chip idle;
+// with many long tiles (a close, dense view) the regular kernel has
+// parallelism enough and keeps its early termination.  Every kernel reads
+// the count from device memory, so they all agree.
 __global__ void k_find_long(const uint32_t *__restrict__ ranges, int ntiles, uint32_t long_list,
                             uint32_t *__restrict__ long_tiles, uint32_t *__restrict__ n_long)
 {
     const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (t >= ntiles) return;
-    if (ranges[2 * t + 1] - ranges[2 * t] > long_list) long_tiles[atomicAdd(n_long, 1u)] = (uint32_t)t;
+    if (ranges[2 * t + 1] - ranges[2 * t] > long_list) {
+        const uint32_t k = atomicAdd(n_long, 1u);
+        if (k < kMaxLongTiles) long_tiles[k] = (uint32_t)t;
+    }
 }
 
 // geometric contribution test of one entry at one pixel (the blend's test
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(256) void k_long_masks(const float4 *__restrict__ r
                                                     const uint32_t *__restrict__ n_long, uint64_t *__restrict__ pixmask,
                                                     uint64_t *__restrict__ summary)
 {
-    if (blockIdx.y >= *n_long) return;
+    if (blockIdx.y >= *n_long || *n_long > kMaxLongTiles) return;
     const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.y]);
     const uint32_t nv = (uint32_t)a.nviews;
     const int t = threadIdx.x;
@@ -416,7 +426,7 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
                                                     const uint64_t *__restrict__ pixmask,
                                                     const uint64_t *__restrict__ summary)
 {
-    if (blockIdx.x >= *n_long) return;
+    if (blockIdx.x >= *n_long || *n_long > kMaxLongTiles) return;
     const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.x]);
     const ViewDev &vw = *L.vw;
     const uint32_t nv = (uint32_t)a.nviews;
