@@ -44,6 +44,24 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_blend_1M_1080p_counters.txt")
 BLEND_SRC = os.path.join(ROOT, "paper_2504_12811_amd", "csrc", "blend.hip")
 
 
+def blend_counters():
+    """key: value lines of the committed counter summary, or {} when it is
+    missing or belongs to a different blend source."""
+    import hashlib
+    try:
+        kv = {}
+        with open(COUNTERS_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(BLEND_SRC, "rb") as f:
+            sha = hashlib.sha1(f.read()).hexdigest()
+        return kv if kv.get("source_sha1") == sha else {}
+    except OSError:
+        return {}
+
+
 def blend_traffic_bytes():
     """HBM bytes per blend launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same
@@ -188,6 +206,7 @@ def main():
             "frac": round(achieved / PEAK_VALU_TFLOPS, 4),
             "traffic": (lambda b: None if b is None else round(b))(blend_traffic_bytes()),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "valu_busy": (lambda kv: float(kv["valu_busy"]) if "valu_busy" in kv else None)(blend_counters()),
             "avg_ms": round(blend_ms, 4),
             "flops_per_launch": flops,
         },
