@@ -272,5 +272,8 @@ constexpr uint32_t kMaxLongTiles = 1024; // ... when at most this many tiles are
 struct GradOut {
     float *means, *log_scales, *quats, *logits, *sh;
 };
-hipError_t launch_preprocess_bwd(const PreArgs &a, const float *grad_rec, GradOut g, hipStream_t s);
+// K6b over the Gaussians with a visible item (list: n entries, count: one
+// uint32 zeroed beforehand; both caller workspace).
+hipError_t launch_preprocess_bwd(const PreArgs &a, const float *grad_rec, GradOut g, uint32_t *list, uint32_t *count,
+                                 hipStream_t s);
 }  // namespace aaa

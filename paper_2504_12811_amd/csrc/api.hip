@@ -624,7 +624,12 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     go.quats = grad->quats;
     go.logits = grad->opacity_logits;
     go.sh = grad->sh;
-    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, s));
+    // K6b over the Gaussians with a visible item; the list reuses the
+    // per-item count buffer (not needed after the forward's scan), the
+    // count sits beside the frame counters
+    uint32_t *bwd_count = (uint32_t *)(at<unsigned long long>(ws, L.hdr) + 9);
+    HIP_TRY(hipMemsetAsync(bwd_count, 0, 4, s));
+    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, at<uint32_t>(ws, L.counts), bwd_count, s));
     // the pinned view table is reused by the next call on this context
     HIP_TRY(hipStreamSynchronize(s));
     return AAA_OK;

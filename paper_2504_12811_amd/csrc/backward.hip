@@ -18,9 +18,13 @@ namespace {
 __device__ __forceinline__ void cross3(const double *a, const double *b, double *c) { cross3d(a, b, c); }
 
 // Adjoint of the preparation of Gaussian i for view v; adds into the
-// per-Gaussian sums (gsh_out is [(deg+1)^2][3], coefficient-major).
-__device__ void preprocess_bwd_item(const PreArgs &a, int64_t i, int v, const float *gv, double *gmu_out,
-                                    double *gls_out, double *gq_out, double &glogit_out, double *gsh_out)
+// per-Gaussian sums (gsh_out is [(DEG+1)^2][3], coefficient-major).  The SH
+// degree is a template parameter so that every SH loop unrolls and its
+// arrays stay in registers.
+template <int DEG>
+__device__ __forceinline__ void preprocess_bwd_item(const PreArgs &a, int64_t i, int v, const float *gv,
+                                                    double *gmu_out, double *gls_out, double *gq_out,
+                                                    double &glogit_out, float *gsh_out)
 {
     const int64_t n = a.n;
     const ViewDev &vw = a.views[v];
@@ -113,22 +117,26 @@ __device__ void preprocess_bwd_item(const PreArgs &a, int64_t i, int v, const fl
     const double glogit = galpha * S.alpha * (1.0 - S.alpha);
 
     // colour: c = max(0, 0.5 + sum_b Y_b(d) sh_b)
+    constexpr int nb = (DEG + 1) * (DEG + 1);
     double Y[16], gY[16];
-    sh_eval(a.sh_degree, d[0], d[1], d[2], Y);
-    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
+    sh_eval(DEG, d[0], d[1], d[2], Y);
+#pragma unroll
     for (int k = 0; k < nb; ++k) gY[k] = 0.0;
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         const double gcol = gv[19 + ch];
         double acc = 0.5;
+#pragma unroll
         for (int k = 0; k < nb; ++k) acc += Y[k] * (double)a.sh[((int64_t)k * 3 + ch) * n + i];
         if (!(acc > 0.0) || gcol == 0.0) continue;
+#pragma unroll
         for (int k = 0; k < nb; ++k) {
             gY[k] += (double)a.sh[((int64_t)k * 3 + ch) * n + i] * gcol;
-            gsh_out[3 * k + ch] += Y[k] * gcol;
+            gsh_out[3 * k + ch] += (float)(Y[k] * gcol);
         }
     }
     double gdY[3];
-    sh_eval_grad(a.sh_degree, d[0], d[1], d[2], gY, gdY);
+    sh_eval_grad(DEG, d[0], d[1], d[2], gY, gdY);
     for (int k = 0; k < 3; ++k) gd[k] += gdY[k];
 
     // d = (mu - o) / |mu - o|;  mu_view = R_V mu + t
@@ -156,17 +164,39 @@ __device__ void preprocess_bwd_item(const PreArgs &a, int64_t i, int v, const fl
     glogit_out += glogit;
 }
 
-// One thread per Gaussian: sums the adjoint over the views of the batch and
-// adds it to the caller's gradient arrays (no atomics needed).
-__global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *__restrict__ grad_rec, GradOut go)
+// Gaussians with a visible item in some view, compacted (order irrelevant:
+// every Gaussian is handled by one thread).
+__global__ __launch_bounds__(256) void k_touched(const int32_t *__restrict__ status, int64_t n, int nviews,
+                                                 uint32_t *__restrict__ list, uint32_t *__restrict__ count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    bool vis = false;
+    if (i < n)
+        for (int v = 0; v < nviews; ++v) vis |= status[i * nviews + v] == kVisible;
+    const uint64_t m = __ballot(vis);
+    const int lane = (int)__lane_id();
+    uint32_t base = 0;
+    if (lane == 0 && m) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, 0);
+    if (vis) list[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)i;
+}
+
+// One thread per listed Gaussian: sums the adjoint over the views of the
+// batch and adds it to the caller's gradient arrays (no atomics needed).
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *__restrict__ grad_rec, GradOut go,
+                                                        const uint32_t *__restrict__ list,
+                                                        const uint32_t *__restrict__ count)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)*count) return;
+    const int64_t i = list[j];
     const int64_t n = a.n;
+    constexpr int nb = (DEG + 1) * (DEG + 1);
     double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, glogit = 0.0;
-    double gsh[48];
-    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
-    for (int k = 0; k < 3 * nb; ++k) gsh[k] = 0.0;
+    float gsh[3 * nb];
+#pragma unroll
+    for (int k = 0; k < 3 * nb; ++k) gsh[k] = 0.0f;
     bool touched = false;
     for (int v = 0; v < a.nviews; ++v) {
         const int64_t item = i * a.nviews + v;
@@ -174,13 +204,14 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
         const float *gr = grad_rec + (size_t)item * kGradStride;
         float gv[22];
         bool any = false;
+#pragma unroll
         for (int k = 0; k < 22; ++k) {
             gv[k] = gr[k];
             any |= gv[k] != 0.0f;
         }
         if (!any) continue;
         touched = true;
-        preprocess_bwd_item(a, i, v, gv, gmu, gls, gq, glogit, gsh);
+        preprocess_bwd_item<DEG>(a, i, v, gv, gmu, gls, gq, glogit, gsh);
     }
     if (!touched) return;
     if (go.means)
@@ -190,17 +221,28 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(PreArgs a, const float *
     if (go.quats)
         for (int k = 0; k < 4; ++k) go.quats[k * n + i] += (float)gq[k];
     if (go.logits) go.logits[i] += (float)glogit;
-    if (go.sh)
+    if (go.sh) {
+#pragma unroll
         for (int k = 0; k < nb; ++k)
-            for (int ch = 0; ch < 3; ++ch) go.sh[((int64_t)k * 3 + ch) * n + i] += (float)gsh[3 * k + ch];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) go.sh[((int64_t)k * 3 + ch) * n + i] += gsh[3 * k + ch];
+    }
 }
 
 }  // namespace
 
-hipError_t launch_preprocess_bwd(const PreArgs &a, const float *grad_rec, GradOut g, hipStream_t s)
+hipError_t launch_preprocess_bwd(const PreArgs &a, const float *grad_rec, GradOut g, uint32_t *list, uint32_t *count,
+                                 hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, grad_rec, g);
+    const unsigned grid = (unsigned)((a.n + 255) / 256);
+    hipLaunchKernelGGL(k_touched, dim3(grid), dim3(256), 0, s, (const int32_t *)a.status, a.n, a.nviews, list, count);
+    switch (a.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(grid), dim3(256), 0, s, a, grad_rec, g, list, count); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(grid), dim3(256), 0, s, a, grad_rec, g, list, count); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, dim3(grid), dim3(256), 0, s, a, grad_rec, g, list, count); break;
+    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, dim3(grid), dim3(256), 0, s, a, grad_rec, g, list, count); break;
+    }
     return hipGetLastError();
 }
 
