@@ -165,20 +165,45 @@ __device__ __forceinline__ void preprocess_bwd_item(const PreArgs &a, int64_t i,
 }
 
 // Gaussians with a visible item in some view, compacted (order irrelevant:
-// every Gaussian is handled by one thread).
-__global__ __launch_bounds__(256) void k_touched(const int32_t *__restrict__ status, int64_t n, int nviews,
-                                                 uint32_t *__restrict__ list, uint32_t *__restrict__ count)
+// every Gaussian is handled by one thread).  A block takes kTouchPer
+// consecutive Gaussians and claims its slots with one atomic.
+constexpr int kTouchPer = 16;
+
+__device__ __forceinline__ bool gauss_visible(const int32_t *status, int64_t i, int64_t n, int nviews)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool vis = false;
     if (i < n)
         for (int v = 0; v < nviews; ++v) vis |= status[i * nviews + v] == kVisible;
-    const uint64_t m = __ballot(vis);
-    const int lane = (int)__lane_id();
-    uint32_t base = 0;
-    if (lane == 0 && m) base = atomicAdd(count, (uint32_t)__popcll(m));
-    base = (uint32_t)__shfl((int)base, 0);
-    if (vis) list[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)i;
+    return vis;
+}
+
+__global__ __launch_bounds__(256) void k_touched(const int32_t *__restrict__ status, int64_t n, int nviews,
+                                                 uint32_t *__restrict__ list, uint32_t *__restrict__ count)
+{
+    __shared__ uint32_t pre[256];
+    __shared__ uint32_t base;
+    const int t = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * 256 * kTouchPer;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kTouchPer; ++k) mine += gauss_visible(status, b0 + (int64_t)k * 256 + t, n, nviews) ? 1u : 0u;
+    // inclusive scan of the per-thread counts over the block
+    pre[t] = mine;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t y = t >= off ? pre[t - off] : 0u;
+        __syncthreads();
+        pre[t] += y;
+        __syncthreads();
+    }
+    if (t == 255) base = pre[255] ? atomicAdd(count, pre[255]) : 0u;
+    __syncthreads();
+    uint32_t pos = base + pre[t] - mine;
+#pragma unroll
+    for (int k = 0; k < kTouchPer; ++k) {
+        const int64_t i = b0 + (int64_t)k * 256 + t;
+        if (gauss_visible(status, i, n, nviews)) list[pos++] = (uint32_t)i;
+    }
 }
 
 // One thread per listed Gaussian: sums the adjoint over the views of the
@@ -236,7 +261,8 @@ hipError_t launch_preprocess_bwd(const PreArgs &a, const float *grad_rec, GradOu
 {
     if (a.n <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((a.n + 255) / 256);
-    hipLaunchKernelGGL(k_touched, dim3(grid), dim3(256), 0, s, (const int32_t *)a.status, a.n, a.nviews, list, count);
+    const unsigned tgrid = (unsigned)((a.n + 256 * kTouchPer - 1) / (256 * kTouchPer));
+    hipLaunchKernelGGL(k_touched, dim3(tgrid), dim3(256), 0, s, (const int32_t *)a.status, a.n, a.nviews, list, count);
     switch (a.sh_degree) {
     case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, dim3(grid), dim3(256), 0, s, a, grad_rec, g, list, count); break;
     case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, dim3(grid), dim3(256), 0, s, a, grad_rec, g, list, count); break;
