@@ -30,7 +30,7 @@ def dev(scene):
     return DeviceScene.from_host(scene, "cuda:0")
 
 
-def compare_image(ras, scene, cam, st, tile_sel=None, label=""):
+def compare_image(ras, scene, cam, st, tile_sel=None, label="", max_flagged=0.02):
     rgb, T, stats = ras.render(dev(scene), cam, st)
     torch.cuda.synchronize()
     ref = O.render(scene, cam, st, tile_sel=tile_sel)
@@ -62,7 +62,7 @@ def compare_image(ras, scene, cam, st, tile_sel=None, label=""):
         print("worst pixels (y,x):", bad[:10].tolist(), flush=True)
     assert emax <= TOL
     assert eT <= TOL
-    assert flagged <= max(8, 0.02 * nsel)
+    assert flagged <= max(8, max_flagged * nsel)
     return rgb, T, stats, ref
 
 
