@@ -161,8 +161,9 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
  * (DEVICE arrays, same layouts as the scene; any pointer may be NULL to skip
  * it).  The blend state is recomputed per tile from the stored sorted pairs
  * (no per-pixel lists are kept by the forward).  `scratch` (DEVICE, 256-byte
- * aligned) holds one 8-byte slot per (pixel, contributor) of the forward; its
- * size comes from aaa_backward_scratch_size.  Decisions (culls, thresholds,
+ * aligned) holds 8-byte slots, for each 8x8 pixel quadrant of each tile 64
+ * per contributor of the quadrant's busiest pixel in the forward; its size
+ * comes from aaa_backward_scratch_size and it needs no clearing.  Decisions (culls, thresholds,
  * the window order, the alpha clamp, min(v_train, v), the colour clamp) are
  * held fixed; their gradients are zero or one-sided.  The forward state is
  * left intact (backward may be called again).  Synchronises `stream`. */

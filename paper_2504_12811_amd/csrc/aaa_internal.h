@@ -247,8 +247,12 @@ struct BlendArgs {
     unsigned long long *counters;  // [0] evaluations, [1] contributors, [2] prefilter passes
     // backward only
     float *grad_rec;               // per item, kGradStride floats
-    const uint64_t *pix_off;       // per pixel: first slot (exclusive scan of n_ins)
-    float2 *slots;                 // per (pixel, contributor rank): dL/dalpha, T alpha
+    // slots: per (tile quadrant, contributor rank, lane) dL/dalpha and T alpha;
+    // quadrant q = 4 * tile + wave owns 64 * (wave_off[q + 1] - wave_off[q])
+    // slots from 64 * wave_off[q], rank-major, so a wave's 64 lanes store and
+    // load one contiguous row per rank
+    const uint64_t *wave_off;
+    float2 *slots;
     // forward only: tiles with longer lists are left to k_blend_long when
     // *n_long (written by k_find_long) is at most kMaxLongTiles
     uint32_t long_list;
@@ -256,6 +260,9 @@ struct BlendArgs {
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s);
+// caps[4 * tile + wave] = the largest n_ins over the quadrant's pixels
+hipError_t launch_wave_caps(const ViewDev *views, int nviews, int total_tiles, const uint32_t *n_ins, uint32_t *caps,
+                            hipStream_t s);
 // Long tile lists: k_find_long collects tiles with more than a.long_list
 // entries (n_long must be zero beforehand); launch_blend_long computes the
 // per-pixel entry masks (pixmask: (pairs / 64 + tiles + 2) * 256 words;

@@ -70,7 +70,7 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 
 struct Layout {
     size_t hdr, views, status, rect, area, area_off, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
-        ranges, long_tiles, masks, summary, n_done, n_ins, pix_off, pix_scan_tmp, grad_rec, total;
+        ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
 uint64_t summary_words(const Shape &sh, uint64_t mp) { return ((mp / 64 + (uint64_t)sh.total_tiles + 2) / 64 + 1) * 256; }
@@ -108,8 +108,10 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.summary = take(summary_words(sh, mp) * 8);
     L.n_done = take((size_t)sh.total_pixels * 4);
     L.n_ins = take((size_t)sh.total_pixels * 4);
-    L.pix_off = take(((size_t)sh.total_pixels + 1) * 8);
-    L.pix_scan_tmp = take(aaa::scan_tmp_bytes(sh.total_pixels > 0 ? sh.total_pixels : 1));
+    const int64_t quads = 4 * sh.total_tiles > 0 ? 4 * sh.total_tiles : 1;  // 8x8 pixel quadrants of the tiles
+    L.wave_caps = take((size_t)quads * 4);
+    L.wave_off = take(((size_t)quads + 1) * 8);
+    L.wave_scan_tmp = take(aaa::scan_tmp_bytes(quads));
     L.grad_rec = take(items * 4 * aaa::kGradStride);
     L.total = o;
     return L;
@@ -154,7 +156,7 @@ int check_common(const aaa_scene *sc, int nviews, const aaa_camera *cams, const 
     int K = st->ray_window;
     if (!(K == 0 || K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32))
         return fail(AAA_ERR_INVALID, "ray_window %d not one of 0,1,2,4,8,16,32", K);
-    if (!(st->alpha_min > 0 && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0 && st->t_min >= 0 && st->t_min < 1))
+    if (!((float)st->alpha_min > 0 && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0 && st->t_min >= 0 && st->t_min < 1))
         return fail(AAA_ERR_INVALID, "need 0 < alpha_min < alpha_max <= 1 and 0 <= t_min < 1");
     if (!(st->filter_k >= 0)) return fail(AAA_ERR_INVALID, "filter_k must be >= 0");
     return AAA_OK;
@@ -481,7 +483,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.n_ins = at<uint32_t>(ws, L.n_ins);
     ba.counters = ctr + 2;
     ba.grad_rec = nullptr;
-    ba.pix_off = nullptr;
+    ba.wave_off = nullptr;
     ba.slots = nullptr;
     const int K = settings->ray_window;
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
@@ -534,14 +536,20 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
     return aaa_render_batch(ctx, scene, 1, cam, settings, ws, ws_bytes, max_pairs, stream, &out_rgb, &out_T, stats);
 }
 
-// Slots of the backward: one per (pixel, contributor) of the last forward,
-// placed by an exclusive scan of the per-pixel contributor counts.
+// Slots of the backward: each 8x8 quadrant of a tile gets one row of 64
+// slots (a lane each) per contributor rank of its busiest pixel, placed by an
+// exclusive scan of those row counts.
 static int backward_slots(const Shape &sh, const Layout &L, void *ws, hipStream_t s, uint64_t *total)
 {
-    HIP_TRY(aaa::launch_exclusive_scan(at<uint32_t>(ws, L.n_ins), at<uint64_t>(ws, L.pix_off), sh.total_pixels,
-                                       at<void>(ws, L.pix_scan_tmp), s));
-    HIP_TRY(hipMemcpyAsync(total, at<uint64_t>(ws, L.pix_off) + sh.total_pixels, 8, hipMemcpyDeviceToHost, s));
+    const int64_t quads = 4 * sh.total_tiles;
+    HIP_TRY(aaa::launch_wave_caps(at<aaa::ViewDev>(ws, L.views), sh.nviews, (int)sh.total_tiles,
+                                  at<uint32_t>(ws, L.n_ins), at<uint32_t>(ws, L.wave_caps), s));
+    HIP_TRY(aaa::launch_exclusive_scan(at<uint32_t>(ws, L.wave_caps), at<uint64_t>(ws, L.wave_off), quads,
+                                       at<void>(ws, L.wave_scan_tmp), s));
+    uint64_t rows = 0;
+    HIP_TRY(hipMemcpyAsync(&rows, at<uint64_t>(ws, L.wave_off) + quads, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    *total = rows * 64;
     return AAA_OK;
 }
 
@@ -591,7 +599,6 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     const int64_t ntiles = sh.total_tiles;
     float *grad_rec = at<float>(ws, L.grad_rec);
     HIP_TRY(hipMemsetAsync(grad_rec, 0, (size_t)n * n_views * 4 * aaa::kGradStride, s));
-    if (total) HIP_TRY(hipMemsetAsync(scratch, 0, total * sizeof(float2), s));  // never-blended contributors stay 0
     // the view table gains the backward's image and gradient pointers
     fill_views(n_views, cams, const_cast<float *const *>(out_rgb), nullptr, dL_drgb, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
@@ -612,7 +619,7 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     ba.n_ins = at<uint32_t>(ws, L.n_ins);
     ba.counters = nullptr;
     ba.grad_rec = grad_rec;
-    ba.pix_off = at<uint64_t>(ws, L.pix_off);
+    ba.wave_off = at<uint64_t>(ws, L.wave_off);
     ba.slots = (float2 *)scratch;
     ba.long_list = 0xffffffffu;
     ba.n_long = nullptr;

@@ -105,36 +105,47 @@ struct BwdPixel {
     float A[3];     // front colour accumulated so far
     float Cout[3];  // forward output of the pixel
     float g[3];     // dL / d out_rgb
-    float2 *slots;  // this pixel's scratch slots, indexed by contributor rank
+    float2 *slots;  // this lane's column of its quadrant's slot rows (row = contributor rank, stride 64)
 };
 
-// Blend (forward) or replay (pass 1) one popped entry.
+// Blend (forward) or replay (pass 1) one popped entry.  Pass 1 writes the
+// slot of every contributor it pops: the two scalars when the entry is
+// blended, zeros when the ray has terminated (at this entry or before), so
+// every slot below the pixel's contributor count is written exactly once.
 template <bool PASS1>
 __device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t item, uint32_t rank,
                                             float a, float t_min, BwdPixel &bp, uint32_t cap)
 {
-    if (a > 0.0f && !ps.done) {  // window fillers and idle lanes carry alpha 0
-        const float Tn = ps.T * (1.0f - a);
-        if (Tn < t_min) {
-            ps.done = true;
-        } else {
-            const float4 c = rec[(size_t)item * kRecQuads + 7];
-            const float W = ps.T * a;
-            if (PASS1) {
-                bp.A[0] += W * c.x;
-                bp.A[1] += W * c.y;
-                bp.A[2] += W * c.z;
-                const float cg = c.x * bp.g[0] + c.y * bp.g[1] + c.z * bp.g[2];
-                const float Sg = (bp.Cout[0] - bp.A[0]) * bp.g[0] + (bp.Cout[1] - bp.A[1]) * bp.g[1] +
-                                 (bp.Cout[2] - bp.A[2]) * bp.g[2];
-                if (rank < cap) bp.slots[rank] = make_float2(ps.T * cg - Sg / (1.0f - a), W);
+    if (a > 0.0f) {  // window fillers and idle lanes carry alpha 0
+        bool blends = false;
+        if (!ps.done) {
+            const float Tn = ps.T * (1.0f - a);
+            if (Tn < t_min) {
+                ps.done = true;
             } else {
-                ps.C[0] += W * c.x;
-                ps.C[1] += W * c.y;
-                ps.C[2] += W * c.z;
+                const float4 c = rec[(size_t)item * kRecQuads + 7];
+                const float W = ps.T * a;
+                if (PASS1) {
+                    bp.A[0] += W * c.x;
+                    bp.A[1] += W * c.y;
+                    bp.A[2] += W * c.z;
+                    const float cg = c.x * bp.g[0] + c.y * bp.g[1] + c.z * bp.g[2];
+                    const float Sg = (bp.Cout[0] - bp.A[0]) * bp.g[0] + (bp.Cout[1] - bp.A[1]) * bp.g[1] +
+                                     (bp.Cout[2] - bp.A[2]) * bp.g[2];
+                    // 1 - a >= 1 - alpha_max > 0
+                    if (rank < cap)
+                        bp.slots[(size_t)rank * 64] =
+                            make_float2(ps.T * cg - Sg * __builtin_amdgcn_rcpf(1.0f - a), W);
+                } else {
+                    ps.C[0] += W * c.x;
+                    ps.C[1] += W * c.y;
+                    ps.C[2] += W * c.z;
+                }
+                ps.T = Tn;
+                blends = true;
             }
-            ps.T = Tn;
         }
+        if (PASS1 && !blends && rank < cap) bp.slots[(size_t)rank * 64] = make_float2(0.0f, 0.0f);
     }
 }
 
@@ -195,7 +206,7 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     }
     uint32_t cap = 0;  // pass 1: slots of this pixel (its contributor count in the forward)
     if (PASS1 && inside) {
-        bp.slots = a.slots + a.pix_off[gpix];
+        bp.slots = a.slots + a.wave_off[4 * tile + wave] * 64 + lane;
         cap = a.n_ins[gpix];
     }
     uint32_t consumed = 0, rank = 0;
@@ -263,14 +274,15 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
         }
         if (contrib && ps.done && consumed == 0) consumed = i - start + 1;
     }
-    // drain the window in depth order (lanes already done pass alpha 0)
+    // drain the window in depth order (lanes already done only zero the
+    // slots of what they hold, in pass 1)
     const bool draining = !ps.done;
     if constexpr (K > 0) {
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const uint2 q = pay[wave][ws[k]][lane];
             const uint32_t rk = PASS1 ? pay_rank[wave][ws[k]][lane] : 0u;
-            blend_entry<PASS1>(ps, rec, q.x, rk, ps.done ? 0.0f : __uint_as_float(q.y), tmin, bp, cap);
+            blend_entry<PASS1>(ps, rec, q.x, rk, __uint_as_float(q.y), tmin, bp, cap);
         }
     }
     if (draining) consumed = end - start;
@@ -677,7 +689,7 @@ __global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, co
     // entries this pixel consumed in the forward, and its slots
     const uint32_t limit = inside ? start + a.n_done[gpix] : start;
     const uint32_t cap = inside ? a.n_ins[gpix] : 0;
-    const float2 *slots = a.slots + (inside ? a.pix_off[gpix] : 0);
+    const float2 *slots = a.slots + (inside ? a.wave_off[4 * tile + wave] * 64 + lane : 0);
     float g[3];
     for (int c = 0; c < 3; ++c) g[c] = inside ? vw.dL_drgb[c * hw + pix] : 0.0f;
     const float amin = a.alpha_min, amax = a.alpha_max, znear = (float)vw.cam.znear;
@@ -697,16 +709,15 @@ __global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, co
         if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) return;
         float2 s = make_float2(0.0f, 0.0f);
         if (contrib) {
-            if (rank < cap) s = slots[rank];
+            if (rank < cap) s = slots[(size_t)rank * 64];
             ++rank;
         }
         // 22 record gradients of this lane (zero when not blended)
         const float ga = s.x, W = s.y;
         const bool moves = contrib && al < amax && W > 0.0f;  // a clamped alpha does not move
-        const float gat = moves ? ga * al / h.at : 0.0f;
+        const float gat = moves ? ga * al * __builtin_amdgcn_rcpf(h.at) : 0.0f;  // alpha~ >= alpha_min > 0
         const float gr2 = moves ? -0.5f * ga * al : 0.0f;
-        const float invD = 1.0f / e.D;
-        const float kw = 2.0f * gr2 * invD, kr = -2.0f * gr2 * rho2 * invD;
+        const float kw = 2.0f * gr2 * inv, kr = -2.0f * gr2 * rho2 * inv;
         float vals22[22];
         const float gr[3] = {kr * e.rx, kr * e.ry, kr * e.rz};
         const float gw[3] = {kw * e.wx, kw * e.wy, kw * e.wz};
@@ -820,6 +831,34 @@ hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32
     case 16: return launch_long_k<16>(a, stats, long_tiles, n_long, grid, pixmask, summary, s);
     default: return hipErrorInvalidValue;  // K = 32 keeps every tile in k_blend (long_list = max)
     }
+}
+
+// One workgroup per tile, one wave per 8x8 quadrant (the pixel mapping of
+// k_blend): the quadrant's largest contributor count.
+__global__ __launch_bounds__(256) void k_wave_caps(const ViewDev *__restrict__ views, int nviews,
+                                                   const uint32_t *__restrict__ n_ins, uint32_t *__restrict__ caps)
+{
+    const int tile = (int)blockIdx.x;
+    int v = 0;
+    while (v + 1 < nviews && views[v + 1].tile_base <= tile) ++v;
+    const ViewDev &vw = views[v];
+    const int lt = tile - vw.tile_base;
+    const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
+    const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
+    const bool inside = px < vw.cam.width && py < vw.cam.height;
+    uint32_t m = inside ? n_ins[vw.pix_base + (size_t)py * vw.cam.width + px] : 0u;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if (lane == 0) caps[4 * tile + wave] = m;
+}
+
+hipError_t launch_wave_caps(const ViewDev *views, int nviews, int total_tiles, const uint32_t *n_ins, uint32_t *caps,
+                            hipStream_t s)
+{
+    if (total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wave_caps, dim3((unsigned)total_tiles), dim3(256), 0, s, views, nviews, n_ins, caps);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s)
