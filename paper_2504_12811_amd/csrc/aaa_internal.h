@@ -202,8 +202,18 @@ struct PreArgs {
     uint32_t *area;   // tiles in the rectangle (0 unless visible)
     float4 *rec;
     float4 *cull;
+    float4 *bbox;     // screen bounding box of the rho^2 <= tau region: x_lo, x_hi, y_lo, y_hi (pixels)
 };
 hipError_t launch_preprocess(const PreArgs &a, hipStream_t s);
+
+// Sorted pair values: the Gaussian index, and, when the scene has fewer than
+// 2^28 Gaussians, the 8x8 quadrants of the pair's tile that the Gaussian's
+// screen bounding box reaches in bits 28..31 (bit 28 + 2 qy + qx, the blend
+// wave of that quadrant).  A wave skips the entries whose bit is clear: no
+// pixel centre of its quadrant lies within half a pixel of the box.
+constexpr int kQuadShift = 28;
+constexpr uint32_t kQuadIdMask = (1u << kQuadShift) - 1u;
+constexpr int64_t kQuadMaxGaussians = (int64_t)1 << kQuadShift;
 
 // One training camera of K7: world->view rows (3x4, row-major), intrinsics,
 // image size, near plane.
@@ -222,10 +232,13 @@ hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               unsigned long long *tests, hipStream_t s);
+// quads: pack the quadrant bits of each pair (from bbox) into its value
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              hipStream_t s);
+                              const float4 *bbox, bool quads, hipStream_t s);
+// p[i] &= mask for i < n
+hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s);
 
@@ -237,6 +250,8 @@ hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges
 struct BlendArgs {
     const float4 *rec;             // per item (i * nviews + v)
     const uint32_t *vals;
+    uint32_t id_mask;              // Gaussian index bits of a value (kQuadIdMask when values carry quadrant bits)
+    uint32_t quad_on;              // bits forced on before the quadrant test (~kQuadIdMask when they carry none)
     const uint32_t *ranges;        // per global tile
     const ViewDev *views;
     int nviews;

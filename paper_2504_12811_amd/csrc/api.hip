@@ -69,7 +69,7 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 }
 
 struct Layout {
-    size_t hdr, views, status, rect, area, area_off, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+    size_t hdr, views, status, rect, bbox, area, area_off, rec, cull, counts, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
         ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
@@ -89,6 +89,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.views = take(sizeof(aaa::ViewDev) * (size_t)(sh.nviews > 0 ? sh.nviews : 1));
     L.status = take(items * 4);
     L.rect = take(items * 16);
+    L.bbox = take(items * 16);
     L.area = take(items * 4);
     L.area_off = take((items + 1) * 8);
     L.rec = take(items * 16 * aaa::kRecQuads);
@@ -229,7 +230,22 @@ aaa::PreArgs pre_args(const aaa_scene *scene, int nviews, const aaa_settings *se
     pa.area = at<uint32_t>(ws, L.area);
     pa.rec = at<float4>(ws, L.rec);
     pa.cull = at<float4>(ws, L.cull);
+    pa.bbox = at<float4>(ws, L.bbox);
     return pa;
+}
+
+// Sorted values carry quadrant bits when the Gaussian index fits below them
+// (and not in the ablation without tile culling, which keeps the plain 2D
+// rectangle of tiles and nothing finer).
+bool quad_values(int64_t n, const aaa_settings *st)
+{
+    return n < aaa::kQuadMaxGaussians && (st->flags & AAA_NO_TILE_CULL) == 0;
+}
+
+void set_value_bits(aaa::BlendArgs &ba, bool quads)
+{
+    ba.id_mask = quads ? aaa::kQuadIdMask : 0xffffffffu;
+    ba.quad_on = quads ? 0u : ~aaa::kQuadIdMask;
 }
 
 }  // namespace
@@ -448,8 +464,9 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
     uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
     STAGE_MARK(4);
+    const bool quads = quad_values(n, settings);
     HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
-                                    offsets, max_pairs, keys, vals, s));
+                                    offsets, max_pairs, keys, vals, pa.bbox, quads, s));
     STAGE_MARK(5);
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,
@@ -472,6 +489,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     aaa::BlendArgs ba;
     ba.rec = pa.rec;
     ba.vals = svals;
+    set_value_bits(ba, quads);
     ba.ranges = ranges;
     ba.views = pa.views;
     ba.nviews = n_views;
@@ -608,6 +626,7 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     aaa::BlendArgs ba;
     ba.rec = pa.rec;
     ba.vals = at<uint32_t>(ws, alt ? L.vals_alt : L.vals);
+    set_value_bits(ba, quad_values(n, settings));
     ba.ranges = at<uint32_t>(ws, L.ranges);
     ba.views = pa.views;
     ba.nviews = n_views;
@@ -693,7 +712,11 @@ int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_p
     if (P > cap) return fail(AAA_ERR_INVALID, "cap %llu < %llu pairs", (unsigned long long)cap, (unsigned long long)P);
     const bool alt = sorted_in_alt(sh.total_tiles);
     if (keys && P) HIP_TRY(hipMemcpyAsync(keys, w + (alt ? L.keys_alt : L.keys), P * 8, hipMemcpyDeviceToDevice, s));
-    if (values && P) HIP_TRY(hipMemcpyAsync(values, w + (alt ? L.vals_alt : L.vals), P * 4, hipMemcpyDeviceToDevice, s));
+    if (values && P) {
+        HIP_TRY(hipMemcpyAsync(values, w + (alt ? L.vals_alt : L.vals), P * 4, hipMemcpyDeviceToDevice, s));
+        // indices only (below 2^28 the mask also clears any quadrant bits)
+        if (scene->n < aaa::kQuadMaxGaussians) HIP_TRY(aaa::launch_and_u32(values, P, aaa::kQuadIdMask, s));
+    }
     if (ranges) HIP_TRY(hipMemcpyAsync(ranges, w + L.ranges, (size_t)sh.total_tiles * 8, hipMemcpyDeviceToDevice, s));
     return AAA_OK;
 }

@@ -216,7 +216,9 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
 
     for (uint32_t i = start; i < end; ++i) {
         if (__builtin_amdgcn_ballot_w64(!ps.done) == 0ull) break;
-        const uint32_t id = vals[i] * (uint32_t)nv + (uint32_t)v;  // item of (Gaussian, view)
+        const uint32_t raw = vals[i];
+        if ((((raw | a.quad_on) >> (kQuadShift + wave)) & 1u) == 0u) continue;  // box misses this quadrant
+        const uint32_t id = (raw & a.id_mask) * (uint32_t)nv + (uint32_t)v;  // item of (Gaussian, view)
         const float4 *r = rec + (size_t)id * kRecQuads;
         const float4 q0 = r[0], q1 = r[1], q2 = r[2], q3 = r[3], q4 = r[4], q5 = r[5], q6 = r[6];
         if (STATS && !ps.done) ++n_eval;
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(256) void k_long_masks(const float4 *__restrict__ r
         for (int idx = t; idx < 64 * 7; idx += 256) {
             const uint32_t e = w * 64 + (uint32_t)(idx / 7);
             if (e >= L.start && e < L.end)
-                srec[idx / 7][idx % 7] = rec[(size_t)(vals[e] * nv + (uint32_t)L.v) * kRecQuads + idx % 7];
+                srec[idx / 7][idx % 7] = rec[(size_t)((vals[e] & a.id_mask) * nv + (uint32_t)L.v) * kRecQuads + idx % 7];
         }
         __syncthreads();
         uint64_t bits = 0;
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
     float4 r0, r1, r2, r3, r4, r5, r6, r7;
     auto fetch = [&](uint32_t e) {
         if (e < end) {
-            const float4 *r = rec + (size_t)(vals[e] * nv + (uint32_t)L.v) * kRecQuads;
+            const float4 *r = rec + (size_t)((vals[e] & a.id_mask) * nv + (uint32_t)L.v) * kRecQuads;
             r0 = r[0]; r1 = r[1]; r2 = r[2]; r3 = r[3]; r4 = r[4]; r5 = r[5]; r6 = r[6]; r7 = r[7];
         }
     };
@@ -695,7 +697,10 @@ __global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, co
     const float amin = a.alpha_min, amax = a.alpha_max, znear = (float)vw.cam.znear;
     uint32_t rank = 0;
 
-    auto step = [&](uint32_t i, uint32_t item, const Hot &h) {
+    const uint32_t qbit = 1u << (kQuadShift + wave);
+    auto step = [&](uint32_t i, uint32_t raw, const Hot &h) {
+        if (((raw | a.quad_on) & qbit) == 0u) return;  // box misses this quadrant: no pixel contributes
+        const uint32_t item = (raw & a.id_mask) * nv + (uint32_t)v;
         const bool active = i < limit;
         const float dx = fxp - h.xa, dy = fyp - h.ya;
         const Eval e = eval_line(dx, dy, h);
@@ -740,16 +745,16 @@ __global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, co
 
     if (start < end) {
         // same software pipeline as the forward
-        uint32_t id = vals[start] * nv + (uint32_t)v;
+        uint32_t raw = vals[start];
         uint32_t raw_next = vals[start + 1 < end ? start + 1 : end - 1];
-        Hot h = load_hot(rec, id);
+        Hot h = load_hot(rec, (raw & a.id_mask) * nv + (uint32_t)v);
         for (uint32_t i = start; i < end; ++i) {
             if (__builtin_amdgcn_ballot_w64(i < limit) == 0ull) break;
-            const uint32_t id_next = raw_next * nv + (uint32_t)v;
+            const uint32_t raw_cur = raw_next;
             raw_next = vals[i + 2 < end ? i + 2 : end - 1];
-            const Hot h_next = load_hot(rec, id_next);
-            step(i, id, h);
-            id = id_next;
+            const Hot h_next = load_hot(rec, (raw_cur & a.id_mask) * nv + (uint32_t)v);
+            step(i, raw, h);
+            raw = raw_cur;
             h = h_next;
         }
     }

@@ -48,6 +48,20 @@ __device__ __forceinline__ float tile_depth(const TileGeom<float> &g, int tx, in
     return l / dot3(r, r);
 }
 
+// Quadrants (bit 2 qy + qx) of tile (tx, ty) whose 8x8 pixel square meets
+// the bounding box; pixel centres lie half a pixel inside the square.
+__device__ __forceinline__ uint32_t quad_bits(float4 box, int tx, int ty)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float x0 = (float)(tx * kTile + (q & 1) * 8), y0 = (float)(ty * kTile + (q >> 1) * 8);
+        const bool meets = box.x <= x0 + 8.0f && box.y >= x0 && box.z <= y0 + 8.0f && box.w >= y0;
+        m |= meets ? 1u << q : 0u;
+    }
+    return m;
+}
+
 __device__ __forceinline__ uint64_t bits_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
@@ -91,7 +105,8 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                                                bool tile_cull, uint32_t *__restrict__ counts,
                                                unsigned long long *__restrict__ tests,
                                                const uint64_t *__restrict__ offsets, uint64_t max_pairs,
-                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
+                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                               const float4 *__restrict__ bbox, bool quads)
 {
     const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
     const int lane = (int)__lane_id();
@@ -159,7 +174,9 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                 if (slot < max_pairs) {
                     const uint32_t tile = (uint32_t)(vw.tile_base + ty * vw.cam.tiles_x + tx);
                     keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(geo, tx, ty));
-                    vals[slot] = (uint32_t)(g / nviews);
+                    uint32_t val = (uint32_t)(g / nviews);
+                    if (quads) val |= quad_bits(bbox[g], tx, ty) << kQuadShift;
+                    vals[slot] = val;
                 }
             }
         }
@@ -270,18 +287,33 @@ hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 
                        counts, items);
     hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
                        nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0, (uint64_t *)nullptr,
-                       (uint32_t *)nullptr);
+                       (uint32_t *)nullptr, (const float4 *)nullptr, false);
     return hipGetLastError();
 }
 
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              hipStream_t s)
+                              const float4 *bbox, bool quads, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
-                       nviews, tile_cull, counts, (unsigned long long *)nullptr, offsets, max_pairs, keys, vals);
+                       nviews, tile_cull, counts, (unsigned long long *)nullptr, offsets, max_pairs, keys, vals, bbox,
+                       quads);
+    return hipGetLastError();
+}
+
+__global__ void k_and_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t mask)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] &= mask;
+}
+
+hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_and_u32, dim3((unsigned)std::min<uint64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, n,
+                       mask);
     return hipGetLastError();
 }
 

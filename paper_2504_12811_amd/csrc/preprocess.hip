@@ -98,15 +98,20 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
         return;
     }
     int x0 = 0, x1 = cam.tiles_x, y0 = 0, y1 = cam.tiles_y;
+    float4 box = make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY);
     if (!fullx) {
         double px_lo = cam.cx + cam.fx * tan(tx_lo) - 1e-3, px_hi = cam.cx + cam.fx * tan(tx_hi) + 1e-3;
         x0 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_lo / kTile)));
         x1 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_hi / kTile) + 1.0));
+        box.x = (float)px_lo;
+        box.y = (float)px_hi;
     }
     if (!fully) {
         double py_lo = cam.cy + cam.fy * tan(ty_lo) - 1e-3, py_hi = cam.cy + cam.fy * tan(ty_hi) + 1e-3;
         y0 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_lo / kTile)));
         y1 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_hi / kTile) + 1.0));
+        box.z = (float)py_lo;
+        box.w = (float)py_hi;
     }
     if (x0 >= x1 || y0 >= y1) {
         a.status[item] = kOutside;
@@ -203,6 +208,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     cu[6] = make_float4(g.qy0[2], g.qy1[0], g.qy1[1], g.qy1[2]);
     cu[7] = make_float4(muv[0], muv[1], muv[2], 0.f);
     a.rect[item] = make_int4(x0, x1, y0, y1);
+    a.bbox[item] = box;
     a.area[item] = (uint32_t)((x1 - x0) * (y1 - y0));
     a.status[item] = kVisible;
 }
