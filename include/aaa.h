@@ -96,6 +96,7 @@ typedef struct {
 #define AAA_STATS 8u           /* count evaluations / contributors (small overhead) */
 #define AAA_TIMING 16u         /* time each stage with HIP events on `stream` (see aaa_stage_times) */
 #define AAA_LONG_ALL 32u       /* diagnostic: every tile takes the long-list blend path (same results) */
+#define AAA_WIDE_RANKS 64u     /* diagnostic: the backward replay keeps 32-bit contributor ranks (same results) */
 
 /* Method settings.  filter_k: filter size k (0.3 in Sec. 4).  ray_window:
  * capacity K of the per-ray re-sort window (0 = blend in tile order; the

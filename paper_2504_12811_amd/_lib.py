@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libaaa_hip.so")
 
 AAA_OK, AAA_ERR_INVALID, AAA_ERR_WORKSPACE, AAA_ERR_PAIR_OVERFLOW, AAA_ERR_HIP, AAA_ERR_UNSUPPORTED = range(6)
 AAA_FILTER_OFF, AAA_FILTER_VOLUME, AAA_NO_TILE_CULL, AAA_STATS, AAA_TIMING, AAA_LONG_ALL = 1, 2, 4, 8, 16, 32
+AAA_WIDE_RANKS = 64
 AAA_MAX_TRAIN_CAMERAS = 4096
 STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "frame"]
 

@@ -268,6 +268,7 @@ struct BlendArgs {
     // load one contiguous row per rank
     const uint64_t *wave_off;
     float2 *slots;
+    bool rank16;                   // pass 1: every contributor rank fits 16 bits
     // forward only: tiles with longer lists are left to k_blend_long when
     // *n_long (written by k_find_long) is at most kMaxLongTiles
     uint32_t long_list;
@@ -275,9 +276,10 @@ struct BlendArgs {
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s);
-// caps[4 * tile + wave] = the largest n_ins over the quadrant's pixels
+// caps[4 * tile + wave] = the largest n_ins over the quadrant's pixels;
+// *max_big (zeroed beforehand) = the largest of those above 65535, if any
 hipError_t launch_wave_caps(const ViewDev *views, int nviews, int total_tiles, const uint32_t *n_ins, uint32_t *caps,
-                            hipStream_t s);
+                            uint32_t *max_big, hipStream_t s);
 // Long tile lists: k_find_long collects tiles with more than a.long_list
 // entries (n_long must be zero beforehand); launch_blend_long computes the
 // per-pixel entry masks (pixmask: (pairs / 64 + tiles + 2) * 256 words;

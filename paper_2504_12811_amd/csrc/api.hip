@@ -503,6 +503,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.grad_rec = nullptr;
     ba.wave_off = nullptr;
     ba.slots = nullptr;
+    ba.rank16 = false;
     const int K = settings->ray_window;
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
     ba.long_list = K > 16 ? 0xffffffffu : (long_all ? 0u : aaa::kLongList);
@@ -556,18 +557,25 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
 
 // Slots of the backward: each 8x8 quadrant of a tile gets one row of 64
 // slots (a lane each) per contributor rank of its busiest pixel, placed by an
-// exclusive scan of those row counts.
-static int backward_slots(const Shape &sh, const Layout &L, void *ws, hipStream_t s, uint64_t *total)
+// exclusive scan of those row counts.  *rank16: every pixel has at most 65536
+// contributors (ranks 0..65535).
+static int backward_slots(const Shape &sh, const Layout &L, void *ws, hipStream_t s, uint64_t *total,
+                          bool *rank16 = nullptr)
 {
     const int64_t quads = 4 * sh.total_tiles;
+    uint32_t *max_big = (uint32_t *)(at<unsigned long long>(ws, L.hdr) + 10);
+    HIP_TRY(hipMemsetAsync(max_big, 0, 4, s));
     HIP_TRY(aaa::launch_wave_caps(at<aaa::ViewDev>(ws, L.views), sh.nviews, (int)sh.total_tiles,
-                                  at<uint32_t>(ws, L.n_ins), at<uint32_t>(ws, L.wave_caps), s));
+                                  at<uint32_t>(ws, L.n_ins), at<uint32_t>(ws, L.wave_caps), max_big, s));
     HIP_TRY(aaa::launch_exclusive_scan(at<uint32_t>(ws, L.wave_caps), at<uint64_t>(ws, L.wave_off), quads,
                                        at<void>(ws, L.wave_scan_tmp), s));
     uint64_t rows = 0;
+    uint32_t big = 0;
     HIP_TRY(hipMemcpyAsync(&rows, at<uint64_t>(ws, L.wave_off) + quads, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&big, max_big, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *total = rows * 64;
+    if (rank16) *rank16 = big == 0;
     return AAA_OK;
 }
 
@@ -609,7 +617,8 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     const int64_t n = scene->n;
     if (n == 0) return AAA_OK;
     uint64_t total = 0;
-    rc = backward_slots(sh, L, ws, s, &total);
+    bool rank16 = false;
+    rc = backward_slots(sh, L, ws, s, &total, &rank16);
     if (rc) return rc;
     if (total > 0 && (!scratch || scratch_bytes < total * sizeof(float2)))
         return fail(AAA_ERR_WORKSPACE, "backward scratch %zu < %zu bytes (aaa_backward_scratch_size)", scratch_bytes,
@@ -640,6 +649,7 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     ba.grad_rec = grad_rec;
     ba.wave_off = at<uint64_t>(ws, L.wave_off);
     ba.slots = (float2 *)scratch;
+    ba.rank16 = rank16 && (settings->flags & AAA_WIDE_RANKS) == 0;
     ba.long_list = 0xffffffffu;
     ba.n_long = nullptr;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));  // pass 1: window replay

@@ -149,7 +149,9 @@ __device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__rest
     }
 }
 
-template <int K, bool STATS, bool PASS1>
+// RankT: the LDS type of pass 1's contributor ranks (uint16_t when every
+// rank of the frame fits, which leaves room for a fourth workgroup per CU).
+template <int K, bool STATS, bool PASS1, typename RankT = uint32_t>
 __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
                                                BlendArgs a)
 {
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     // two registers per position take part in the sorting network.
     constexpr int KS = K > 0 ? K : 1;
     __shared__ uint2 pay[K > 0 ? 4 : 1][KS][64];
-    __shared__ uint32_t pay_rank[PASS1 && K > 0 ? 4 : 1][PASS1 ? KS : 1][64];
+    __shared__ RankT pay_rank[PASS1 && K > 0 ? 4 : 1][PASS1 ? KS : 1][64];
     float wz[KS];
     uint32_t ws[KS];
 #pragma unroll
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
             const uint32_t pop_rk = front_out ? frk : my_rank;
             if (front_out) {
                 pay[wave][fs][lane] = make_uint2(id, __float_as_uint(ak));
-                if (PASS1) pay_rank[wave][fs][lane] = my_rank;
+                if (PASS1) pay_rank[wave][fs][lane] = (RankT)my_rank;
             }
             blend_entry<PASS1>(ps, rec, pop_id, pop_rk, pop_a, tmin, bp, cap);
         }
@@ -766,7 +768,9 @@ hipError_t launch_k(const BlendArgs &a, bool stats, bool pass1, hipStream_t s)
     const int ntiles = a.total_tiles;
     const int per = (ntiles + 7) / 8;
     dim3 grid((unsigned)(per * 8));
-    if (pass1)
+    if (pass1 && a.rank16)
+        hipLaunchKernelGGL((k_blend<K, false, true, uint16_t>), grid, dim3(256), 0, s, a.rec, a.vals, a);
+    else if (pass1)
         hipLaunchKernelGGL((k_blend<K, false, true>), grid, dim3(256), 0, s, a.rec, a.vals, a);
     else if (stats)
         hipLaunchKernelGGL((k_blend<K, true, false>), grid, dim3(256), 0, s, a.rec, a.vals, a);
@@ -841,7 +845,8 @@ hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32
 // One workgroup per tile, one wave per 8x8 quadrant (the pixel mapping of
 // k_blend): the quadrant's largest contributor count.
 __global__ __launch_bounds__(256) void k_wave_caps(const ViewDev *__restrict__ views, int nviews,
-                                                   const uint32_t *__restrict__ n_ins, uint32_t *__restrict__ caps)
+                                                   const uint32_t *__restrict__ n_ins, uint32_t *__restrict__ caps,
+                                                   uint32_t *__restrict__ max_big)
 {
     const int tile = (int)blockIdx.x;
     int v = 0;
@@ -855,14 +860,17 @@ __global__ __launch_bounds__(256) void k_wave_caps(const ViewDev *__restrict__ v
     const bool inside = px < vw.cam.width && py < vw.cam.height;
     uint32_t m = inside ? n_ins[vw.pix_base + (size_t)py * vw.cam.width + px] : 0u;
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if (lane == 0) caps[4 * tile + wave] = m;
+    if (lane == 0) {
+        caps[4 * tile + wave] = m;
+        if (m > 0x10000u) atomicMax(max_big, m);  // rare: pixels with more than 65536 contributors
+    }
 }
 
 hipError_t launch_wave_caps(const ViewDev *views, int nviews, int total_tiles, const uint32_t *n_ins, uint32_t *caps,
-                            hipStream_t s)
+                            uint32_t *max_big, hipStream_t s)
 {
     if (total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_wave_caps, dim3((unsigned)total_tiles), dim3(256), 0, s, views, nviews, n_ins, caps);
+    hipLaunchKernelGGL(k_wave_caps, dim3((unsigned)total_tiles), dim3(256), 0, s, views, nviews, n_ins, caps, max_big);
     return hipGetLastError();
 }
 

@@ -183,12 +183,13 @@ class Rasterizer:
             return rgbs, Ts, out
         raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
 
-    def backward_batch(self, scene: DeviceScene, cams, settings, ws: Workspace, out_rgbs, grad_rgbs) -> dict:
+    def backward_batch(self, scene: DeviceScene, cams, settings, ws: Workspace, out_rgbs, grad_rgbs,
+                       flags: int = 0) -> dict:
         """Gradients of sum_v sum(grad_rgbs[v] * rgb_v) for the batch held in `ws`."""
         sc = scene.abi()
         V = len(cams)
         carr = (L.Camera * V)(*[L.make_camera(c) for c in cams])
-        st = L.make_settings(settings)
+        st = L.make_settings(settings, flags)
         grads = {k: torch.zeros_like(t) for k, t in zip(["means", "log_scales", "quats", "opacity_logits", "sh"],
                                                         scene.tensors())}
         g = L.SceneGrad()
@@ -214,11 +215,11 @@ class Rasterizer:
         return ptr, int(need.value)
 
     def backward(self, scene: DeviceScene, cam, settings, ws: Workspace, out_rgb: torch.Tensor,
-                 grad_rgb: torch.Tensor) -> dict:
+                 grad_rgb: torch.Tensor, flags: int = 0) -> dict:
         """Gradients of sum(grad_rgb * rgb) for the frame held in `ws`."""
         sc = scene.abi()
         c = L.make_camera(cam)
-        st = L.make_settings(settings)
+        st = L.make_settings(settings, flags)
         grads = {k: torch.zeros_like(t) for k, t in zip(["means", "log_scales", "quats", "opacity_logits", "sh"],
                                                         scene.tensors())}
         g = L.SceneGrad()
