@@ -108,13 +108,17 @@ struct BwdPixel {
     float2 *slots;  // this lane's column of its quadrant's slot rows (row = contributor rank, stride 64)
 };
 
+__device__ __forceinline__ float3 float3_of(float4 q) { return make_float3(q.x, q.y, q.z); }
+
 // Blend (forward) or replay (pass 1) one popped entry.  Pass 1 writes the
 // slot of every contributor it pops: the two scalars when the entry is
 // blended, zeros when the ray has terminated (at this entry or before), so
 // every slot below the pixel's contributor count is written exactly once.
+// The forward passes the entry's colour in `cf` (gathered ahead of use);
+// pass 1 gathers it here, only for entries that blend.
 template <bool PASS1>
-__device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t item, uint32_t rank,
-                                            float a, float t_min, BwdPixel &bp, uint32_t cap)
+__device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__restrict__ rec, uint32_t item, float3 cf,
+                                            uint32_t rank, float a, float t_min, BwdPixel &bp, uint32_t cap)
 {
     if (a > 0.0f) {  // window fillers and idle lanes carry alpha 0
         bool blends = false;
@@ -123,7 +127,7 @@ __device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__rest
             if (Tn < t_min) {
                 ps.done = true;
             } else {
-                const float4 c = rec[(size_t)item * kRecQuads + 7];
+                const float3 c = PASS1 ? float3_of(rec[(size_t)item * kRecQuads + 7]) : cf;
                 const float W = ps.T * a;
                 if (PASS1) {
                     bp.A[0] += W * c.x;
@@ -242,8 +246,10 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
         if (STATS) ++w_contrib;
         const uint32_t my_rank = rank;
         if (contrib) ++rank;
+        // the entry's own colour: scalar loads, like the rest of its record
+        const float3 c_new = PASS1 ? make_float3(0.0f, 0.0f, 0.0f) : float3_of(r[7]);
         if constexpr (K == 0) {
-            blend_entry<PASS1>(ps, rec, id, my_rank, contrib ? al : 0.0f, tmin, bp, cap);
+            blend_entry<PASS1>(ps, rec, id, c_new, my_rank, contrib ? al : 0.0f, tmin, bp, cap);
         } else {
             // Non-contributing lanes insert a NaN depth: every comparison is
             // false, the window stays as it is and the popped entry is the
@@ -256,6 +262,10 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
             const uint2 fp = pay[wave][fs][lane];
             const uint32_t frk = PASS1 ? pay_rank[wave][fs][lane] : 0u;
             const bool front_out = wz[0] <= zk;
+            // forward: gather the front's colour before the sorting network,
+            // so that its latency overlaps the network
+            float4 fc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (!PASS1 && front_out) fc = rec[(size_t)fp.x * kRecQuads + 7];
             {
                 bool gcur = front_out;
 #pragma unroll
@@ -269,12 +279,13 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
             }
             const float pop_a = front_out ? __uint_as_float(fp.y) : ak;
             const uint32_t pop_id = front_out ? fp.x : id;
+            const float3 pop_c = front_out ? float3_of(fc) : c_new;
             const uint32_t pop_rk = front_out ? frk : my_rank;
             if (front_out) {
                 pay[wave][fs][lane] = make_uint2(id, __float_as_uint(ak));
                 if (PASS1) pay_rank[wave][fs][lane] = (RankT)my_rank;
             }
-            blend_entry<PASS1>(ps, rec, pop_id, pop_rk, pop_a, tmin, bp, cap);
+            blend_entry<PASS1>(ps, rec, pop_id, pop_c, pop_rk, pop_a, tmin, bp, cap);
         }
         if (contrib && ps.done && consumed == 0) consumed = i - start + 1;
     }
@@ -286,7 +297,8 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
         for (int k = 0; k < KS; ++k) {
             const uint2 q = pay[wave][ws[k]][lane];
             const uint32_t rk = PASS1 ? pay_rank[wave][ws[k]][lane] : 0u;
-            blend_entry<PASS1>(ps, rec, q.x, rk, __uint_as_float(q.y), tmin, bp, cap);
+            const float3 c = PASS1 ? make_float3(0.0f, 0.0f, 0.0f) : float3_of(rec[(size_t)q.x * kRecQuads + 7]);
+            blend_entry<PASS1>(ps, rec, q.x, c, rk, __uint_as_float(q.y), tmin, bp, cap);
         }
     }
     if (draining) consumed = end - start;
