@@ -1,8 +1,10 @@
 // K3: stable LSD radix sort of (uint64 key, uint32 value) pairs, 8-bit
 // digits, and K4: tile ranges of the sorted keys.
 //
-// Each pass: (1) per-block digit histograms, (2) an exclusive scan over the
-// digit-major [digit][block] table, (3) a stable scatter.  A block owns 4096
+// Each pass: (1) per-block digit histograms into a digit-major [digit][block]
+// table, (2) one workgroup per digit scans its row in place (the block's
+// offset within the digit) and records the digit's total, (3) a stable
+// scatter, whose workgroups add the prefix of the digit totals themselves.  A block owns 4096
 // consecutive keys; each of its four wavefronts ranks a contiguous quarter in
 // rounds of 64 with a ballot-based match on the digit bits (lanes with equal
 // digits see each other through eight ballots), so the rank of a key is the
@@ -50,14 +52,45 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
     hist[(uint64_t)t * nblocks + blockIdx.x] = s;
 }
 
+// Row d of the [digit][block] table: exclusive prefix over the blocks, in
+// place, and the row total in totals[d].
+__global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ hist, uint32_t nblocks,
+                                                         uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t wsum[4];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    uint32_t *row = hist + (uint64_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nblocks; c0 += kThreads) {
+        const uint32_t i = c0 + (uint32_t)t;
+        const uint32_t v = i < nblocks ? row[i] : 0u;
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t wpre = 0;
+        for (int w = 0; w < wave; ++w) wpre += wsum[w];
+        const uint32_t chunk = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (i < nblocks) row[i] = carry + wpre + x - v;
+        carry += chunk;
+        __syncthreads();
+    }
+    if (t == 0) totals[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ keys_in,
                                                       const uint32_t *__restrict__ vals_in, uint64_t n, int shift,
-                                                      const uint64_t *__restrict__ offsets, uint32_t nblocks,
+                                                      const uint32_t *__restrict__ offsets,
+                                                      const uint32_t *__restrict__ totals, uint32_t nblocks,
                                                       uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
 {
     __shared__ uint32_t cnt[4][kBins];   // per-wave digit counts, then per-wave prefixes
     __shared__ uint32_t lbase[kBins];    // block-local start of each digit
     __shared__ uint32_t wsum[4];
+    __shared__ uint64_t gsum[4];
     __shared__ uint64_t gbase[kBins];    // global start of each digit for this block
     __shared__ uint64_t skey[kPerBlock];
     __shared__ uint32_t sval[kPerBlock];
@@ -100,18 +133,32 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         cnt[w][t] = tot;
         tot += c;
     }
-    gbase[t] = offsets[(uint64_t)t * nblocks + blockIdx.x];
-    // exclusive scan of the block totals over the 256 digits
+    // exclusive scans over the 256 digits of the block totals (block-local
+    // starts) and of the global digit totals (global starts)
+    const uint64_t dt = totals[t];
     uint32_t x = tot;
+    uint64_t gx = dt;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
+        const uint64_t gy = __shfl_up(gx, off);
+        if (lane >= off) {
+            x += y;
+            gx += gy;
+        }
     }
-    if (lane == 63) wsum[wave] = x;
+    if (lane == 63) {
+        wsum[wave] = x;
+        gsum[wave] = gx;
+    }
     __syncthreads();
     uint32_t wpre = 0;
-    for (int w = 0; w < wave; ++w) wpre += wsum[w];
+    uint64_t gpre = 0;
+    for (int w = 0; w < wave; ++w) {
+        wpre += wsum[w];
+        gpre += gsum[w];
+    }
     lbase[t] = wpre + x - tot;
+    gbase[t] = gpre + gx - dt + offsets[(uint64_t)t * nblocks + blockIdx.x];
     __syncthreads();
     // stage the block's pairs in digit order (stable: wave order, then rank)
 #pragma unroll
@@ -159,10 +206,7 @@ size_t sort_tmp_bytes(uint64_t n)
     uint64_t cells = nb * kBins;
     size_t b = cells * sizeof(uint32_t);
     b = (b + 255) & ~(size_t)255;
-    b += (cells + 1) * sizeof(uint64_t);
-    b = (b + 255) & ~(size_t)255;
-    b += scan_tmp_bytes((int64_t)cells);
-    return b + 256;
+    return b + kBins * sizeof(uint32_t) + 256;
 }
 
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
@@ -174,19 +218,15 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     uint64_t cells = (uint64_t)nb * kBins;
     char *p = (char *)tmp;
     uint32_t *hist = (uint32_t *)p;
-    size_t o = (cells * sizeof(uint32_t) + 255) & ~(size_t)255;
-    uint64_t *offs = (uint64_t *)(p + o);
-    o += (((cells + 1) * sizeof(uint64_t)) + 255) & ~(size_t)255;
-    void *scan_tmp = p + o;
+    uint32_t *totals = (uint32_t *)(p + ((cells * sizeof(uint32_t) + 255) & ~(size_t)255));
     uint64_t *ki = keys, *ko = keys_alt;
     uint32_t *vi = vals, *vo = vals_alt;
     for (int shift = begin_bit; shift < end_bit; shift += kBits) {
         hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, n, shift, hist, nb);
-        hipError_t e = launch_exclusive_scan(hist, offs, (int64_t)cells, scan_tmp, s);
-        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_digit_scan, dim3(kBins), dim3(kThreads), 0, s, hist, nb, totals);
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, (const uint32_t *)vi, n,
-                           shift, (const uint64_t *)offs, nb, ko, vo);
-        e = hipGetLastError();
+                           shift, (const uint32_t *)hist, (const uint32_t *)totals, nb, ko, vo);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint64_t *tk = ki; ki = ko; ko = tk;
         uint32_t *tv = vi; vi = vo; vo = tv;
