@@ -173,6 +173,20 @@ __device__ __forceinline__ void load_tile_geom(const float4 *__restrict__ rec, c
     g.muv[0] = p7.x; g.muv[1] = p7.y; g.muv[2] = p7.z;
 }
 
+// The record part of load_tile_geom (lines, depth numerator, anchor).
+__device__ __forceinline__ void load_line_geom(const float4 *__restrict__ rec, TileGeom<float> &g)
+{
+    float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3], q4 = rec[4], q5 = rec[5];
+    g.c0[0] = q0.x; g.c0[1] = q0.y; g.c0[2] = q0.z;
+    g.c1[0] = q0.w; g.c1[1] = q1.x; g.c1[2] = q1.y;
+    g.c2[0] = q1.z; g.c2[1] = q1.w; g.c2[2] = q2.x;
+    g.w0[0] = q2.y; g.w0[1] = q2.z; g.w0[2] = q2.w;
+    g.w1[0] = q3.x; g.w1[1] = q3.y; g.w1[2] = q3.z;
+    g.w2[0] = q3.w; g.w2[1] = q4.x; g.w2[2] = q4.y;
+    g.l[0] = q4.z; g.l[1] = q4.w; g.l[2] = q5.x;
+    g.xa = q5.y; g.ya = q5.z;
+}
+
 // Order-preserving map of a float to uint32 (-0 -> +0; NaN never occurs).
 __device__ __forceinline__ uint32_t order_key(float f)
 {
@@ -229,14 +243,18 @@ hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams
 // Pair emission over the candidate tests numbered by area_off (exclusive
 // scan of the rectangle areas, items + 1 entries).  count: zeroes counts, then
 // adds the survivors per item.  write: takes slots by running counts down to 0.
+// keep_bits: room for keep_cap / 64 words; the counter stores one bit per
+// candidate test there (when the batch has at most keep_cap tests) and the
+// writer, given the same buffer and cap, reads them instead of testing again.
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              unsigned long long *tests, hipStream_t s);
+                              unsigned long long *tests, uint64_t *keep_bits, uint64_t keep_cap, hipStream_t s);
 // quads: pack the quadrant bits of each pair (from bbox) into its value
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              const float4 *bbox, bool quads, hipStream_t s);
+                              const float4 *bbox, bool quads, uint64_t *keep_bits, uint64_t keep_cap,
+                              hipStream_t s);
 // p[i] &= mask for i < n
 hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);

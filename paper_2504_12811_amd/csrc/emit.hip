@@ -106,9 +106,14 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                                                unsigned long long *__restrict__ tests,
                                                const uint64_t *__restrict__ offsets, uint64_t max_pairs,
                                                uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                               const float4 *__restrict__ bbox, bool quads)
+                                               const float4 *__restrict__ bbox, bool quads,
+                                               uint64_t *__restrict__ keep_bits, uint64_t keep_cap)
 {
     const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
+    // The counter leaves each wave's 64 test results in keep_bits (when the
+    // batch has at most keep_cap tests) and the writer reads them back
+    // instead of testing again.
+    const bool bits = keep_bits != nullptr && C <= keep_cap;
     const int lane = (int)__lane_id();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     unsigned long long n_first = 0, n_tests = 0;
@@ -152,16 +157,24 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         const int tx = r.x + j % w, ty = r.z + j / w;
         const ViewDev &vw = views[g % nviews];
         TileGeom<float> geo;
-        load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
-        const float tau = recs[(size_t)g * kRecQuads + 6].y;
-        const bool keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
+        bool keep;
+        if (WRITE && bits) {
+            keep = valid && ((keep_bits[t0 >> 6] >> lane) & 1ull);
+            if (keep) load_line_geom(recs + (size_t)g * kRecQuads, geo);
+        } else {
+            load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
+            const float tau = recs[(size_t)g * kRecQuads + 6].y;
+            keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
+        }
         // this item's lanes in the wave: [s0, s1)
         const int s0 = g0 > t0 ? (int)(g0 - t0) : 0;
         const int s1 = g1 - t0 < 64 ? (int)(g1 - t0) : 64;
         const uint64_t seg = (s1 >= 64 ? ~0ull : ((1ull << s1) - 1ull)) & ~bits_below(s0);
-        const uint64_t km = __ballot(keep) & seg;
+        const uint64_t kall = __ballot(keep);
+        const uint64_t km = kall & seg;
         const uint32_t nk = (uint32_t)__popcll(km);
         if (!WRITE) {
+            if (bits && lane == 0) keep_bits[t0 >> 6] = kall;
             if (valid && lane == s0 && nk) atomicAdd(&counts[g], nk);
             n_tests += valid ? 1 : 0;
             n_first += (valid && j == 0) ? 1 : 0;
@@ -280,26 +293,26 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              unsigned long long *tests, hipStream_t s)
+                              unsigned long long *tests, uint64_t *keep_bits, uint64_t keep_cap, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 1024)), dim3(256), 0, s,
                        counts, items);
     hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
                        nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0, (uint64_t *)nullptr,
-                       (uint32_t *)nullptr, (const float4 *)nullptr, false);
+                       (uint32_t *)nullptr, (const float4 *)nullptr, false, keep_bits, keep_cap);
     return hipGetLastError();
 }
 
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              const float4 *bbox, bool quads, hipStream_t s)
+                              const float4 *bbox, bool quads, uint64_t *keep_bits, uint64_t keep_cap, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
                        nviews, tile_cull, counts, (unsigned long long *)nullptr, offsets, max_pairs, keys, vals, bbox,
-                       quads);
+                       quads, keep_bits, keep_cap);
     return hipGetLastError();
 }
 
