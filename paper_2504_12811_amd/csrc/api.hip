@@ -68,8 +68,9 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
     return sh;
 }
 
-// Candidate tile tests whose keep bits the pair counter hands to the writer
-// (8 per pair of the pair buffer; larger batches test twice).
+// Candidate tile tests whose results the pair counter hands to the writer
+// (8 per pair of the pair buffer, 16 bytes per 64; larger batches test
+// twice).
 uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 1) * 8 + 63) / 64 * 64; }
 
 struct Layout {
@@ -99,7 +100,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.rec = take(items * 16 * aaa::kRecQuads);
     L.cull = take(items * 16 * aaa::kCullQuads);
     L.counts = take(items * 4);
-    L.keep_bits = take(keep_cap_of(max_pairs) / 8);
+    L.keep_bits = take(keep_cap_of(max_pairs) / 64 * 16);
     L.offsets = take((items + 1) * 8);
     L.scan_tmp = take(aaa::scan_tmp_bytes(items));
     uint64_t mp = max_pairs > 0 ? max_pairs : 1;
@@ -451,7 +452,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *offsets = at<uint64_t>(ws, L.offsets);
     uint64_t *area_off = at<uint64_t>(ws, L.area_off);
     HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s));
-    uint64_t *keep_bits = at<uint64_t>(ws, L.keep_bits);
+    uint4 *keep_bits = at<uint4>(ws, L.keep_bits);
     const uint64_t keep_cap = keep_cap_of(max_pairs);
     HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
                                     want_stats ? ctr : nullptr, keep_bits, keep_cap, s));

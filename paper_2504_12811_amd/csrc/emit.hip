@@ -107,12 +107,13 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                                                const uint64_t *__restrict__ offsets, uint64_t max_pairs,
                                                uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                const float4 *__restrict__ bbox, bool quads,
-                                               uint64_t *__restrict__ keep_bits, uint64_t keep_cap)
+                                               uint4 *__restrict__ keep_bits, uint64_t keep_cap)
 {
     const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
-    // The counter leaves each wave's 64 test results in keep_bits (when the
-    // batch has at most keep_cap tests) and the writer reads them back
-    // instead of testing again.
+    // The counter leaves, per wave of 64 tests, the test results and the
+    // wave's item bracket in keep_bits (when the batch has at most keep_cap
+    // tests); the writer reads them back instead of searching and testing
+    // again.
     const bool bits = keep_bits != nullptr && C <= keep_cap;
     const int lane = (int)__lane_id();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -125,8 +126,17 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         // then > 0).  The wave first brackets its 64 candidates with two
         // 64-way searches, then each lane searches the bracket.
         const uint64_t t_last = t0 + 63 < C ? t0 + 63 : C - 1;
-        const int64_t g_lo = wave_search(area_off, 0, nitems - 1, t0, lane);
-        const int64_t g_hi = wave_search(area_off, g_lo, nitems - 1, t_last, lane);
+        int64_t g_lo, g_hi;
+        uint64_t kept = 0;
+        if (WRITE && bits) {
+            const uint4 w = keep_bits[t0 >> 6];
+            kept = ((uint64_t)w.y << 32) | w.x;
+            g_lo = (int64_t)w.z;
+            g_hi = (int64_t)w.w;
+        } else {
+            g_lo = wave_search(area_off, 0, nitems - 1, t0, lane);
+            g_hi = wave_search(area_off, g_lo, nitems - 1, t_last, lane);
+        }
         int64_t g;
         if (g_hi - g_lo < 64) {
             // bracket held across the lanes: lane k has area_off[g_lo + k]
@@ -159,7 +169,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         TileGeom<float> geo;
         bool keep;
         if (WRITE && bits) {
-            keep = valid && ((keep_bits[t0 >> 6] >> lane) & 1ull);
+            keep = valid && ((kept >> lane) & 1ull);
             if (keep) load_line_geom(recs + (size_t)g * kRecQuads, geo);
         } else {
             load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
@@ -174,7 +184,8 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         const uint64_t km = kall & seg;
         const uint32_t nk = (uint32_t)__popcll(km);
         if (!WRITE) {
-            if (bits && lane == 0) keep_bits[t0 >> 6] = kall;
+            if (bits && lane == 0)
+                keep_bits[t0 >> 6] = make_uint4((uint32_t)kall, (uint32_t)(kall >> 32), (uint32_t)g_lo, (uint32_t)g_hi);
             if (valid && lane == s0 && nk) atomicAdd(&counts[g], nk);
             n_tests += valid ? 1 : 0;
             n_first += (valid && j == 0) ? 1 : 0;
@@ -293,7 +304,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
 
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              unsigned long long *tests, uint64_t *keep_bits, uint64_t keep_cap, hipStream_t s)
+                              unsigned long long *tests, uint4 *keep_bits, uint64_t keep_cap, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 1024)), dim3(256), 0, s,
@@ -307,7 +318,7 @@ hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              const float4 *bbox, bool quads, uint64_t *keep_bits, uint64_t keep_cap, hipStream_t s)
+                              const float4 *bbox, bool quads, uint4 *keep_bits, uint64_t keep_cap, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
