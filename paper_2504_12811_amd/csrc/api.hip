@@ -68,13 +68,13 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
     return sh;
 }
 
-// Candidate tile tests whose results the pair counter hands to the writer
-// (8 per pair of the pair buffer, 16 bytes per 64; larger batches test
-// twice).
+// Candidate tile tests for which the emitter keeps per-chunk items and keep
+// bits (8 per pair of the pair buffer, 12 bytes per 64; larger batches
+// search and test in both passes).
 uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 1) * 8 + 63) / 64 * 64; }
 
 struct Layout {
-    size_t hdr, views, status, rect, bbox, area, area_off, rec, cull, counts, keep_bits, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+    size_t hdr, views, status, rect, bbox, area, area_off, rec, cull, counts, keep_bits, chunk_item, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
         ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
@@ -100,7 +100,8 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.rec = take(items * 16 * aaa::kRecQuads);
     L.cull = take(items * 16 * aaa::kCullQuads);
     L.counts = take(items * 4);
-    L.keep_bits = take(keep_cap_of(max_pairs) / 64 * 16);
+    L.keep_bits = take(keep_cap_of(max_pairs) / 64 * 8);
+    L.chunk_item = take(keep_cap_of(max_pairs) / 64 * 4);
     L.offsets = take((items + 1) * 8);
     L.scan_tmp = take(aaa::scan_tmp_bytes(items));
     uint64_t mp = max_pairs > 0 ? max_pairs : 1;
@@ -452,10 +453,12 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *offsets = at<uint64_t>(ws, L.offsets);
     uint64_t *area_off = at<uint64_t>(ws, L.area_off);
     HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s));
-    uint4 *keep_bits = at<uint4>(ws, L.keep_bits);
+    uint64_t *keep_bits = at<uint64_t>(ws, L.keep_bits);
+    uint32_t *chunk_item = at<uint32_t>(ws, L.chunk_item);
     const uint64_t keep_cap = keep_cap_of(max_pairs);
+    HIP_TRY(aaa::launch_chunk_items(area_off, items, keep_cap, chunk_item, s));
     HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
-                                    want_stats ? ctr : nullptr, keep_bits, keep_cap, s));
+                                    want_stats ? ctr : nullptr, keep_bits, chunk_item, keep_cap, s));
     STAGE_MARK(2);
     HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, items, at<void>(ws, L.scan_tmp), s));
     STAGE_MARK(3);
@@ -473,7 +476,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     STAGE_MARK(4);
     const bool quads = quad_values(n, settings);
     HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
-                                    offsets, max_pairs, keys, vals, pa.bbox, quads, keep_bits, keep_cap, s));
+                                    offsets, max_pairs, keys, vals, pa.bbox, quads, keep_bits, chunk_item, keep_cap,
+                                    s));
     STAGE_MARK(5);
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,

@@ -107,13 +107,13 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                                                const uint64_t *__restrict__ offsets, uint64_t max_pairs,
                                                uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                const float4 *__restrict__ bbox, bool quads,
-                                               uint4 *__restrict__ keep_bits, uint64_t keep_cap)
+                                               uint64_t *__restrict__ keep_bits, const uint32_t *__restrict__ chunk_item,
+                                               uint64_t keep_cap)
 {
     const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
-    // The counter leaves, per wave of 64 tests, the test results and the
-    // wave's item bracket in keep_bits (when the batch has at most keep_cap
-    // tests); the writer reads them back instead of searching and testing
-    // again.
+    // When the batch has at most keep_cap tests, chunk_item gives the item of
+    // each wave's first test (no search), and the counter leaves each wave's
+    // 64 test results in keep_bits for the writer (no second test).
     const bool bits = keep_bits != nullptr && C <= keep_cap;
     const int lane = (int)__lane_id();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -127,12 +127,10 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         // 64-way searches, then each lane searches the bracket.
         const uint64_t t_last = t0 + 63 < C ? t0 + 63 : C - 1;
         int64_t g_lo, g_hi;
-        uint64_t kept = 0;
-        if (WRITE && bits) {
-            const uint4 w = keep_bits[t0 >> 6];
-            kept = ((uint64_t)w.y << 32) | w.x;
-            g_lo = (int64_t)w.z;
-            g_hi = (int64_t)w.w;
+        if (bits) {
+            // the next chunk's first item bounds this chunk's last one
+            g_lo = (int64_t)chunk_item[t0 >> 6];
+            g_hi = t0 + 64 < C ? (int64_t)chunk_item[(t0 >> 6) + 1] : nitems - 1;
         } else {
             g_lo = wave_search(area_off, 0, nitems - 1, t0, lane);
             g_hi = wave_search(area_off, g_lo, nitems - 1, t_last, lane);
@@ -169,7 +167,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         TileGeom<float> geo;
         bool keep;
         if (WRITE && bits) {
-            keep = valid && ((kept >> lane) & 1ull);
+            keep = valid && ((keep_bits[t0 >> 6] >> lane) & 1ull);
             if (keep) load_line_geom(recs + (size_t)g * kRecQuads, geo);
         } else {
             load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
@@ -184,8 +182,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
         const uint64_t km = kall & seg;
         const uint32_t nk = (uint32_t)__popcll(km);
         if (!WRITE) {
-            if (bits && lane == 0)
-                keep_bits[t0 >> 6] = make_uint4((uint32_t)kall, (uint32_t)(kall >> 32), (uint32_t)g_lo, (uint32_t)g_hi);
+            if (bits && lane == 0) keep_bits[t0 >> 6] = kall;
             if (valid && lane == s0 && nk) atomicAdd(&counts[g], nk);
             n_tests += valid ? 1 : 0;
             n_first += (valid && j == 0) ? 1 : 0;
@@ -300,30 +297,55 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
 }
 
+// chunk_item[c] = the item holding candidate test 64 c, for the chunks below
+// cap_chunks: every item with tests writes the chunks that start inside its
+// range [area_off[g], area_off[g + 1]).
+__global__ __launch_bounds__(256) void k_chunk_items(const uint64_t *__restrict__ area_off, int64_t nitems,
+                                                     uint64_t cap_chunks, uint32_t *__restrict__ chunk_item)
+{
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t g0 = area_off[g], g1 = area_off[g + 1];
+        if (g1 <= g0) continue;
+        const uint64_t c1 = (g1 - 1) >> 6;
+        for (uint64_t c = (g0 + 63) >> 6; c <= c1 && c < cap_chunks; ++c) chunk_item[c] = (uint32_t)g;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t keep_cap, uint32_t *chunk_item,
+                              hipStream_t s)
+{
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_chunk_items, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 4096)), dim3(256), 0, s,
+                       area_off, items, keep_cap / 64, chunk_item);
+    return hipGetLastError();
+}
 
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              unsigned long long *tests, uint4 *keep_bits, uint64_t keep_cap, hipStream_t s)
+                              unsigned long long *tests, uint64_t *keep_bits, const uint32_t *chunk_item, uint64_t keep_cap, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 1024)), dim3(256), 0, s,
                        counts, items);
     hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
                        nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0, (uint64_t *)nullptr,
-                       (uint32_t *)nullptr, (const float4 *)nullptr, false, keep_bits, keep_cap);
+                       (uint32_t *)nullptr, (const float4 *)nullptr, false, keep_bits, chunk_item, keep_cap);
     return hipGetLastError();
 }
 
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
                               const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              const float4 *bbox, bool quads, uint4 *keep_bits, uint64_t keep_cap, hipStream_t s)
+                              const float4 *bbox, bool quads, uint64_t *keep_bits, const uint32_t *chunk_item, uint64_t keep_cap,
+                              hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
                        nviews, tile_cull, counts, (unsigned long long *)nullptr, offsets, max_pairs, keys, vals, bbox,
-                       quads, keep_bits, keep_cap);
+                       quads, keep_bits, chunk_item, keep_cap);
     return hipGetLastError();
 }
 
