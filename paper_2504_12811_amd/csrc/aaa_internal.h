@@ -217,6 +217,8 @@ struct PreArgs {
     float4 *rec;
     float4 *cull;
     float4 *bbox;     // screen bounding box of the rho^2 <= tau region: x_lo, x_hi, y_lo, y_hi (pixels)
+    uint32_t *pending;    // per item: items left to the whole-view cull, listed per workgroup of 256
+    uint32_t *pending_n;  // per workgroup of 256 items: its number of listed items
 };
 hipError_t launch_preprocess(const PreArgs &a, hipStream_t s);
 

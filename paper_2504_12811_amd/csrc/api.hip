@@ -74,7 +74,7 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 1) * 8 + 63) / 64 * 64; }
 
 struct Layout {
-    size_t hdr, views, status, rect, bbox, area, area_off, rec, cull, counts, keep_bits, chunk_item, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+    size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, counts, keep_bits, chunk_item, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
         ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
@@ -95,6 +95,8 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.status = take(items * 4);
     L.rect = take(items * 16);
     L.bbox = take(items * 16);
+    L.pending = take(items * 4);
+    L.pending_n = take((items + 255) / 256 * 4);
     L.area = take(items * 4);
     L.area_off = take((items + 1) * 8);
     L.rec = take(items * 16 * aaa::kRecQuads);
@@ -238,6 +240,8 @@ aaa::PreArgs pre_args(const aaa_scene *scene, int nviews, const aaa_settings *se
     pa.rec = at<float4>(ws, L.rec);
     pa.cull = at<float4>(ws, L.cull);
     pa.bbox = at<float4>(ws, L.bbox);
+    pa.pending = at<uint32_t>(ws, L.pending);
+    pa.pending_n = at<uint32_t>(ws, L.pending_n);
     return pa;
 }
 

@@ -62,63 +62,13 @@ __device__ bool view_bounds(const double *Ma, const double *Mc, double ma, doubl
     return true;
 }
 
-// One thread per item (Gaussian i, view v), item = i * nviews + v: the
-// threads of a Gaussian's views are adjacent, so its parameters are fetched
-// from HBM once per batch.
-__global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
+// Anchored line record and culling geometry of a visible item whose tile
+// rectangle is [x0, x1) x [y0, y1) (the anchor: the pixel centre nearest the
+// projected mean, kept inside the rectangle's pixels; the rectangle's centre
+// when the mean is not in front).
+__device__ void build_geom(const Setup &S, const CamDev &cam, int x0, int x1, int y0, int y1, TileGeom<double> &g)
 {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (item >= a.n * a.nviews) return;
-    const int64_t i = item / a.nviews;
-    const int v = (int)(item - i * a.nviews);
-    const ViewDev &vw = a.views[v];
-    const int64_t n = a.n;
-    a.rect[item] = make_int4(0, 0, 0, 0);
-    a.area[item] = 0u;
-    Setup S;
-    const int st0 = setup_gaussian(a, i, vw, S);
-    if (st0 != kVisible) {
-        a.status[item] = st0;
-        return;
-    }
-    const double *muv = S.muv, *M = S.M, *A = S.A, *og = S.og, *d = S.d;
-    const double alpha_t = S.alpha_t, tau = S.tau, og2 = S.og2;
-    if (og2 < tau) {  // Sec. 3.3: camera inside the ellipsoid
-        a.status[item] = kCamInside;
-        return;
-    }
-    // Sec. 3.3 bounds in the x-z and y-z view planes
-    const CamDev &cam = vw.cam;
-    double tx_lo, tx_hi, ty_lo, ty_hi;
-    bool fullx, fully;
-    bool okx = view_bounds(&M[0], &M[6], muv[0], muv[2], tau, tx_lo, tx_hi, fullx);
-    bool oky = view_bounds(&M[3], &M[6], muv[1], muv[2], tau, ty_lo, ty_hi, fully);
-    if (!okx || !oky) {
-        a.status[item] = kOutside;
-        return;
-    }
-    int x0 = 0, x1 = cam.tiles_x, y0 = 0, y1 = cam.tiles_y;
-    float4 box = make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY);
-    if (!fullx) {
-        double px_lo = cam.cx + cam.fx * tan(tx_lo) - 1e-3, px_hi = cam.cx + cam.fx * tan(tx_hi) + 1e-3;
-        x0 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_lo / kTile)));
-        x1 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_hi / kTile) + 1.0));
-        box.x = (float)px_lo;
-        box.y = (float)px_hi;
-    }
-    if (!fully) {
-        double py_lo = cam.cy + cam.fy * tan(ty_lo) - 1e-3, py_hi = cam.cy + cam.fy * tan(ty_hi) + 1e-3;
-        y0 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_lo / kTile)));
-        y1 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_hi / kTile) + 1.0));
-        box.z = (float)py_lo;
-        box.w = (float)py_hi;
-    }
-    if (x0 >= x1 || y0 >= y1) {
-        a.status[item] = kOutside;
-        return;
-    }
-    // anchor: the pixel centre nearest the projected mean, kept inside the
-    // rectangle's pixels (rectangle centre when the mean is not in front)
+    const double *muv = S.muv, *M = S.M, *A = S.A, *og = S.og;
     int pxl = x0 * kTile, pxh = min(x1 * kTile, cam.width) - 1;
     int pyl = y0 * kTile, pyh = min(y1 * kTile, cam.height) - 1;
     double xa, ya;
@@ -133,7 +83,6 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     }
     // anchored line coefficients (Eq. 4-5 written as o_g x r_g and -o_g . r_g)
     double ua = (xa - cam.cx) / cam.fx, va = (ya - cam.cy) / cam.fy;
-    TileGeom<double> g;
     g.xa = xa;
     g.ya = ya;
     for (int r = 0; r < 3; ++r) {
@@ -151,7 +100,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     g.l[0] = -lam * dot3(og, g.c0);
     g.l[1] = -lam * dot3(og, g.c1);
     g.l[2] = -lam * dot3(og, g.c2);
-    g.og2 = og2;
+    g.og2 = S.og2;
     // culling geometry of the screen planes relative to the anchor
     double G[9];  // Sigma~ in view space = M M^T
     for (int r = 0; r < 3; ++r)
@@ -171,12 +120,76 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
         g.qy1[k] = G[3 * k + 2] / cam.fy;
         g.muv[k] = muv[k];
     }
-    // Sec. 3.4: cull against the whole view frustum
-    double mview = tile_min_rho2<double>(g, 0.0, (double)cam.width, 0.0, (double)cam.height, cam);
-    if (!(mview < tau)) {
-        a.status[item] = kOutside;
-        return;
+}
+
+// Whether the mean lies inside the pyramid of the whole view (then the
+// minimum of Eq. 18 over the view is 0 and the item is not culled there).
+__device__ __forceinline__ bool mean_in_view(const TileGeom<double> &g, const CamDev &cam)
+{
+    const double sL = g.dx0 - (0.0 - g.xa) * g.dx1, sR = g.dx0 - ((double)cam.width - g.xa) * g.dx1;
+    const double sT = g.dy0 - (0.0 - g.ya) * g.dy1, sB = g.dy0 - ((double)cam.height - g.ya) * g.dy1;
+    return !(sL < 0.0 || sR > 0.0 || sT < 0.0 || sB > 0.0);
+}
+
+// One item (Gaussian i, view v), item = i * nviews + v: the threads of a
+// Gaussian's views are adjacent, so its parameters are fetched from HBM once
+// per batch.  Returns true when the item is visible so far but its mean
+// lies outside the view pyramid: the cull of Sec. 3.4 against the whole view
+// is then left to k_view_cull (its double-precision pyramid minimum needs
+// more registers than the rest of this pass).
+__device__ bool preprocess_item(const PreArgs &a, int64_t item)
+{
+    const int64_t i = item / a.nviews;
+    const int v = (int)(item - i * a.nviews);
+    const ViewDev &vw = a.views[v];
+    const int64_t n = a.n;
+    a.rect[item] = make_int4(0, 0, 0, 0);
+    a.area[item] = 0u;
+    Setup S;
+    const int st0 = setup_gaussian(a, i, vw, S);
+    if (st0 != kVisible) {
+        a.status[item] = st0;
+        return false;
     }
+    const double *muv = S.muv, *M = S.M, *d = S.d;
+    const double alpha_t = S.alpha_t, tau = S.tau, og2 = S.og2;
+    if (og2 < tau) {  // Sec. 3.3: camera inside the ellipsoid
+        a.status[item] = kCamInside;
+        return false;
+    }
+    // Sec. 3.3 bounds in the x-z and y-z view planes
+    const CamDev &cam = vw.cam;
+    double tx_lo, tx_hi, ty_lo, ty_hi;
+    bool fullx, fully;
+    bool okx = view_bounds(&M[0], &M[6], muv[0], muv[2], tau, tx_lo, tx_hi, fullx);
+    bool oky = view_bounds(&M[3], &M[6], muv[1], muv[2], tau, ty_lo, ty_hi, fully);
+    if (!okx || !oky) {
+        a.status[item] = kOutside;
+        return false;
+    }
+    int x0 = 0, x1 = cam.tiles_x, y0 = 0, y1 = cam.tiles_y;
+    float4 box = make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY);
+    if (!fullx) {
+        double px_lo = cam.cx + cam.fx * tan(tx_lo) - 1e-3, px_hi = cam.cx + cam.fx * tan(tx_hi) + 1e-3;
+        x0 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_lo / kTile)));
+        x1 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_hi / kTile) + 1.0));
+        box.x = (float)px_lo;
+        box.y = (float)px_hi;
+    }
+    if (!fully) {
+        double py_lo = cam.cy + cam.fy * tan(ty_lo) - 1e-3, py_hi = cam.cy + cam.fy * tan(ty_hi) + 1e-3;
+        y0 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_lo / kTile)));
+        y1 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_hi / kTile) + 1.0));
+        box.z = (float)py_lo;
+        box.w = (float)py_hi;
+    }
+    if (x0 >= x1 || y0 >= y1) {
+        a.status[item] = kOutside;
+        return false;
+    }
+    TileGeom<double> g;
+    build_geom(S, cam, x0, x1, y0, y1, g);
+    const bool pending = !mean_in_view(g, cam);
     // colour from real SH along the camera->mean direction
     double Y[16];
     sh_eval(a.sh_degree, d[0], d[1], d[2], Y);
@@ -193,7 +206,7 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     rec[2] = make_float4(g.c2[2], g.w0[0], g.w0[1], g.w0[2]);
     rec[3] = make_float4(g.w1[0], g.w1[1], g.w1[2], g.w2[0]);
     rec[4] = make_float4(g.w2[1], g.w2[2], g.l[0], g.l[1]);
-    rec[5] = make_float4(g.l[2], xa, ya, alpha_t);
+    rec[5] = make_float4(g.l[2], g.xa, g.ya, alpha_t);
     // prefilter level slightly above tau so that it never rejects an
     // evaluation the exact alpha test would accept
     rec[6] = make_float4((float)(tau * (1.0 + 1e-4) + 1e-6), (float)tau, (float)og2, 0.f);
@@ -211,6 +224,51 @@ __global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
     a.bbox[item] = box;
     a.area[item] = (uint32_t)((x1 - x0) * (y1 - y0));
     a.status[item] = kVisible;
+    return pending;
+}
+
+// Items with their mean outside the view pyramid are listed per workgroup
+// (pending[256 b + k], k < pending_n[b]) for k_view_cull.
+__global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
+{
+    __shared__ uint32_t n_pend;
+    if (threadIdx.x == 0) n_pend = 0;
+    __syncthreads();
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool pend = item < a.n * a.nviews && preprocess_item(a, item);
+    const uint64_t m = __ballot(pend);
+    uint32_t base = 0;
+    if (__lane_id() == 0 && m) base = atomicAdd(&n_pend, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, 0);
+    if (pend) {
+        const uint64_t below = __lane_id() == 0 ? 0ull : (~0ull >> (64 - __lane_id()));
+        a.pending[(size_t)blockIdx.x * 256 + base + (uint32_t)__popcll(m & below)] = (uint32_t)item;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.pending_n[blockIdx.x] = n_pend;
+}
+
+// Sec. 3.4: cull the listed items against the pyramid of the whole view
+// (double-precision minimum of Eq. 18, same geometry as the records).
+__global__ __launch_bounds__(256) void k_view_cull(PreArgs a)
+{
+    if (threadIdx.x >= a.pending_n[blockIdx.x]) return;
+    const int64_t item = a.pending[(size_t)blockIdx.x * 256 + threadIdx.x];
+    const int64_t i = item / a.nviews;
+    const int v = (int)(item - i * a.nviews);
+    const ViewDev &vw = a.views[v];
+    const CamDev &cam = vw.cam;
+    Setup S;
+    setup_gaussian(a, i, vw, S);
+    const int4 r = a.rect[item];
+    TileGeom<double> g;
+    build_geom(S, cam, r.x, r.y, r.z, r.w, g);
+    const double mview = tile_min_rho2<double>(g, 0.0, (double)cam.width, 0.0, (double)cam.height, cam);
+    if (!(mview < S.tau)) {
+        a.status[item] = kOutside;
+        a.rect[item] = make_int4(0, 0, 0, 0);
+        a.area[item] = 0u;
+    }
 }
 
 }  // namespace
@@ -220,6 +278,7 @@ hipError_t launch_preprocess(const PreArgs &a, hipStream_t s)
     if (a.n <= 0 || a.nviews <= 0) return hipSuccess;
     int64_t blocks = (a.n * a.nviews + 255) / 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_view_cull, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
