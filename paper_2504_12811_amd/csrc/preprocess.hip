@@ -228,8 +228,10 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
 }
 
 // Items with their mean outside the view pyramid are listed per workgroup
-// (pending[256 b + k], k < pending_n[b]) for k_view_cull.
-__global__ __launch_bounds__(256) void k_preprocess(PreArgs a)
+// (pending[256 b + k], k < pending_n[b]) for k_view_cull.  Four waves per
+// SIMD (128 VGPRs, a few spilled) hide the double-precision latency better
+// than three.
+__global__ __launch_bounds__(256, 4) void k_preprocess(PreArgs a)
 {
     __shared__ uint32_t n_pend;
     if (threadIdx.x == 0) n_pend = 0;
