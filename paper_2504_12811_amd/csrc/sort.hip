@@ -4,8 +4,11 @@
 // Each pass: (1) per-block digit histograms into a digit-major [digit][block]
 // table, (2) one workgroup per digit scans its row in place (the block's
 // offset within the digit) and records the digit's total, (3) a stable
-// scatter, whose workgroups add the prefix of the digit totals themselves.  A block owns 4096
-// consecutive keys; each of its four wavefronts ranks a contiguous quarter in
+// scatter, whose workgroups add the prefix of the digit totals themselves.
+// A block owns 2048 consecutive keys (24 KB of LDS staging: six workgroups
+// per CU; 4096 or 8192 keys per block measured slower, the longer runs per
+// digit not making up for the lower occupancy); each of its four wavefronts
+// ranks a contiguous quarter in
 // rounds of 64 with a ballot-based match on the digit bits (lanes with equal
 // digits see each other through eight ballots), so the rank of a key is the
 // number of equal digits before it in its wave's segment.  The block then
@@ -21,9 +24,9 @@ namespace {
 constexpr int kBits = 8;
 constexpr int kBins = 1 << kBits;
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kPerBlock = kThreads * kItems;   // 4096
-constexpr int kPerWave = kPerBlock / 4;        // 1024
+constexpr int kItems = 8;
+constexpr int kPerBlock = kThreads * kItems;   // 2048
+constexpr int kPerWave = kPerBlock / 4;        // 512
 
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
