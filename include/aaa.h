@@ -151,7 +151,9 @@ int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_
  * per-Gaussian records, sorted pairs and per-pixel state until it is used
  * again; aaa_render_backward reads them.  The call synchronises `stream`
  * once to learn the pair count; on AAA_ERR_PAIR_OVERFLOW stats->pairs is the
- * count needed and the outputs are not written.  stats (host) may be NULL. */
+ * max_pairs needed (the pair count, or an eighth of the candidate tile tests
+ * when that is larger: a workspace holds the tests of 8 per pair) and the
+ * outputs are not written.  stats (host) may be NULL. */
 int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
                void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream, float *out_rgb, float *out_T,
                aaa_stats *stats);

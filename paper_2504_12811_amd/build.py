@@ -18,6 +18,8 @@ HIPCC_FLAGS = [
     # native float atomic adds (device memory is coarse-grained)
     "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    # every symbol resolved at link time (a missing definition fails the build)
+    "-Wl,-z,defs",
 ]
 
 

@@ -242,26 +242,28 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
 hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams, int ncam, float *out,
                              hipStream_t s);
 
-// Pair emission over the candidate tests numbered by area_off (exclusive
-// scan of the rectangle areas, items + 1 entries).  count: zeroes counts, then
-// adds the survivors per item.  write: takes slots by running counts down to 0.
-// When the batch has at most keep_cap candidate tests (a multiple of 64):
-// chunk_item (keep_cap / 64 words, from launch_chunk_items) gives the item of
-// every 64th test, so neither pass searches the area offsets, and the
-// counter leaves one bit per test in keep_bits (keep_cap / 64 words) for the
-// writer, which then does not test again.  Items must number below 2^32.
+// Pair emission over the batch's candidate tests, numbered by area_off (the
+// exclusive scan of the rectangle areas, items + 1 entries; at most keep_cap of them,
+// a multiple of 64; with more, the three kernels do nothing and the caller
+// must ask for a larger pair buffer).  chunk_item (keep_cap / 64 words) gets
+// the item of every 64th test; the counter stores, per chunk of 64 tests,
+// the keep bits (keep_bits, keep_cap / 64 words) and their number
+// (chunk_cnt, zeroed beforehand); after an exclusive scan of chunk_cnt into
+// kept_before, the writer emits every kept test's pair at index
+// kept_before[chunk] + (kept tests before it in the chunk).  Items must
+// number below 2^32.
 hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t keep_cap, uint32_t *chunk_item,
                               hipStream_t s);
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
-                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              unsigned long long *tests, uint64_t *keep_bits, const uint32_t *chunk_item,
-                              uint64_t keep_cap, hipStream_t s);
+                              int64_t items, const ViewDev *views, int nviews, bool tile_cull,
+                              unsigned long long *tests, uint64_t *keep_bits, uint32_t *chunk_cnt,
+                              const uint32_t *chunk_item, uint64_t keep_cap, hipStream_t s);
 // quads: pack the quadrant bits of each pair (from bbox) into its value
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
-                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              const float4 *bbox, bool quads, uint64_t *keep_bits, const uint32_t *chunk_item,
-                              uint64_t keep_cap, hipStream_t s);
+                              int64_t items, const ViewDev *views, int nviews, const uint64_t *keep_bits,
+                              const uint32_t *chunk_item, const uint64_t *kept_before, uint64_t keep_cap,
+                              uint64_t max_pairs, uint64_t *keys, uint32_t *vals, const float4 *bbox, bool quads,
+                              hipStream_t s);
 // p[i] &= mask for i < n
 hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);

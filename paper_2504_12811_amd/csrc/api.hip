@@ -68,13 +68,13 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
     return sh;
 }
 
-// Candidate tile tests for which the emitter keeps per-chunk items and keep
-// bits (8 per pair of the pair buffer, 12 bytes per 64; larger batches
-// search and test in both passes).
+// Candidate tile tests a workspace can take: 8 per pair of the pair buffer
+// (per 64 tests: item, keep bits, count and offset, 24 bytes).  A batch with
+// more is reported as a pair overflow asking for a larger buffer.
 uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 1) * 8 + 63) / 64 * 64; }
 
 struct Layout {
-    size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, counts, keep_bits, chunk_item, offsets, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+    size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, counts, keep_bits, chunk_item, chunk_cnt, kept_before, chunk_scan_tmp, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
         ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
@@ -102,9 +102,12 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.rec = take(items * 16 * aaa::kRecQuads);
     L.cull = take(items * 16 * aaa::kCullQuads);
     L.counts = take(items * 4);
-    L.keep_bits = take(keep_cap_of(max_pairs) / 64 * 8);
-    L.chunk_item = take(keep_cap_of(max_pairs) / 64 * 4);
-    L.offsets = take((items + 1) * 8);
+    const uint64_t chunks = keep_cap_of(max_pairs) / 64;
+    L.keep_bits = take(chunks * 8);
+    L.chunk_item = take(chunks * 4);
+    L.chunk_cnt = take(chunks * 4);
+    L.kept_before = take((chunks + 1) * 8);
+    L.chunk_scan_tmp = take(aaa::scan_tmp_bytes((int64_t)chunks));
     L.scan_tmp = take(aaa::scan_tmp_bytes(items));
     uint64_t mp = max_pairs > 0 ? max_pairs : 1;
     L.keys = take(mp * 8);
@@ -453,22 +456,25 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
 
     const bool tile_cull = (settings->flags & AAA_NO_TILE_CULL) == 0;
     const int64_t items = n * n_views;
-    uint32_t *counts = at<uint32_t>(ws, L.counts);
-    uint64_t *offsets = at<uint64_t>(ws, L.offsets);
     uint64_t *area_off = at<uint64_t>(ws, L.area_off);
     HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s));
     uint64_t *keep_bits = at<uint64_t>(ws, L.keep_bits);
     uint32_t *chunk_item = at<uint32_t>(ws, L.chunk_item);
-    const uint64_t keep_cap = keep_cap_of(max_pairs);
+    uint32_t *chunk_cnt = at<uint32_t>(ws, L.chunk_cnt);
+    uint64_t *kept_before = at<uint64_t>(ws, L.kept_before);
+    const uint64_t keep_cap = keep_cap_of(max_pairs), chunks = keep_cap / 64;
+    HIP_TRY(hipMemsetAsync(chunk_cnt, 0, chunks * 4, s));
     HIP_TRY(aaa::launch_chunk_items(area_off, items, keep_cap, chunk_item, s));
-    HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
-                                    want_stats ? ctr : nullptr, keep_bits, chunk_item, keep_cap, s));
+    HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull,
+                                    want_stats ? ctr : nullptr, keep_bits, chunk_cnt, chunk_item, keep_cap, s));
     STAGE_MARK(2);
-    HIP_TRY(aaa::launch_exclusive_scan(counts, offsets, items, at<void>(ws, L.scan_tmp), s));
+    HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s));
     STAGE_MARK(3);
-    uint64_t P = 0;
-    HIP_TRY(hipMemcpyAsync(&P, offsets + items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    uint64_t P = 0, C = 0;
+    HIP_TRY(hipMemcpyAsync(&P, kept_before + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&C, area_off + items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (C > keep_cap) P = std::max<uint64_t>(max_pairs + 1, (C + 7) / 8);  // buffer too small to even count
     if (stats) {
         memset(stats, 0, sizeof(*stats));
         stats->pairs = P;
@@ -479,9 +485,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
     STAGE_MARK(4);
     const bool quads = quad_values(n, settings);
-    HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull, counts,
-                                    offsets, max_pairs, keys, vals, pa.bbox, quads, keep_bits, chunk_item, keep_cap,
-                                    s));
+    HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, keep_bits,
+                                    chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads, s));
     STAGE_MARK(5);
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,
@@ -730,7 +735,7 @@ int aaa_read_pairs(const aaa_scene *scene, const aaa_camera *cam, uint64_t max_p
     hipStream_t s = (hipStream_t)stream;
     const char *w = (const char *)ws;
     uint64_t P = 0;
-    HIP_TRY(hipMemcpyAsync(&P, w + L.offsets + 8 * (size_t)scene->n, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&P, w + L.kept_before + 8 * (keep_cap_of(max_pairs) / 64), 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     *n_pairs = P;
     if (P > max_pairs) return fail(AAA_ERR_PAIR_OVERFLOW, "last frame overflowed");

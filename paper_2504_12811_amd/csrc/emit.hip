@@ -1,24 +1,19 @@
 // K2: tile-pair emission.  For every visible Gaussian, every tile of its
-// bounding rectangle is tested in 3D (Sec. 3.4, Eq. 18); the pair counter
-// counts survivors, an exclusive scan turns counts into offsets, and the
-// writer emits (tile << 32 | order key of the tile depth, Gaussian index).
+// bounding rectangle is tested in 3D (Sec. 3.4, Eq. 18); the counter keeps
+// the results, a scan numbers the survivors, and the writer emits
+// (tile << 32 | order key of the tile depth, Gaussian index) at each
+// survivor's number.
 //
 // Work split: the candidate (item, rectangle tile) tests are numbered through
 // an exclusive scan of the rectangle areas, and every lane takes one test
-// (grid-stride), so lanes stay busy whatever the mix of rectangle sizes.  A
-// lane finds its item in the area offsets: the wave brackets its 64
-// candidates with two cooperative 64-way searches, then each lane searches
-// the bracket held across the lanes.  The lanes of
-// one item inside a wave form a contiguous segment; its first lane adds the
-// segment's survivors to the item's count with one atomic.
+// (grid-stride), so lanes stay busy whatever the mix of rectangle sizes.  One
+// pass over the area offsets records the item of every 64th test
+// (k_chunk_items); a wave's 64 tests then lie between two recorded items and
+// each lane searches that bracket, held across the lanes.
 //
-// The writer places an item's pairs in the item's slot range [offset,
-// offset + count) in whatever order its segments arrive (each segment's
-// leader takes a block of slots by an atomic on the item's count, which
-// runs down to 0).  Items occupy increasing ranges, so the stable sort still
-// breaks key ties by item, i.e. by Gaussian index within a view; within one
-// item all keys differ (one pair per tile), so the order inside its range
-// does not change the sorted result.
+// Pairs are written in test order (item, then tile within the rectangle):
+// items occupy increasing ranges, so the stable sort breaks key ties by item,
+// i.e. by Gaussian index within a view.
 #include <algorithm>
 
 #include "aaa_internal.h"
@@ -70,71 +65,42 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
     return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
 }
 
-// Largest g in [lo, hi] with off[g] <= target, for a wave-uniform target and
-// non-decreasing off with off[lo] <= target: each round every lane probes one
-// of 64 evenly spaced points and a ballot keeps the stretch between the last
-// probe at or below the target and the next probe (4 rounds for 10^6 items).
-__device__ __forceinline__ int64_t wave_search(const uint64_t *__restrict__ off, int64_t lo, int64_t hi,
-                                               uint64_t target, int lane)
-{
-    while (hi > lo) {
-        const int64_t step = (hi - lo + 64) / 64;
-        const int64_t p = lo + (int64_t)lane * step;
-        const bool le = p <= hi && off[p] <= target;
-        const uint64_t b = __ballot(le);  // lanes 0..k, lane 0 probes lo
-        const int k = 63 - __builtin_clzll(b);
-        lo = lo + (int64_t)k * step;
-        hi = lo + step - 1 < hi ? lo + step - 1 : hi;
-        if (step == 1) break;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(256) void k_zero_u32(uint32_t *__restrict__ p, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
-}
 
 // Pass 1 (count) and pass 2 (write) share one body.  Items are (Gaussian,
-// view) pairs, item = i * nviews + v.
+// view) pairs, item = i * nviews + v.  The candidate tests come in chunks of
+// 64, one chunk per wave step; chunk_item holds the item of each chunk's
+// first test, so a lane finds its item in a bracket held across the wave.
+// The counter stores each chunk's 64 results (keep_bits) and their number
+// (chunk_cnt); an exclusive scan of the numbers (kept_before) gives every
+// kept test its pair slot: the number of kept tests before it.  Slots thus
+// follow test order (item, then tile within the rectangle), with no atomics.
+// Both passes do nothing when the batch has more than keep_cap tests (the
+// host reports that as a pair overflow, asking for a larger pair buffer).
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, const float4 *__restrict__ recs,
                                                const float4 *__restrict__ culls, const uint64_t *__restrict__ area_off,
                                                int64_t nitems, const ViewDev *__restrict__ views, int nviews,
-                                               bool tile_cull, uint32_t *__restrict__ counts,
-                                               unsigned long long *__restrict__ tests,
-                                               const uint64_t *__restrict__ offsets, uint64_t max_pairs,
-                                               uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                               const float4 *__restrict__ bbox, bool quads,
-                                               uint64_t *__restrict__ keep_bits, const uint32_t *__restrict__ chunk_item,
-                                               uint64_t keep_cap)
+                                               bool tile_cull, unsigned long long *__restrict__ tests,
+                                               uint64_t *__restrict__ keep_bits, uint32_t *__restrict__ chunk_cnt,
+                                               const uint32_t *__restrict__ chunk_item,
+                                               const uint64_t *__restrict__ kept_before, uint64_t keep_cap,
+                                               uint64_t max_pairs, uint64_t *__restrict__ keys,
+                                               uint32_t *__restrict__ vals, const float4 *__restrict__ bbox, bool quads)
 {
     const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
-    // When the batch has at most keep_cap tests, chunk_item gives the item of
-    // each wave's first test (no search), and the counter leaves each wave's
-    // 64 test results in keep_bits for the writer (no second test).
-    const bool bits = keep_bits != nullptr && C <= keep_cap;
+    if (C > keep_cap) return;
     const int lane = (int)__lane_id();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     unsigned long long n_first = 0, n_tests = 0;
     for (uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); t0 < C; t0 += stride) {
+        const uint64_t c = t0 >> 6;
         const uint64_t t = t0 + (uint64_t)lane;
         const bool valid = t < C;
         const uint64_t tq = valid ? t : C - 1;
         // this lane's item: the largest g with area_off[g] <= tq (its area is
-        // then > 0).  The wave first brackets its 64 candidates with two
-        // 64-way searches, then each lane searches the bracket.
-        const uint64_t t_last = t0 + 63 < C ? t0 + 63 : C - 1;
-        int64_t g_lo, g_hi;
-        if (bits) {
-            // the next chunk's first item bounds this chunk's last one
-            g_lo = (int64_t)chunk_item[t0 >> 6];
-            g_hi = t0 + 64 < C ? (int64_t)chunk_item[(t0 >> 6) + 1] : nitems - 1;
-        } else {
-            g_lo = wave_search(area_off, 0, nitems - 1, t0, lane);
-            g_hi = wave_search(area_off, g_lo, nitems - 1, t_last, lane);
-        }
+        // then > 0), between the first items of this chunk and the next
+        const int64_t g_lo = (int64_t)chunk_item[c];
+        const int64_t g_hi = t0 + 64 < C ? (int64_t)chunk_item[c + 1] : nitems - 1;
         int64_t g;
         if (g_hi - g_lo < 64) {
             // bracket held across the lanes: lane k has area_off[g_lo + k]
@@ -148,6 +114,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
             }
             g = g_lo + k;
         } else {
+            // many empty items in between: binary search of the bracket
             int64_t lo = g_lo, hi = g_hi;
             while (lo < hi) {
                 const int64_t mid = lo + (hi - lo + 1) / 2;
@@ -158,41 +125,30 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
             }
             g = lo;
         }
-        const uint64_t g0 = area_off[g], g1 = area_off[g + 1];
+        const uint64_t g0 = area_off[g];
         const int j = (int)(tq - g0);
         const int4 r = rects[g];
         const int w = r.y - r.x;
         const int tx = r.x + j % w, ty = r.z + j / w;
         const ViewDev &vw = views[g % nviews];
         TileGeom<float> geo;
-        bool keep;
-        if (WRITE && bits) {
-            keep = valid && ((keep_bits[t0 >> 6] >> lane) & 1ull);
-            if (keep) load_line_geom(recs + (size_t)g * kRecQuads, geo);
-        } else {
+        if (!WRITE) {
             load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
             const float tau = recs[(size_t)g * kRecQuads + 6].y;
-            keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
-        }
-        // this item's lanes in the wave: [s0, s1)
-        const int s0 = g0 > t0 ? (int)(g0 - t0) : 0;
-        const int s1 = g1 - t0 < 64 ? (int)(g1 - t0) : 64;
-        const uint64_t seg = (s1 >= 64 ? ~0ull : ((1ull << s1) - 1ull)) & ~bits_below(s0);
-        const uint64_t kall = __ballot(keep);
-        const uint64_t km = kall & seg;
-        const uint32_t nk = (uint32_t)__popcll(km);
-        if (!WRITE) {
-            if (bits && lane == 0) keep_bits[t0 >> 6] = kall;
-            if (valid && lane == s0 && nk) atomicAdd(&counts[g], nk);
+            const bool keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
+            const uint64_t kall = __ballot(keep);
+            if (lane == 0) {
+                keep_bits[c] = kall;
+                chunk_cnt[c] = (uint32_t)__popcll(kall);
+            }
             n_tests += valid ? 1 : 0;
             n_first += (valid && j == 0) ? 1 : 0;
         } else {
-            uint32_t base = 0;
-            if (valid && lane == s0 && nk) base = atomicSub(&counts[g], nk) - nk;
-            base = (uint32_t)__shfl((int)base, s0);
-            if (keep) {
-                const uint64_t slot = offsets[g] + base + (uint64_t)__popcll(km & bits_below(lane));
+            const uint64_t kall = keep_bits[c];
+            if (valid && ((kall >> lane) & 1ull)) {
+                const uint64_t slot = kept_before[c] + (uint64_t)__popcll(kall & bits_below(lane));
                 if (slot < max_pairs) {
+                    load_line_geom(recs + (size_t)g * kRecQuads, geo);
                     const uint32_t tile = (uint32_t)(vw.tile_base + ty * vw.cam.tiles_x + tx);
                     keys[slot] = ((uint64_t)tile << 32) | order_key(tile_depth(geo, tx, ty));
                     uint32_t val = (uint32_t)(g / nviews);
@@ -324,28 +280,27 @@ hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t 
 }
 
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
-                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              unsigned long long *tests, uint64_t *keep_bits, const uint32_t *chunk_item, uint64_t keep_cap, hipStream_t s)
+                              int64_t items, const ViewDev *views, int nviews, bool tile_cull,
+                              unsigned long long *tests, uint64_t *keep_bits, uint32_t *chunk_cnt,
+                              const uint32_t *chunk_item, uint64_t keep_cap, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 1024)), dim3(256), 0, s,
-                       counts, items);
     hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
-                       nviews, tile_cull, counts, tests, (const uint64_t *)nullptr, (uint64_t)0, (uint64_t *)nullptr,
-                       (uint32_t *)nullptr, (const float4 *)nullptr, false, keep_bits, chunk_item, keep_cap);
+                       nviews, tile_cull, tests, keep_bits, chunk_cnt, chunk_item, (const uint64_t *)nullptr, keep_cap,
+                       (uint64_t)0, (uint64_t *)nullptr, (uint32_t *)nullptr, (const float4 *)nullptr, false);
     return hipGetLastError();
 }
 
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
-                              int64_t items, const ViewDev *views, int nviews, bool tile_cull, uint32_t *counts,
-                              const uint64_t *offsets, uint64_t max_pairs, uint64_t *keys, uint32_t *vals,
-                              const float4 *bbox, bool quads, uint64_t *keep_bits, const uint32_t *chunk_item, uint64_t keep_cap,
+                              int64_t items, const ViewDev *views, int nviews, const uint64_t *keep_bits,
+                              const uint32_t *chunk_item, const uint64_t *kept_before, uint64_t keep_cap,
+                              uint64_t max_pairs, uint64_t *keys, uint32_t *vals, const float4 *bbox, bool quads,
                               hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
-                       nviews, tile_cull, counts, (unsigned long long *)nullptr, offsets, max_pairs, keys, vals, bbox,
-                       quads, keep_bits, chunk_item, keep_cap);
+                       nviews, true, (unsigned long long *)nullptr, const_cast<uint64_t *>(keep_bits),
+                       (uint32_t *)nullptr, chunk_item, kept_before, keep_cap, max_pairs, keys, vals, bbox, quads);
     return hipGetLastError();
 }
 

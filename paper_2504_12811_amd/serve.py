@@ -53,13 +53,13 @@ class Result:
 
 def estimate_bytes(n_gaussians: int, cams, pairs_per_pixel: float = 2.0) -> int:
     """Device memory of one request: the per-(Gaussian, view) records and
-    scratch (~420 B), the pair buffers (~49 B per pair incl. sort and emitter scratch,
+    scratch (~420 B), the pair buffers (~51 B per pair incl. sort and emitter scratch,
     plus ~33 B per pair of long-list masks), per-pixel state and the output
     images."""
     pix = sum(int(c.width) * int(c.height) for c in cams)
-    per_item = 4 + 16 + 16 + 4 + 128 + 128 + 4 + 8 + 96 + 16
+    per_item = 4 + 16 + 16 + 4 + 128 + 128 + 4 + 8 + 4 + 96
     pairs = pairs_per_pixel * pix + 4096
-    return int(n_gaussians * len(cams) * per_item + pairs * 82 + pix * (4 + 16 + 4) + (1 << 20))
+    return int(n_gaussians * len(cams) * per_item + pairs * 84 + pix * (4 + 16 + 4) + (1 << 20))
 
 
 class Server:
