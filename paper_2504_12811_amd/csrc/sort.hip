@@ -56,7 +56,10 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
 }
 
 // Row d of the [digit][block] table: exclusive prefix over the blocks, in
-// place, and the row total in totals[d].
+// place, and the row total in totals[d].  Each thread takes 8 consecutive
+// entries per round (2048 per round: long rows take few rounds).
+constexpr int kScanPer = 8;
+
 __global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ hist, uint32_t nblocks,
                                                          uint32_t *__restrict__ totals)
 {
@@ -64,10 +67,15 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ 
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     uint32_t *row = hist + (uint64_t)blockIdx.x * nblocks;
     uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < nblocks; c0 += kThreads) {
-        const uint32_t i = c0 + (uint32_t)t;
-        const uint32_t v = i < nblocks ? row[i] : 0u;
-        uint32_t x = v;
+    for (uint32_t c0 = 0; c0 < nblocks; c0 += kThreads * kScanPer) {
+        const uint32_t i0 = c0 + (uint32_t)t * kScanPer;
+        uint32_t v[kScanPer], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            v[k] = i0 + k < nblocks ? row[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t x = sum;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off);
             if (lane >= off) x += y;
@@ -77,7 +85,12 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ 
         uint32_t wpre = 0;
         for (int w = 0; w < wave; ++w) wpre += wsum[w];
         const uint32_t chunk = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        if (i < nblocks) row[i] = carry + wpre + x - v;
+        uint32_t run = carry + wpre + x - sum;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < nblocks) row[i0 + k] = run;
+            run += v[k];
+        }
         carry += chunk;
         __syncthreads();
     }
