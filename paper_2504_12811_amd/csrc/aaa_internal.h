@@ -264,6 +264,9 @@ hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 
                               const uint32_t *chunk_item, const uint64_t *kept_before, uint64_t keep_cap,
                               uint64_t max_pairs, uint64_t *keys, uint32_t *vals, const float4 *bbox, bool quads,
                               hipStream_t s);
+// host[0] = *a, host[1] = *b (host: pinned host memory), visible to the host
+// once the stream has synchronised: one launch instead of two small copies
+hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, hipStream_t s);
 // p[i] &= mask for i < n
 hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);

@@ -270,6 +270,8 @@ struct aaa_ctx {
     aaa::ViewDev *views_host;
     // training-camera table of K7: pinned staging and its device copy
     aaa::TrainCam *train_host, *train_dev;
+    // pinned words the device publishes before the host's one wait per call
+    uint64_t *sync_host;
     // second stream for the long-list blend, forked from and joined back to
     // the caller's stream with these events
     hipStream_t side;
@@ -321,12 +323,14 @@ int aaa_create(aaa_ctx **out, int device)
     c->views_host = nullptr;
     c->train_host = nullptr;
     c->train_dev = nullptr;
+    c->sync_host = nullptr;
     c->side = nullptr;
     c->fork = c->join = nullptr;
     hipError_t e = hipHostMalloc((void **)&c->views_host, sizeof(aaa::ViewDev) * kMaxViews, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->train_host, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&c->train_dev, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->sync_host, 64, hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
@@ -334,6 +338,7 @@ int aaa_create(aaa_ctx **out, int device)
         if (c->views_host) (void)hipHostFree(c->views_host);
         if (c->train_host) (void)hipHostFree(c->train_host);
         if (c->train_dev) (void)hipFree(c->train_dev);
+        if (c->sync_host) (void)hipHostFree(c->sync_host);
         if (c->fork) (void)hipEventDestroy(c->fork);
         if (c->side) (void)hipStreamDestroy(c->side);
         delete c;
@@ -347,6 +352,7 @@ int aaa_create(aaa_ctx **out, int device)
                 (void)hipHostFree(c->views_host);
                 (void)hipHostFree(c->train_host);
                 (void)hipFree(c->train_dev);
+                (void)hipHostFree(c->sync_host);
                 (void)hipEventDestroy(c->fork);
                 (void)hipEventDestroy(c->join);
                 (void)hipStreamDestroy(c->side);
@@ -371,6 +377,7 @@ void aaa_destroy(aaa_ctx *ctx)
     (void)hipHostFree(ctx->views_host);
     (void)hipHostFree(ctx->train_host);
     (void)hipFree(ctx->train_dev);
+    (void)hipHostFree(ctx->sync_host);
     (void)hipEventDestroy(ctx->fork);
     (void)hipEventDestroy(ctx->join);
     (void)hipStreamDestroy(ctx->side);
@@ -470,10 +477,10 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     STAGE_MARK(2);
     HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s));
     STAGE_MARK(3);
-    uint64_t P = 0, C = 0;
-    HIP_TRY(hipMemcpyAsync(&P, kept_before + chunks, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&C, area_off + items, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(aaa::launch_publish2(kept_before + chunks, area_off + items, ctx->sync_host, s));
     HIP_TRY(hipStreamSynchronize(s));
+    uint64_t P = ctx->sync_host[0];
+    const uint64_t C = ctx->sync_host[1];
     if (C > keep_cap) P = std::max<uint64_t>(max_pairs + 1, (C + 7) / 8);  // buffer too small to even count
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -579,7 +586,7 @@ int aaa_render(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, cons
 // slots (a lane each) per contributor rank of its busiest pixel, placed by an
 // exclusive scan of those row counts.  *rank16: every pixel has at most 65536
 // contributors (ranks 0..65535).
-static int backward_slots(const Shape &sh, const Layout &L, void *ws, hipStream_t s, uint64_t *total,
+static int backward_slots(aaa_ctx *ctx, const Shape &sh, const Layout &L, void *ws, hipStream_t s, uint64_t *total,
                           bool *rank16 = nullptr)
 {
     const int64_t quads = 4 * sh.total_tiles;
@@ -589,11 +596,10 @@ static int backward_slots(const Shape &sh, const Layout &L, void *ws, hipStream_
                                   at<uint32_t>(ws, L.n_ins), at<uint32_t>(ws, L.wave_caps), max_big, s));
     HIP_TRY(aaa::launch_exclusive_scan(at<uint32_t>(ws, L.wave_caps), at<uint64_t>(ws, L.wave_off), quads,
                                        at<void>(ws, L.wave_scan_tmp), s));
-    uint64_t rows = 0;
-    uint32_t big = 0;
-    HIP_TRY(hipMemcpyAsync(&rows, at<uint64_t>(ws, L.wave_off) + quads, 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&big, max_big, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(aaa::launch_publish2(at<uint64_t>(ws, L.wave_off) + quads, (const uint64_t *)max_big, ctx->sync_host, s));
     HIP_TRY(hipStreamSynchronize(s));
+    const uint64_t rows = ctx->sync_host[0];
+    const uint32_t big = (uint32_t)ctx->sync_host[1];  // the low word of the 8 bytes at max_big
     *total = rows * 64;
     if (rank16) *rank16 = big == 0;
     return AAA_OK;
@@ -612,7 +618,7 @@ int aaa_backward_scratch_size(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     if (ws_bytes < L.total) return fail(AAA_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
     HIP_TRY(hipSetDevice(ctx->device));
     uint64_t total = 0;
-    rc = backward_slots(sh, L, ws, (hipStream_t)stream, &total);
+    rc = backward_slots(ctx, sh, L, ws, (hipStream_t)stream, &total);
     if (rc) return rc;
     *bytes_out = (size_t)total * sizeof(float2) + 256;
     return AAA_OK;
@@ -638,7 +644,7 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     if (n == 0) return AAA_OK;
     uint64_t total = 0;
     bool rank16 = false;
-    rc = backward_slots(sh, L, ws, s, &total, &rank16);
+    rc = backward_slots(ctx, sh, L, ws, s, &total, &rank16);
     if (rc) return rc;
     if (total > 0 && (!scratch || scratch_bytes < total * sizeof(float2)))
         return fail(AAA_ERR_WORKSPACE, "backward scratch %zu < %zu bytes (aaa_backward_scratch_size)", scratch_bytes,

@@ -304,6 +304,21 @@ hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 
     return hipGetLastError();
 }
 
+__global__ void k_publish2(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b, uint64_t *host)
+{
+    if (threadIdx.x == 0) {
+        host[0] = *a;
+        host[1] = *b;
+        __threadfence_system();
+    }
+}
+
+hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_publish2, dim3(1), dim3(64), 0, s, a, b, host);
+    return hipGetLastError();
+}
+
 __global__ void k_and_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t mask)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
