@@ -248,8 +248,9 @@ hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams
 // must ask for a larger pair buffer).  chunk_item (keep_cap / 64 words) gets
 // the item of every 64th test; the counter stores, per chunk of 64 tests,
 // the keep bits (keep_bits, keep_cap / 64 words) and their number
-// (chunk_cnt, zeroed beforehand); after an exclusive scan of chunk_cnt into
-// kept_before, the writer emits every kept test's pair at index
+// (chunk_cnt); after an exclusive scan of the batch's chunks of chunk_cnt
+// into kept_before (launch_exclusive_scan with count_of = &area_off[items]),
+// the writer emits every kept test's pair at index
 // kept_before[chunk] + (kept tests before it in the chunk).  Items must
 // number below 2^32.
 hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t keep_cap, uint32_t *chunk_item,
@@ -270,7 +271,12 @@ hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host,
 // p[i] &= mask for i < n
 hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
-hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s);
+// Exclusive scan of n counts into n + 1 offsets (the last: the total).  With
+// count_of (device), only the first min(n, ceil(*count_of / 64)) counts are
+// scanned (entries past them are never read) and the total is also stored
+// at out[n].
+hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s,
+                                 const uint64_t *count_of = nullptr);
 
 size_t sort_tmp_bytes(uint64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,

@@ -470,12 +470,13 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint32_t *chunk_cnt = at<uint32_t>(ws, L.chunk_cnt);
     uint64_t *kept_before = at<uint64_t>(ws, L.kept_before);
     const uint64_t keep_cap = keep_cap_of(max_pairs), chunks = keep_cap / 64;
-    HIP_TRY(hipMemsetAsync(chunk_cnt, 0, chunks * 4, s));
     HIP_TRY(aaa::launch_chunk_items(area_off, items, keep_cap, chunk_item, s));
     HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull,
                                     want_stats ? ctr : nullptr, keep_bits, chunk_cnt, chunk_item, keep_cap, s));
     STAGE_MARK(2);
-    HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s));
+    // the chunks of this batch's C tests only (the host does not know C yet)
+    HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s,
+                                       area_off + items));
     STAGE_MARK(3);
     HIP_TRY(aaa::launch_publish2(kept_before + chunks, area_off + items, ctx->sync_host, s));
     HIP_TRY(hipStreamSynchronize(s));

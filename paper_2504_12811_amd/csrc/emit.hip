@@ -196,10 +196,24 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *s
     return wpre + x - v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n, uint64_t *__restrict__ sums)
+// The element count n is the host's, or, when count_of is given, taken on
+// the device as min(n, ceil(*count_of / 64)): a scan over the 64-test chunks
+// of a batch whose test count only the device knows.  The total goes to
+// out[n] and, for the device-side count, also to out[n_host].
+__device__ __forceinline__ int64_t scan_len(int64_t n, const uint64_t *count_of)
+{
+    if (!count_of) return n;
+    const int64_t m = (int64_t)((*count_of + 63) >> 6);
+    return m < n ? m : n;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict__ in, int64_t n_host,
+                                                     const uint64_t *__restrict__ count_of, uint64_t *__restrict__ sums)
 {
     __shared__ uint64_t sm[4];
+    const int64_t n = scan_len(n_host, count_of);
     const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    if (b0 >= n) return;  // uniform per block
     uint64_t acc = 0;
     for (int k = 0; k < 4; ++k) {
         int64_t idx = b0 + threadIdx.x * 4 + k;
@@ -210,10 +224,12 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t *__restrict_
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_sums(uint64_t *__restrict__ sums, int64_t nb)
+__global__ __launch_bounds__(256) void k_scan_sums(uint64_t *__restrict__ sums, int64_t n_host,
+                                                   const uint64_t *__restrict__ count_of)
 {
     __shared__ uint64_t sm[4];
     __shared__ uint64_t carry;
+    const int64_t nb = (scan_len(n_host, count_of) + kScanBlock - 1) / kScanBlock;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t c0 = 0; c0 < nb; c0 += 256) {
@@ -230,12 +246,19 @@ __global__ __launch_bounds__(256) void k_scan_sums(uint64_t *__restrict__ sums, 
     if (threadIdx.x == 0) sums[nb] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int64_t n,
-                                                    const uint64_t *__restrict__ sums, int64_t nb,
-                                                    uint64_t *__restrict__ out)
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int64_t n_host,
+                                                    const uint64_t *__restrict__ count_of,
+                                                    const uint64_t *__restrict__ sums, uint64_t *__restrict__ out)
 {
     __shared__ uint64_t sm[4];
+    const int64_t n = scan_len(n_host, count_of);
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[n] = sums[nb];
+        out[n_host] = sums[nb];
+    }
     const int64_t b0 = (int64_t)blockIdx.x * kScanBlock;
+    if (b0 >= n) return;  // uniform per block
     uint32_t v[4];
     uint64_t acc = 0;
     for (int k = 0; k < 4; ++k) {
@@ -250,7 +273,6 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
         if (idx < n) out[idx] = ex;
         ex += v[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums[nb];
 }
 
 // chunk_item[c] = the item holding candidate test 64 c, for the chunks below
@@ -339,16 +361,18 @@ size_t scan_tmp_bytes(int64_t n)
     return (size_t)(nb + 1) * sizeof(uint64_t);
 }
 
-hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t s)
+hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t s,
+                                 const uint64_t *count_of)
 {
     int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     uint64_t *sums = (uint64_t *)tmp;
     if (n <= 0) {
         return hipMemsetAsync(out, 0, sizeof(uint64_t), s);
     }
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, n, sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, n, (const uint64_t *)sums, nb, out);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, n, count_of, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, n, count_of);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, n, count_of, (const uint64_t *)sums,
+                       out);
     return hipGetLastError();
 }
 
