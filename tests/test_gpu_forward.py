@@ -314,3 +314,34 @@ def test_far_view_long_lists_sampled(ras):
         sel[:] = 0
         sel[keep] = 1
     compare_image(ras, scene, cam, st, tile_sel=sel, label="far view long lists")
+
+
+def test_candidate_overflow_grows_pair_buffer(ras):
+    """Needles along the image diagonal: each one's tile rectangle is large
+    but only a diagonal band of its tiles survives the 3D test, so the
+    candidate tests outnumber eight times the pairs.  A workspace sized for
+    exactly the pairs cannot hold the tests: the render reports a pair
+    overflow whose requested capacity covers them, the binding retries with
+    it, and the image equals the render with a roomy buffer."""
+    rng = np.random.default_rng(31)
+    n = 300
+    means = np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n)])
+    log_scales = np.stack([np.full(n, np.log(0.6)), np.full(n, np.log(0.004)), np.full(n, np.log(0.004))])
+    th = np.pi / 4 + rng.uniform(-0.15, 0.15, n)  # rotation about the view axis
+    quats = np.stack([np.cos(th / 2), np.zeros(n), np.zeros(n), np.sin(th / 2)])
+    logits = np.full(n, 0.0)
+    sh = ((rng.uniform(0.0, 1.0, size=(3, n)) - 0.5) / S.SH_C0)[None]
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    scene = S.Scene(f32(means), f32(log_scales), f32(quats), f32(logits), f32(sh), None)
+    cam = S.pinhole((0.0, 0.0, 3.0), 512, 512, 60.0)
+    st = S.Settings()
+    ds = dev(scene)
+    ref, _, s0 = ras.render(ds, cam, st, stats=True, fresh_ws=True)
+    ref = ref.clone()
+    P, Cn = int(s0.pairs), int(s0.candidate_tiles)
+    print(f"pairs {P}, candidate tile tests {Cn}", flush=True)
+    assert Cn > 8 * P
+    rgb, _, s1 = ras.render(ds, cam, st, max_pairs=P, fresh_ws=True)
+    assert ras.last_ws.max_pairs > P  # the first attempt overflowed and the retry grew the buffer
+    assert int(s1.pairs) == P
+    assert torch.equal(rgb, ref)
