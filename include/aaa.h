@@ -141,7 +141,8 @@ const char *aaa_last_error(void);
 const char *aaa_version(void);
 
 /* Bytes of workspace needed to render `scene` through `cam` with room for
- * max_pairs (Gaussian, tile) pairs.  Host-only computation. */
+ * max_pairs (Gaussian, tile) pairs and 8 * max_pairs candidate tile tests
+ * (the tiles of the Gaussians' screen rectangles).  Host-only computation. */
 int aaa_workspace_size(const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
                        uint64_t max_pairs, size_t *bytes_out);
 

@@ -74,7 +74,7 @@ Shape shape_of(const aaa_scene *scene, int nviews, const aaa_camera *cams)
 uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 1) * 8 + 63) / 64 * 64; }
 
 struct Layout {
-    size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, counts, keep_bits, chunk_item, chunk_cnt, kept_before, chunk_scan_tmp, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
+    size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, bwd_list, keep_bits, chunk_item, chunk_cnt, kept_before, chunk_scan_tmp, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
         ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
@@ -101,7 +101,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.area_off = take((items + 1) * 8);
     L.rec = take(items * 16 * aaa::kRecQuads);
     L.cull = take(items * 16 * aaa::kCullQuads);
-    L.counts = take(items * 4);
+    L.bwd_list = take(items * 4);  // K6b: the Gaussians with a visible item
     const uint64_t chunks = keep_cap_of(max_pairs) / 64;
     L.keep_bits = take(chunks * 8);
     L.chunk_item = take(chunks * 4);
@@ -687,12 +687,11 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     go.quats = grad->quats;
     go.logits = grad->opacity_logits;
     go.sh = grad->sh;
-    // K6b over the Gaussians with a visible item; the list reuses the
-    // per-item count buffer (not needed after the forward's scan), the
-    // count sits beside the frame counters
+    // K6b over the Gaussians with a visible item (listed in bwd_list; the
+    // count sits beside the frame counters)
     uint32_t *bwd_count = (uint32_t *)(at<unsigned long long>(ws, L.hdr) + 9);
     HIP_TRY(hipMemsetAsync(bwd_count, 0, 4, s));
-    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, at<uint32_t>(ws, L.counts), bwd_count, s));
+    HIP_TRY(aaa::launch_preprocess_bwd(pa, grad_rec, go, at<uint32_t>(ws, L.bwd_list), bwd_count, s));
     // the pinned view table is reused by the next call on this context
     HIP_TRY(hipStreamSynchronize(s));
     return AAA_OK;
