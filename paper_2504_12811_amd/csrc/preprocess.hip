@@ -251,25 +251,44 @@ __global__ __launch_bounds__(256, 4) void k_preprocess(PreArgs a)
 }
 
 // Sec. 3.4: cull the listed items against the pyramid of the whole view
-// (double-precision minimum of Eq. 18, same geometry as the records).
-__global__ __launch_bounds__(256) void k_view_cull(PreArgs a)
+// (double-precision minimum of Eq. 18, same geometry as the records).  One
+// workgroup gathers the lists of kViewCullGroup preprocess workgroups, so
+// that its waves run full (each list holds only the few items of its 256
+// whose mean lies outside the view).
+constexpr int kViewCullGroup = 8;
+
+__global__ __launch_bounds__(256) void k_view_cull(PreArgs a, int64_t nlists)
 {
-    if (threadIdx.x >= a.pending_n[blockIdx.x]) return;
-    const int64_t item = a.pending[(size_t)blockIdx.x * 256 + threadIdx.x];
-    const int64_t i = item / a.nviews;
-    const int v = (int)(item - i * a.nviews);
-    const ViewDev &vw = a.views[v];
-    const CamDev &cam = vw.cam;
-    Setup S;
-    setup_gaussian(a, i, vw, S);
-    const int4 r = a.rect[item];
-    TileGeom<double> g;
-    build_geom(S, cam, r.x, r.y, r.z, r.w, g);
-    const double mview = tile_min_rho2<double>(g, 0.0, (double)cam.width, 0.0, (double)cam.height, cam);
-    if (!(mview < S.tau)) {
-        a.status[item] = kOutside;
-        a.rect[item] = make_int4(0, 0, 0, 0);
-        a.area[item] = 0u;
+    __shared__ uint32_t pre[kViewCullGroup + 1];
+    const int64_t l0 = (int64_t)blockIdx.x * kViewCullGroup;
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < kViewCullGroup; ++k) {
+            pre[k] = acc;
+            acc += l0 + k < nlists ? a.pending_n[l0 + k] : 0u;
+        }
+        pre[kViewCullGroup] = acc;
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < pre[kViewCullGroup]; j += blockDim.x) {
+        int k = 0;
+        while (j >= pre[k + 1]) ++k;  // the list holding the j-th gathered item
+        const int64_t item = a.pending[(size_t)(l0 + k) * 256 + (j - pre[k])];
+        const int64_t i = item / a.nviews;
+        const int v = (int)(item - i * a.nviews);
+        const ViewDev &vw = a.views[v];
+        const CamDev &cam = vw.cam;
+        Setup S;
+        setup_gaussian(a, i, vw, S);
+        const int4 r = a.rect[item];
+        TileGeom<double> g;
+        build_geom(S, cam, r.x, r.y, r.z, r.w, g);
+        const double mview = tile_min_rho2<double>(g, 0.0, (double)cam.width, 0.0, (double)cam.height, cam);
+        if (!(mview < S.tau)) {
+            a.status[item] = kOutside;
+            a.rect[item] = make_int4(0, 0, 0, 0);
+            a.area[item] = 0u;
+        }
     }
 }
 
@@ -280,7 +299,8 @@ hipError_t launch_preprocess(const PreArgs &a, hipStream_t s)
     if (a.n <= 0 || a.nviews <= 0) return hipSuccess;
     int64_t blocks = (a.n * a.nviews + 255) / 256;
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_view_cull, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_view_cull, dim3((unsigned)((blocks + kViewCullGroup - 1) / kViewCullGroup)), dim3(256), 0, s,
+                       a, blocks);
     return hipGetLastError();
 }
 
