@@ -155,15 +155,20 @@ __device__ __forceinline__ void blend_entry(PixelState &ps, const float4 *__rest
 
 // RankT: the LDS type of pass 1's contributor ranks (uint16_t when every
 // rank of the frame fits, which leaves room for a fourth workgroup per CU).
-template <int K, bool STATS, bool PASS1, typename RankT = uint32_t>
-__global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                               BlendArgs a)
+// WPB: waves per workgroup, 4 (a tile) or 1 (a quadrant: a wave that
+// finishes early frees its registers and LDS at once, which the forward
+// gains from; the replay does better with whole tiles).
+template <int K, bool STATS, bool PASS1, typename RankT = uint32_t, int WPB = 4>
+__global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                    BlendArgs a)
 {
     const int ntiles = a.total_tiles;
     // XCD-aware order: consecutive workgroups land on different XCDs, so hand
-    // each XCD a contiguous band of tiles (neighbouring tiles share records).
+    // each XCD a contiguous band of tiles (neighbouring tiles share records);
+    // with one wave per workgroup the four quadrants of a tile share an XCD.
     const int per = (ntiles + 7) / 8;
-    const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    const int wq = (int)(blockIdx.x >> 3);
+    const int tile = (int)(blockIdx.x & 7) * per + (WPB == 4 ? wq : wq >> 2);
     if (tile >= ntiles) return;
     int v = 0;  // the view owning this tile (views are ordered by tile_base)
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
@@ -171,7 +176,8 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     const int nv = a.nviews;
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = WPB == 4 ? (int)(threadIdx.x >> 6) : (wq & 3), lane = threadIdx.x & 63;
+    const int wl = WPB == 4 ? wave : 0;  // this wave's LDS rows
     const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
     const bool inside = px < vw.cam.width && py < vw.cam.height;
@@ -189,15 +195,15 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     // A popped entry's slot takes the entry inserted in its place, so only
     // two registers per position take part in the sorting network.
     constexpr int KS = K > 0 ? K : 1;
-    __shared__ uint2 pay[K > 0 ? 4 : 1][KS][64];
-    __shared__ RankT pay_rank[PASS1 && K > 0 ? 4 : 1][PASS1 ? KS : 1][64];
+    __shared__ uint2 pay[K > 0 ? WPB : 1][KS][64];
+    __shared__ RankT pay_rank[PASS1 && K > 0 ? WPB : 1][PASS1 ? KS : 1][64];
     float wz[KS];
     uint32_t ws[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         wz[k] = -INFINITY;  // fillers: popped first, with alpha 0
         ws[k] = (uint32_t)k;
-        if constexpr (K > 0) pay[wave][k][lane] = make_uint2(0u, 0u);
+        if constexpr (K > 0) pay[wl][k][lane] = make_uint2(0u, 0u);
     }
     PixelState ps;
     ps.T = 1.0f;
@@ -259,8 +265,8 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
             // pop min(new, front); insert new behind equal depths, into the
             // slot the front leaves
             const uint32_t fs = ws[0];
-            const uint2 fp = pay[wave][fs][lane];
-            const uint32_t frk = PASS1 ? pay_rank[wave][fs][lane] : 0u;
+            const uint2 fp = pay[wl][fs][lane];
+            const uint32_t frk = PASS1 ? pay_rank[wl][fs][lane] : 0u;
             const bool front_out = wz[0] <= zk;
             // forward: gather the front's colour before the sorting network,
             // so that its latency overlaps the network
@@ -282,8 +288,8 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
             const float3 pop_c = front_out ? float3_of(fc) : c_new;
             const uint32_t pop_rk = front_out ? frk : my_rank;
             if (front_out) {
-                pay[wave][fs][lane] = make_uint2(id, __float_as_uint(ak));
-                if (PASS1) pay_rank[wave][fs][lane] = (RankT)my_rank;
+                pay[wl][fs][lane] = make_uint2(id, __float_as_uint(ak));
+                if (PASS1) pay_rank[wl][fs][lane] = (RankT)my_rank;
             }
             blend_entry<PASS1>(ps, rec, pop_id, pop_c, pop_rk, pop_a, tmin, bp, cap);
         }
@@ -295,8 +301,8 @@ __global__ __launch_bounds__(256) void k_blend(const float4 *__restrict__ rec, c
     if constexpr (K > 0) {
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            const uint2 q = pay[wave][ws[k]][lane];
-            const uint32_t rk = PASS1 ? pay_rank[wave][ws[k]][lane] : 0u;
+            const uint2 q = pay[wl][ws[k]][lane];
+            const uint32_t rk = PASS1 ? pay_rank[wl][ws[k]][lane] : 0u;
             const float3 c = PASS1 ? make_float3(0.0f, 0.0f, 0.0f) : float3_of(rec[(size_t)q.x * kRecQuads + 7]);
             blend_entry<PASS1>(ps, rec, q.x, c, rk, __uint_as_float(q.y), tmin, bp, cap);
         }
@@ -779,15 +785,15 @@ hipError_t launch_k(const BlendArgs &a, bool stats, bool pass1, hipStream_t s)
 {
     const int ntiles = a.total_tiles;
     const int per = (ntiles + 7) / 8;
-    dim3 grid((unsigned)(per * 8));
+    dim3 tiles((unsigned)(per * 8)), quads((unsigned)(per * 8 * 4));
     if (pass1 && a.rank16)
-        hipLaunchKernelGGL((k_blend<K, false, true, uint16_t>), grid, dim3(256), 0, s, a.rec, a.vals, a);
+        hipLaunchKernelGGL((k_blend<K, false, true, uint16_t>), tiles, dim3(256), 0, s, a.rec, a.vals, a);
     else if (pass1)
-        hipLaunchKernelGGL((k_blend<K, false, true>), grid, dim3(256), 0, s, a.rec, a.vals, a);
+        hipLaunchKernelGGL((k_blend<K, false, true>), tiles, dim3(256), 0, s, a.rec, a.vals, a);
     else if (stats)
-        hipLaunchKernelGGL((k_blend<K, true, false>), grid, dim3(256), 0, s, a.rec, a.vals, a);
+        hipLaunchKernelGGL((k_blend<K, true, false, uint32_t, 1>), quads, dim3(64), 0, s, a.rec, a.vals, a);
     else
-        hipLaunchKernelGGL((k_blend<K, false, false>), grid, dim3(256), 0, s, a.rec, a.vals, a);
+        hipLaunchKernelGGL((k_blend<K, false, false, uint32_t, 1>), quads, dim3(64), 0, s, a.rec, a.vals, a);
     return hipGetLastError();
 }
 
