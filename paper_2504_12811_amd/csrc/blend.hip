@@ -272,13 +272,20 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
             // so that its latency overlaps the network
             float4 fc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (!PASS1 && front_out) fc = rec[(size_t)fp.x * kRecQuads + 7];
+            // For a sorted window the new k-th depth is the median of the old
+            // k-th, zk and the old (k+1)-th: one v_med3_f32 instead of two
+            // selects.  With zk a quiet NaN, med3 returns the minimum of the
+            // other two (the old k-th) and every comparison is false, so a
+            // non-inserting lane moves neither depths nor slots.  (Kept
+            // written out here: as a shared helper the compiler stopped
+            // updating the window registers in place.)
             {
                 bool gcur = front_out;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const int kn = k + 1 < K ? k + 1 : k;
                     const bool gnext = (k + 1 < K) ? (wz[kn] <= zk) : false;
-                    wz[k] = gnext ? wz[kn] : (gcur ? zk : wz[k]);
+                    wz[k] = (k + 1 < K) ? __builtin_amdgcn_fmed3f(wz[k], zk, wz[kn]) : (gcur ? zk : wz[k]);
                     ws[k] = gnext ? ws[kn] : (gcur ? fs : ws[k]);
                     gcur = gnext;
                 }
@@ -581,12 +588,12 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
             const uint32_t fs = ws[0];
             const float4 fp = pay[wave][fs][lane];
             const bool front_out = wz[0] <= zk;
-            bool gcur = front_out;
+            bool gcur = front_out;  // same update as k_blend's (median-of-three depths)
 #pragma unroll
             for (int kk = 0; kk < K; ++kk) {
                 const int kn = kk + 1 < K ? kk + 1 : kk;
                 const bool gnext = (kk + 1 < K) ? (wz[kn] <= zk) : false;
-                wz[kk] = gnext ? wz[kn] : (gcur ? zk : wz[kk]);
+                wz[kk] = (kk + 1 < K) ? __builtin_amdgcn_fmed3f(wz[kk], zk, wz[kn]) : (gcur ? zk : wz[kk]);
                 ws[kk] = gnext ? ws[kn] : (gcur ? fs : ws[kk]);
                 gcur = gnext;
             }
