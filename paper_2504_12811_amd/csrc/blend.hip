@@ -268,9 +268,11 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
             const uint2 fp = pay[wl][fs][lane];
             const uint32_t frk = PASS1 ? pay_rank[wl][fs][lane] : 0u;
             const bool front_out = wz[0] <= zk;
-            // forward: gather the front's colour before the sorting network,
-            // so that its latency overlaps the network
-            float4 fc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            // forward: gather the popped entry's colour before the sorting
+            // network, so that its latency overlaps the network (the register
+            // starts as the new entry's colour, which pops when the front
+            // stays; the compiler then issues one load for both cases)
+            float4 fc = make_float4(c_new.x, c_new.y, c_new.z, 0.0f);
             if (!PASS1 && front_out) fc = rec[(size_t)fp.x * kRecQuads + 7];
             // For a sorted window the new k-th depth is the median of the old
             // k-th, zk and the old (k+1)-th: one v_med3_f32 instead of two
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
             }
             const float pop_a = front_out ? __uint_as_float(fp.y) : ak;
             const uint32_t pop_id = front_out ? fp.x : id;
-            const float3 pop_c = front_out ? float3_of(fc) : c_new;
+            const float3 pop_c = float3_of(fc);
             const uint32_t pop_rk = front_out ? frk : my_rank;
             if (front_out) {
                 pay[wl][fs][lane] = make_uint2(id, __float_as_uint(ak));
