@@ -143,7 +143,9 @@ def test_pair_sets_near_camera(ras):
 def test_sort_bit_exact(ras):
     from paper_2504_12811_amd.render import sort_pairs
     rng = np.random.default_rng(5)
-    for n, bits in [(1, 40), (7, 40), (4096, 45), (4097, 45), (300_001, 45), (1 << 20, 64)]:
+    # key widths with one, two, four, five, six and eight 8-bit passes
+    for n, bits in [(1, 40), (7, 40), (4096, 45), (4097, 45), (300_001, 45), (1 << 20, 64), (65_537, 47),
+                    (9_999, 32), (2_049, 17), (513, 8)]:
         tiles = rng.integers(0, 8160, n, dtype=np.uint64)
         depth = rng.integers(0, 1 << 32, n, dtype=np.uint64)
         depth[: n // 3] = depth[0]  # many ties
