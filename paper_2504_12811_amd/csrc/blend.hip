@@ -695,12 +695,17 @@ __device__ __forceinline__ float reduce22(const float (&x)[22], int lane, int &i
     return mine;
 }
 
-__global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                              BlendArgs a)
+// WPB: waves per workgroup (the launch uses 1: one 8x8 quadrant per
+// workgroup, so a quadrant whose pixels consumed few entries frees its slot
+// on the CU without waiting for the rest of its tile).
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                   BlendArgs a)
 {
     const int ntiles = a.total_tiles;
     const int per = (ntiles + 7) / 8;
-    const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    const int wq = (int)(blockIdx.x >> 3);
+    const int tile = (int)(blockIdx.x & 7) * per + (WPB == 4 ? wq : wq >> 2);
     if (tile >= ntiles) return;
     int v = 0;
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
@@ -708,7 +713,7 @@ __global__ __launch_bounds__(256) void k_grad(const float4 *__restrict__ rec, co
     const uint32_t nv = (uint32_t)a.nviews;
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = WPB == 4 ? (int)(threadIdx.x >> 6) : (wq & 3), lane = threadIdx.x & 63;
     const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
     const bool inside = px < vw.cam.width && py < vw.cam.height;
@@ -905,7 +910,7 @@ hipError_t launch_grad(const BlendArgs &a, hipStream_t s)
 {
     if (a.total_tiles <= 0) return hipSuccess;
     const int per = (a.total_tiles + 7) / 8;
-    hipLaunchKernelGGL(k_grad, dim3((unsigned)(per * 8)), dim3(256), 0, s, a.rec, a.vals, a);
+    hipLaunchKernelGGL(k_grad<1>, dim3((unsigned)(per * 8 * 4)), dim3(64), 0, s, a.rec, a.vals, a);
     return hipGetLastError();
 }
 
