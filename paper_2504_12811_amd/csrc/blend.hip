@@ -409,7 +409,7 @@ struct LongTile {
     uint32_t start, end;
 };
 
-__device__ __forceinline__ LongTile long_tile_setup(const BlendArgs &a, int tile)
+__device__ __forceinline__ LongTile long_tile_setup(const BlendArgs &a, int tile, int wave)
 {
     LongTile L;
     L.tile = tile;
@@ -419,7 +419,7 @@ __device__ __forceinline__ LongTile long_tile_setup(const BlendArgs &a, int tile
     L.vw = &a.views[v];
     const int lt = tile - L.vw->tile_base;
     const int tx = lt % L.vw->cam.tiles_x, ty = lt / L.vw->cam.tiles_x;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63;
     L.px = tx * kTile + (wave & 1) * 8 + (lane & 7);
     L.py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
     L.inside = L.px < L.vw->cam.width && L.py < L.vw->cam.height;
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_long_masks(const float4 *__restrict__ r
                                                     uint64_t *__restrict__ summary)
 {
     if (blockIdx.y >= *n_long || *n_long > kMaxLongTiles) return;
-    const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.y]);
+    const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.y], (int)(threadIdx.x >> 6));
     const uint32_t nv = (uint32_t)a.nviews;
     const int t = threadIdx.x;
     const float fxp = (float)L.px + 0.5f, fyp = (float)L.py + 0.5f;
@@ -462,18 +462,22 @@ __global__ __launch_bounds__(256) void k_long_masks(const float4 *__restrict__ r
     }
 }
 
+// One 64-thread workgroup per 8x8 quadrant of a long tile (workgroup 4j + q
+// takes quadrant q of long tile j), like the forward k_blend.
 template <int K, bool STATS>
-__global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
-                                                    BlendArgs a, const uint32_t *__restrict__ long_tiles,
-                                                    const uint32_t *__restrict__ n_long,
-                                                    const uint64_t *__restrict__ pixmask,
-                                                    const uint64_t *__restrict__ summary)
+__global__ __launch_bounds__(64) void k_blend_long(const float4 *__restrict__ rec, const uint32_t *__restrict__ vals,
+                                                   BlendArgs a, const uint32_t *__restrict__ long_tiles,
+                                                   const uint32_t *__restrict__ n_long,
+                                                   const uint64_t *__restrict__ pixmask,
+                                                   const uint64_t *__restrict__ summary)
 {
-    if (blockIdx.x >= *n_long || *n_long > kMaxLongTiles) return;
-    const LongTile L = long_tile_setup(a, (int)long_tiles[blockIdx.x]);
+    const uint32_t j = blockIdx.x >> 2;
+    if (j >= *n_long || *n_long > kMaxLongTiles) return;
+    const int wave = (int)(blockIdx.x & 3);
+    const LongTile L = long_tile_setup(a, (int)long_tiles[j], wave);
     const ViewDev &vw = *L.vw;
     const uint32_t nv = (uint32_t)a.nviews;
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int lane = (int)(threadIdx.x & 63), t = wave * 64 + lane;  // t: the pixel's column of the masks
     const float fxp = (float)L.px + 0.5f, fyp = (float)L.py + 0.5f;
     const uint32_t start = L.start, end = L.end;
     const size_t hw = (size_t)vw.cam.width * vw.cam.height;
@@ -481,14 +485,14 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
     const size_t gpix = vw.pix_base + pix;
 
     constexpr int KS = K > 0 ? K : 1;
-    __shared__ float4 pay[K > 0 ? 4 : 1][KS][64];  // (alpha, r, g, b) per slot
+    __shared__ float4 pay[1][KS][64];  // (alpha, r, g, b) per slot
     float wz[KS];
     uint32_t ws[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         wz[k] = -INFINITY;
         ws[k] = (uint32_t)k;
-        if constexpr (K > 0) pay[wave][k][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if constexpr (K > 0) pay[0][k][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     bool done = !L.inside;
@@ -588,7 +592,7 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
             const float zk = contrib ? z : __builtin_nanf("");
             const float ak = contrib ? al : 0.0f;
             const uint32_t fs = ws[0];
-            const float4 fp = pay[wave][fs][lane];
+            const float4 fp = pay[0][fs][lane];
             const bool front_out = wz[0] <= zk;
             bool gcur = front_out;  // same update as k_blend's (median-of-three depths)
 #pragma unroll
@@ -599,7 +603,7 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
                 ws[kk] = gnext ? ws[kn] : (gcur ? fs : ws[kk]);
                 gcur = gnext;
             }
-            if (front_out) pay[wave][fs][lane] = make_float4(ak, col.x, col.y, col.z);
+            if (front_out) pay[0][fs][lane] = make_float4(ak, col.x, col.y, col.z);
             if (front_out)
                 blend(fp.x, fp.y, fp.z, fp.w);
             else
@@ -611,7 +615,7 @@ __global__ __launch_bounds__(256) void k_blend_long(const float4 *__restrict__ r
     if constexpr (K > 0) {
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            const float4 q = pay[wave][ws[k]][lane];
+            const float4 q = pay[0][ws[k]][lane];
             blend(done ? 0.0f : q.x, q.y, q.z, q.w);
         }
     }
@@ -833,11 +837,11 @@ hipError_t launch_long_k(const BlendArgs &a, bool stats, const uint32_t *long_ti
                          unsigned grid, const uint64_t *pixmask, const uint64_t *summary, hipStream_t s)
 {
     if (stats)
-        hipLaunchKernelGGL((k_blend_long<K, true>), dim3(grid), dim3(256), 0, s, a.rec, a.vals, a, long_tiles, n_long,
+        hipLaunchKernelGGL((k_blend_long<K, true>), dim3(grid * 4), dim3(64), 0, s, a.rec, a.vals, a, long_tiles, n_long,
                            pixmask, summary);
     else
-        hipLaunchKernelGGL((k_blend_long<K, false>), dim3(grid), dim3(256), 0, s, a.rec, a.vals, a, long_tiles, n_long,
-                           pixmask, summary);
+        hipLaunchKernelGGL((k_blend_long<K, false>), dim3(grid * 4), dim3(64), 0, s, a.rec, a.vals, a, long_tiles,
+                           n_long, pixmask, summary);
     return hipGetLastError();
 }
 
