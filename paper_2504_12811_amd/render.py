@@ -145,13 +145,13 @@ class Rasterizer:
         raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
 
     def render_batch(self, scene: DeviceScene, cams, settings, stats: bool = False, max_pairs: Optional[int] = None,
-                     fresh_ws: bool = False):
+                     fresh_ws: bool = False, flags: int = 0):
         """Render several views of one scene in one launch sequence; returns
         ([rgb_v], [T_v], Stats).  Each view equals its single-view render."""
         sc = scene.abi()
         V = len(cams)
         carr = (L.Camera * V)(*[L.make_camera(c) for c in cams])
-        st = L.make_settings(settings, L.AAA_STATS if stats else 0)
+        st = L.make_settings(settings, (L.AAA_STATS if stats else 0) | flags)
         rgbs = [torch.empty((3, int(c.height), int(c.width)), dtype=torch.float32, device=self.device) for c in cams]
         Ts = [torch.empty((int(c.height), int(c.width)), dtype=torch.float32, device=self.device) for c in cams]
         prgb = (C.c_void_p * V)(*[t.data_ptr() for t in rgbs])

@@ -295,6 +295,24 @@ def test_long_list_path_equals_regular_path(ras):
         assert b[2].evaluations <= a[2].evaluations, K
 
 
+def test_long_list_path_batched_views(ras):
+    """Three views of different sizes in one batch, every tile forced
+    through the long-list route (one workgroup per quadrant of each listed
+    tile, tiles of all views in one list): bit-identical to the regular
+    route."""
+    from paper_2504_12811_amd import _lib as L
+    scene, poses = S.cluster_scene(30_000, seed=1003, n_rig=8)
+    cams = [S.pinhole(poses[0], 250, 170, 60.0), S.pinhole(poses[3], 131, 77, 90.0),
+            S.pinhole(poses[5], 200, 200, 45.0)]
+    st = S.Settings(ray_window=16)
+    a_rgb, a_T, a_st = ras.render_batch(dev(scene), cams, st, stats=True)
+    b_rgb, b_T, b_st = ras.render_batch(dev(scene), cams, st, stats=True, flags=L.AAA_LONG_ALL)
+    for k in range(len(cams)):
+        assert torch.equal(a_rgb[k], b_rgb[k]) and torch.equal(a_T[k], b_T[k]), k
+    assert a_st.contributors == b_st.contributors
+    assert b_st.evaluations <= a_st.evaluations
+
+
 def test_far_view_long_lists_sampled(ras):
     """A far view puts the whole cluster scene into a few tiles with lists of
     several thousand entries (the long-list path); oracle on those tiles."""
