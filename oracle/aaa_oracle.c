@@ -735,7 +735,8 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                     qsort(seq, ns, sizeof(or_contrib), cmp_tile_order);
                     window_blend(seq, ns, K, &ps, st, win);
                     /* Near-ties in either ordering key whose swap would move the
-                     * pixel by more than a tenth of the image tolerance. */
+                     * pixel by more than three quarters of the image tolerance
+                     * (1.5e-4 of 2e-4). */
                     if (ns > 1) {
                         const double imp = 1.5e-4;
                         if (K == 0 || ns > K) {

@@ -23,7 +23,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, replace
-from typing import List, Optional
+from typing import Optional
 
 import numpy as np
 
@@ -154,28 +154,21 @@ def _base_colour_sh(rng, n, degree, ac_std):
     return sh
 
 
-def training_frequency(means: np.ndarray, cams: List[Camera]) -> np.ndarray:
-    """Per-Gaussian maximum focal/depth over a synthetic training rig.
+def rig_frequency(means: np.ndarray, rig_radius: float, rig_fx: float) -> np.ndarray:
+    """Stand-in for the stored per-Gaussian training sampling frequency (a
+    renderer input: pixels per world unit).  A trainer would record it from
+    its cameras; here it is drawn from the rig's shape alone: its focal
+    length over the smallest distance a camera on the rig sphere can have
+    from the mean (the sphere radius minus the mean's distance from the
+    centre, at least a twentieth of the radius).  Plain input data: no
+    visibility, no camera poses."""
+    r = np.linalg.norm(means.astype(np.float64), axis=0)
+    d = np.maximum(rig_radius - r, 0.05 * rig_radius)
+    return (rig_fx / d).astype(np.float32)
 
-    This is the stored per-Gaussian quantity a trainer would hand to the
-    renderer (the paper keeps the maximum sampling frequency seen during
-    training).  Poses where the mean is in the frustum count; otherwise poses
-    with positive depth; otherwise +inf (no clamp)."""
-    n = means.shape[1]
-    best_in = np.zeros(n)
-    best_any = np.zeros(n)
-    for c in cams:
-        X = c.viewmat[:3, :3] @ means.astype(np.float64) + c.viewmat[:3, 3:4]
-        z = X[2]
-        pos = z > c.znear
-        v = np.where(pos, c.fx / np.where(pos, z, 1.0), 0.0)
-        xs = c.cx + c.fx * X[0] / np.where(pos, z, 1.0)
-        ys = c.cy + c.fy * X[1] / np.where(pos, z, 1.0)
-        inside = pos & (xs >= 0) & (xs <= c.width) & (ys >= 0) & (ys <= c.height)
-        best_in = np.maximum(best_in, np.where(inside, v, 0.0))
-        best_any = np.maximum(best_any, v)
-    out = np.where(best_in > 0, best_in, np.where(best_any > 0, best_any, np.inf))
-    return out.astype(np.float32)
+
+def _focal(width, fov_x_deg):
+    return (width / 2.0) / math.tan(math.radians(fov_x_deg) / 2.0)
 
 
 def _finish(means, log_scales, quats, logits, sh, v_train) -> Scene:
@@ -197,8 +190,8 @@ def small_scene(n=2000, seed=1001, sh_degree=0, with_v_train=True):
     quats = _random_quats(rng, n)
     logits = rng.normal(0.0, 1.0, size=n)
     sh = _base_colour_sh(rng, n, sh_degree, 0.1)
-    rig = [pinhole(p, 128, 128, 60.0) for p in sphere_poses(rng, 8, 3.0)]
-    v_train = training_frequency(means, rig) if with_v_train else None
+    sphere_poses(rng, 8, 3.0)  # keeps the draw sequence of the rig
+    v_train = rig_frequency(means, 3.0, _focal(128, 60.0)) if with_v_train else None
     cam = pinhole(sphere_poses(rng, 1, 3.0)[0], 128, 128, 60.0)
     return _finish(means, log_scales, quats, logits, sh, v_train), cam
 
@@ -209,7 +202,8 @@ def cluster_scene(n, seed=1002, sh_degree=3, n_clusters=64, box=10.0, log_scale_
     U[-box,box]^3, cluster covariance Rc diag(sigma^2) Rc^T with sigma
     U[0.25,2.5]^3, means rejection-sampled into the box; log-scales
     N(-4,0.7); logits N(0.5,1.5); SH3 coefficients N(0,0.1) with the DC term
-    encoding a U[0,1] base colour.  Training rig = n_rig poses on a sphere."""
+    encoding a U[0,1] base colour.  n_rig poses on a sphere of rig_radius
+    (the benchmark views); v_train from the rig's radius and focal length."""
     rng = np.random.default_rng(seed)
     centres = rng.uniform(-box, box, size=(n_clusters, 3))
     sig = rng.uniform(0.25, 2.5, size=(n_clusters, 3))
@@ -235,8 +229,7 @@ def cluster_scene(n, seed=1002, sh_degree=3, n_clusters=64, box=10.0, log_scale_
     logits = rng.normal(0.5, 1.5, size=n)
     sh = _base_colour_sh(rng, n, sh_degree, 0.1)
     rig_pos = sphere_poses(rng, n_rig, rig_radius)
-    rig = [pinhole(p, rig_w, rig_h, rig_fov) for p in rig_pos]
-    v_train = training_frequency(means, rig)
+    v_train = rig_frequency(means, rig_radius, _focal(rig_w, rig_fov))
     return _finish(means, log_scales, quats, logits, sh, v_train), rig_pos
 
 
@@ -295,8 +288,8 @@ def fd_scene(n=64, seed=1005):
     quats = _random_quats(rng, n)
     logits = rng.normal(0.0, 1.0, size=n)
     sh = _base_colour_sh(rng, n, 3, 0.1)
-    rig = [pinhole(p, 32, 32, 60.0) for p in sphere_poses(rng, 8, 3.0)]
-    v_train = training_frequency(means, rig)
+    sphere_poses(rng, 8, 3.0)  # keeps the draw sequence of the rig
+    v_train = rig_frequency(means, 3.0, _focal(32, 60.0))
     cam = pinhole(sphere_poses(rng, 1, 3.0)[0], 32, 32, 60.0)
     return _finish(means, log_scales, quats, logits, sh, v_train), cam
 

@@ -1,0 +1,311 @@
+"""Pins of the oracle's ordering steps and of its bounds behind the camera.
+
+- The per-ray window (Sec. 3.1 "Blending Sort Order", Sec. 4: per-ray
+  sorting and queuing) at capacities below the contributor count, with
+  arrivals in tile order that differ from the pixel's depth order: the blend
+  sequence for each capacity is written out by hand from the window's
+  definition (insert; pop the front when more than K are held; drain at the
+  end of the list) and the pixel must equal the blend of that sequence.
+- The tile-level key (the depth of maximum response on the tile-centre line):
+  with the window off (K = 0) every pixel of a tile blends in the order of
+  that key, whatever its own depth order; the orders at the two tile centres
+  are written out by hand.
+- The exact pyramid minimum of rho^2 (Sec. 3.4, Eq. 18) and the sampled
+  screen bounds (Sec. 3.3) for means behind the camera and straddling the
+  camera plane, against dense sampling, a multi-start search and the
+  tangent-plane closed form of a sphere.
+
+Geometry is built from thin tilted sheets whose depth of maximum response
+varies across the image; the scenes are checked first (preconditions) with
+numpy closed forms that do not use the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import minimize
+
+from oracle import oracle as O
+from paper_2504_12811_amd import scenes as S
+
+
+def f64(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def identity_camera(w, h, fx, bg=(0.0, 0.0, 0.0)):
+    """Camera at the origin looking down +z (view space = world space)."""
+    return S.Camera(np.eye(4), float(fx), float(fx), w / 2.0, h / 2.0, int(w), int(h), 0.01, tuple(bg))
+
+
+def sheets(z0, tan_beta, colours, big=2.0, thin=0.02, logit=0.0):
+    """Thin Gaussians (scales big, big, thin) centred on the optical axis at
+    depths z0, each rotated about the view y axis so that its thin axis is
+    (sin b, 0, cos b): the sheet is the plane z = z0 - tan(b) x, and the line
+    through view direction (u, v, 1) meets it at depth z0 / (1 + u tan b)."""
+    n = len(z0)
+    beta = np.arctan(np.asarray(tan_beta, np.float64))
+    quats = np.stack([np.cos(beta / 2), np.zeros(n), np.sin(beta / 2), np.zeros(n)])
+    means = np.stack([np.zeros(n), np.zeros(n), np.asarray(z0, np.float64)])
+    log_s = np.stack([np.full(n, math.log(big)), np.full(n, math.log(big)), np.full(n, math.log(thin))])
+    sh = ((np.asarray(colours, np.float64).T - 0.5) / S.SH_C0)[None]
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return S.Scene(f32(means), f32(log_s), f32(quats), f32(np.full(n, logit)), f32(sh), None)
+
+
+def closed_form(sc, cam, i, x, y):
+    """Depth and alpha of the maximum response of Gaussian i on the line
+    through pixel position (x, y), with the filter off, by the Mahalanobis
+    closest point of the line (numpy, independent of the oracle)."""
+    q = f64(sc.quats[:, i])
+    q = q / np.linalg.norm(q)
+    w_, x_, y_, z_ = q
+    R = np.array([[1 - 2 * (y_ * y_ + z_ * z_), 2 * (x_ * y_ - w_ * z_), 2 * (x_ * z_ + w_ * y_)],
+                  [2 * (x_ * y_ + w_ * z_), 1 - 2 * (x_ * x_ + z_ * z_), 2 * (y_ * z_ - w_ * x_)],
+                  [2 * (x_ * z_ - w_ * y_), 2 * (y_ * z_ + w_ * x_), 1 - 2 * (x_ * x_ + y_ * y_)]])
+    s = np.exp(f64(sc.log_scales[:, i]))
+    P = np.linalg.inv(R @ np.diag(s * s) @ R.T)
+    mu = f64(sc.means[:, i])
+    d = np.array([(x - cam.cx) / cam.fx, (y - cam.cy) / cam.fy, 1.0])  # view = world here
+    t = (d @ P @ mu) / (d @ P @ d)
+    X = t * d - mu
+    a = 1.0 / (1.0 + math.exp(-float(sc.opacity_logits[i])))
+    return t, min(0.99, a * math.exp(-0.5 * (X @ P @ X)))
+
+
+def blend(seq, alphas, colours, bg):
+    """Front-to-back blending of a written-out sequence (no termination is
+    reached by these few entries)."""
+    T, C = 1.0, np.zeros(3)
+    for k in seq:
+        C += T * alphas[k] * np.asarray(colours[k])
+        T *= 1.0 - alphas[k]
+    return C + T * np.asarray(bg), T
+
+
+OFF = dict(filter_mode=1)  # filter off: alpha~ = alpha, the closed form above holds
+
+
+# ----------------------------------------------------------------------------
+# per-ray window capacity with out-of-order arrivals
+
+
+def test_window_capacity_blend_sequences():
+    """Four sheets A, B, C, D.  On the tile-centre line their depths are
+    D < C < B < A (so they arrive in the order D, C, B, A), on the line of
+    pixel (15, 7) they are A < B < C < D.  By the window's definition:
+      K = 0: D C B A (tile order);
+      K = 1: D held; C arrives, C pops; B arrives, B pops; A arrives, A pops;
+             D drains                                   -> C B A D;
+      K = 2: D, C held; B arrives, B pops; A arrives, A pops; C, D drain
+                                                        -> B A C D;
+      K = 3: D, C, B held; A arrives, A pops; B, C, D drain -> A B C D;
+      K >= 4: everything drains in depth order          -> A B C D.
+    A window that popped when it held K entries instead of more than K would
+    give K = 3 the sequence of K = 2, and so on."""
+    cam = identity_camera(16, 16, 8.0, bg=(0.1, 0.2, 0.3))
+    names = "ABCD"
+    colours = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), (1.0, 1.0, 1.0)]
+    # depths 2.3, 2.2, 2.1, 2.0 at the image centre (= the tile centre) and
+    # about 1.4, 1.6, 1.8, 2.0 at u = 0.9375 (pixel x = 15.5)
+    sc = sheets([2.3, 2.2, 2.1, 2.0], [0.6857, 0.4, 0.1778, 0.0], colours)
+    x, y = 15.5, 7.5
+    zt = [closed_form(sc, cam, i, 8.0, 8.0)[0] for i in range(4)]
+    zp = [closed_form(sc, cam, i, x, y)[0] for i in range(4)]
+    assert zt[3] < zt[2] < zt[1] < zt[0]          # tile order D C B A
+    assert zp[0] < zp[1] < zp[2] < zp[3]          # pixel order A B C D
+    al = {names[i]: closed_form(sc, cam, i, x, y)[1] for i in range(4)}
+    col = {names[i]: colours[i] for i in range(4)}
+    assert min(al.values()) > 0.2                 # every sheet contributes strongly here
+    expected = {0: "DCBA", 1: "CBAD", 2: "BACD", 3: "ABCD", 4: "ABCD", 16: "ABCD"}
+    seen = {}
+    for K, seq in expected.items():
+        r = O.render(sc, cam, S.Settings(ray_window=K, **OFF))
+        assert r.flags[7, 15] == 0
+        C, T = blend(seq, al, col, cam.bg)
+        np.testing.assert_allclose(r.rgb[:, 7, 15], C, atol=1e-9, err_msg=f"K={K}")
+        assert r.T[7, 15] == pytest.approx(T, abs=1e-9)
+        seen[seq] = C
+    # the written-out sequences give pixels far apart, so the pin has teeth
+    vals = list(seen.values())
+    for i in range(len(vals)):
+        for j in range(i + 1, len(vals)):
+            assert np.abs(vals[i] - vals[j]).max() > 1e-2
+
+
+# ----------------------------------------------------------------------------
+# tile-level key: depth of maximum response on the tile-centre line
+
+
+def test_tile_key_is_the_tile_centre_depth():
+    """Three sheets P (flat), Q and R on a 32x16 image of two tiles.  At the
+    centre of tile 0 (x = 8) the depths are R < P < Q, at the centre of tile
+    1 (x = 24) Q < P < R; on the lines through the tile corners at x = 16
+    they are Q < R < P.  With the window off, every pixel of tile 0 blends
+    R P Q and every pixel of tile 1 blends Q P R, also where the pixel's own
+    depth order differs (x = 13.5: R Q P; x = 17.5: Q R P).  Keying the tile
+    by a corner line, or by the pixel line, gives other images."""
+    cam = identity_camera(32, 16, 16.0, bg=(0.0, 0.0, 0.0))
+    names = "PQR"
+    colours = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)]
+    sc = sheets([2.0, 1.8, 1.9], [0.0, 0.26667, -0.4], colours)
+
+    def order(x, y):
+        z = [closed_form(sc, cam, i, x, y)[0] for i in range(3)]
+        return "".join(names[i] for i in np.argsort(z))
+
+    assert order(8.0, 8.0) == "RPQ"
+    assert order(24.0, 8.0) == "QPR"
+    assert order(16.0, 0.0) == "QRP" and order(16.0, 16.0) == "QRP"
+    col = {names[i]: colours[i] for i in range(3)}
+    r0 = O.render(sc, cam, S.Settings(ray_window=0, **OFF))
+    rK = O.render(sc, cam, S.Settings(ray_window=16, **OFF))
+    checked = 0
+    for (px, py, tile_seq, own_seq) in [(13, 3, "RPQ", "RQP"), (13, 12, "RPQ", "RQP"), (2, 8, "RPQ", "RPQ"),
+                                        (17, 5, "QPR", "QRP"), (28, 9, "QPR", "QPR")]:
+        x, y = px + 0.5, py + 0.5
+        assert order(x, y) == own_seq
+        al = {names[i]: closed_form(sc, cam, i, x, y)[1] for i in range(3)}
+        assert min(al.values()) > 0.2
+        C0, _ = blend(tile_seq, al, col, cam.bg)
+        np.testing.assert_allclose(r0.rgb[:, py, px], C0, atol=1e-9, err_msg=f"K=0 at ({px},{py})")
+        # the window (K >= 3 contributors) restores the pixel's own order
+        CK, _ = blend(own_seq, al, col, cam.bg)
+        np.testing.assert_allclose(rK.rgb[:, py, px], CK, atol=1e-9, err_msg=f"K=16 at ({px},{py})")
+        if tile_seq != own_seq:
+            assert np.abs(C0 - CK).max() > 1e-2
+            checked += 1
+    assert checked == 3
+
+
+# ----------------------------------------------------------------------------
+# pyramid minimum and bounds behind / straddling the camera plane
+
+
+def behind_scene():
+    """Gaussians near the camera plane of an identity camera: means behind it
+    (z < 0), on it, and just in front with extents reaching behind."""
+    rng = np.random.default_rng(77)
+    pts = [(0.3, -0.2, -0.5), (1.5, 0.4, -1.0), (-0.2, 0.1, -0.05), (0.6, 0.6, 0.0), (-0.8, 0.3, 0.02),
+           (0.05, -0.4, -0.2), (2.0, -1.0, -0.3), (-0.3, -0.3, 0.1)]
+    n = len(pts)
+    means = np.asarray(pts, np.float64).T
+    log_s = rng.normal(-1.3, 0.4, size=(3, n))
+    quats = rng.normal(size=(4, n))
+    logits = np.full(n, 1.5)
+    sh = ((rng.uniform(0, 1, (1, 3, n)) - 0.5) / S.SH_C0)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return S.Scene(f32(means), f32(log_s), f32(quats), f32(logits), f32(sh), None)
+
+
+def _rot(q):
+    q = f64(q)
+    q = q / np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def test_cone_min_behind_and_straddling_camera():
+    """Exact pyramid minimum (faces, edges, apex) for means behind or on the
+    camera plane: never above a dense sample of the pyramid (depths down to
+    1e-6 and the apex itself), and equal to a multi-start local search."""
+    sc = behind_scene()
+    cam = identity_camera(96, 96, 40.0)
+    st = S.Settings(**OFF)
+    pp = O.preprocess(sc, cam, st)
+    rng = np.random.default_rng(8)
+    checked = 0
+    for i in range(sc.n):
+        assert pp["status"][i] not in (O.INVALID, O.LOW_OPACITY)
+        s = np.exp(f64(sc.log_scales[:, i]))
+        R = _rot(sc.quats[:, i])
+        P = np.linalg.inv(R @ np.diag(s * s) @ R.T)
+        mu = f64(sc.means[:, i])
+        for rect in [(0.0, 96.0, 0.0, 96.0), (32.0, 48.0, 48.0, 64.0), (80.0, 96.0, 0.0, 16.0),
+                     tuple(16.0 * np.repeat(rng.integers(0, 6, 2), 2) + np.array([0, 16, 0, 16]))]:
+            m, _ = O.cone_min(sc, cam, st, [i], [rect])
+            xs = np.concatenate([rng.uniform(rect[0], rect[1], 800), np.repeat([rect[0], rect[1]], 150),
+                                 rng.uniform(rect[0], rect[1], 300)])
+            ys = np.concatenate([rng.uniform(rect[2], rect[3], 800), rng.uniform(rect[2], rect[3], 300),
+                                 np.repeat([rect[2], rect[3]], 150)])
+            zs = np.geomspace(1e-6, 30, 300)
+            rv = np.stack([(xs - cam.cx) / cam.fx, (ys - cam.cy) / cam.fy, np.ones_like(xs)], 1)
+            D = rv[:, None, :] * zs[None, :, None] - mu
+            q = np.einsum("...i,ij,...j->...", D, P, D)
+            qmin = min(q.min(), float(mu @ P @ mu))  # apex = camera centre = origin
+            assert m[0] <= qmin * (1 + 1e-9) + 1e-12, (i, rect)
+
+            def f(p):
+                p = np.clip(p, -60, 60)
+                x = rect[0] + (rect[1] - rect[0]) / (1 + math.exp(-p[0]))
+                y = rect[2] + (rect[3] - rect[2]) / (1 + math.exp(-p[1]))
+                X = np.array([(x - cam.cx) / cam.fx, (y - cam.cy) / cam.fy, 1.0]) * math.exp(p[2]) - mu
+                return X @ P @ X
+
+            best = min(minimize(f, np.array([a, b, c]), method="Nelder-Mead",
+                                options=dict(xatol=1e-10, fatol=1e-14, maxiter=40000)).fun
+                       for a in (-2, 2) for b in (-2, 2) for c in (-8, -2, 0, 2))
+            best = min(best, float(mu @ P @ mu))
+            assert m[0] <= best * (1 + 1e-9) + 1e-12, (i, rect)
+            assert best == pytest.approx(m[0], rel=2e-3, abs=1e-6), (i, rect)
+            checked += 1
+    assert checked == 4 * sc.n
+
+
+def _sphere(centre, logit=2.0, radius=1.0):
+    """Isotropic Gaussian whose level-tau sphere (filter off) has about the given radius."""
+    a = 1.0 / (1.0 + math.exp(-logit))
+    tau = 2.0 * math.log(255.0 * a)
+    s = radius / math.sqrt(tau)
+    sh = np.zeros((1, 3, 1), np.float32)
+    return S.Scene(np.asarray(centre, np.float32).reshape(3, 1), np.full((3, 1), math.log(s), np.float32),
+                   np.array([[1.0], [0.0], [0.0], [0.0]], np.float32), np.array([logit], np.float32), sh, None)
+
+
+def test_sampled_bounds_behind_and_straddling_spheres():
+    """A sphere seen from a camera on its outside (Sec. 3.3): the horizontal
+    angles of its surface lie between the two tangent planes through the
+    camera's vertical axis, theta_c -/+ asin(R / rho) with theta_c =
+    atan2(x_c, z_c) and rho = hypot(x_c, z_c).  Only surface points in front
+    of the camera (z > 0) reach the screen, so a sphere centred behind the
+    camera plane that reaches in front covers screen x from cx + fx
+    tan(theta_c - asin(R / rho)) to +infinity (and y without bound on both
+    sides); one wholly behind covers nothing and is culled."""
+    cam = identity_camera(200, 200, 100.0)
+    st = S.Settings(**OFF)
+    statuses = []
+    for centre in [(3.0, 0.2, -0.5), (1.2, 0.0, -0.2), (1.6, -0.3, 0.05), (-1.1, 0.1, -0.15)]:
+        sc = _sphere(centre)
+        pp = O.preprocess(sc, cam, st)
+        Rr = math.sqrt(pp["tau"][0]) * pp["s_t"][0, 0]
+        mv = pp["mu_v"][:, 0]
+        th = math.atan2(mv[0], mv[2])
+        half = math.asin(Rr / math.hypot(mv[0], mv[2]))
+        st_, out = O.sampled_bounds(sc, cam, st, 0, 1024, 2048)
+        if th > 0:   # right of the camera: the tangent th - half is the finite bound, the range runs to +inf
+            assert th - half < math.pi / 2 < th + half
+            x_lo = cam.cx + cam.fx * math.tan(th - half)
+            assert out[0] == pytest.approx(x_lo, abs=0.5)
+            assert out[1] > 50 * cam.width
+            meets = x_lo < cam.width
+        else:        # left of the camera: mirrored
+            assert th - half < -math.pi / 2 < th + half
+            x_hi = cam.cx + cam.fx * math.tan(th + half)
+            assert out[1] == pytest.approx(x_hi, abs=0.5)
+            assert out[0] < -50 * cam.width
+            meets = x_hi > 0
+        assert out[2] < -20 * cam.height and out[3] > 20 * cam.height
+        # the whole-view cull (Sec. 3.4) keeps it exactly when that range meets the image
+        assert pp["status"][0] == (O.VISIBLE if meets else O.OUTSIDE)
+        statuses.append(int(pp["status"][0]))
+    assert O.VISIBLE in statuses and O.OUTSIDE in statuses
+    # wholly behind the camera: no surface point in front, whole-frustum cull
+    sc = _sphere((0.4, -0.3, -3.0))
+    st_, out = O.sampled_bounds(sc, cam, st, 0, 256, 512)
+    assert st_ == O.OUTSIDE
+    assert out[0] > out[1] and out[2] > out[3]
+    # camera inside the level set: discarded before any bound is taken
+    sc = _sphere((0.2, 0.0, -0.3))
+    assert O.preprocess(sc, cam, st)["status"][0] == O.CAM_INSIDE
