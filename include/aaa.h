@@ -102,8 +102,11 @@ typedef struct {
  * capacity K of the per-ray re-sort window (0 = blend in tile order; the
  * supported values are 0, 1, 2, 4, 8, 16, 32).  alpha_min: contribution
  * threshold (a Gaussian contributes to a pixel iff min(alpha_max, alpha~
- * exp(-rho^2/2)) >= alpha_min); alpha_max: opacity clamp; t_min: blending
- * stops before the first entry that would take transmittance below t_min.
+ * exp(-rho^2/2)) >= alpha_min); alpha_max: opacity clamp, below 1 also
+ * after rounding to float (the backward divides by 1 - alpha; 0.99 in the
+ * 3DGS lineage); t_min: blending stops before the first entry that would
+ * take transmittance below t_min.  Calls reject settings outside
+ * 0 < alpha_min < alpha_max < 1, 0 <= t_min < 1 with AAA_ERR_INVALID.
  * Host. */
 typedef struct {
     double filter_k;

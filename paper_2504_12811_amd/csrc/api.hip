@@ -169,8 +169,11 @@ int check_common(const aaa_scene *sc, int nviews, const aaa_camera *cams, const 
     int K = st->ray_window;
     if (!(K == 0 || K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32))
         return fail(AAA_ERR_INVALID, "ray_window %d not one of 0,1,2,4,8,16,32", K);
-    if (!((float)st->alpha_min > 0 && st->alpha_min < st->alpha_max && st->alpha_max <= 1.0 && st->t_min >= 0 && st->t_min < 1))
-        return fail(AAA_ERR_INVALID, "need 0 < alpha_min < alpha_max <= 1 and 0 <= t_min < 1");
+    // alpha_max < 1 in float: the kernels blend with 1 - alpha and the
+    // backward divides by it, so an opaque clamp is not representable
+    if (!((float)st->alpha_min > 0 && st->alpha_min < st->alpha_max && (float)st->alpha_max < 1.0f && st->t_min >= 0 &&
+          st->t_min < 1))
+        return fail(AAA_ERR_INVALID, "need 0 < alpha_min < alpha_max < 1 (as float) and 0 <= t_min < 1");
     if (!(st->filter_k >= 0)) return fail(AAA_ERR_INVALID, "filter_k must be >= 0");
     return AAA_OK;
 }

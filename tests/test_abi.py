@@ -51,6 +51,15 @@ def test_workspace_size_host_checks():
     assert lib.aaa_workspace_size(C.byref(_abi_scene()), C.byref(c), C.byref(bad), 1000, C.byref(need)) == L.AAA_ERR_INVALID
     assert b"ray_window" in lib.aaa_last_error()
     assert lib.aaa_workspace_size(C.byref(_abi_scene(deg=4)), C.byref(c), C.byref(st), 1000, C.byref(need)) == L.AAA_ERR_UNSUPPORTED
+    # an opacity clamp of 1 (or one that rounds to 1 in float) is rejected:
+    # the backward divides by 1 - alpha
+    for amax in (1.0, 1.0 - 1e-9, 1.5):
+        bad = L.make_settings(S.Settings(alpha_max=amax, t_min=0.0))
+        assert lib.aaa_workspace_size(C.byref(_abi_scene()), C.byref(c), C.byref(bad), 1000,
+                                      C.byref(need)) == L.AAA_ERR_INVALID, amax
+        assert b"alpha_max" in lib.aaa_last_error()
+    ok = L.make_settings(S.Settings(alpha_max=0.999, t_min=0.0))
+    assert lib.aaa_workspace_size(C.byref(_abi_scene()), C.byref(c), C.byref(ok), 1000, C.byref(need)) == L.AAA_OK
     c.width = 0
     assert lib.aaa_workspace_size(C.byref(_abi_scene()), C.byref(c), C.byref(st), 1000, C.byref(need)) == L.AAA_ERR_INVALID
 
