@@ -464,7 +464,21 @@ typedef struct {
     int done;
     int flag;
     int64_t nblend;
+    double errT; /* relative error bound of a float32 T after the entries blended so far */
+    int flip_at; /* termination test (counted from 0) taken the other way; -1: none */
+    int ncall;   /* termination tests so far */
+    int nterm;   /* termination tests within their band (flag 4), recorded in term_at */
+    int term_at[4];
 } or_pixel_state;
+
+static or_pixel_state pixel_state_init(int flip_at)
+{
+    or_pixel_state ps;
+    memset(&ps, 0, sizeof ps);
+    ps.T = 1.0;
+    ps.flip_at = flip_at;
+    return ps;
+}
 
 static double max3(const double *c)
 {
@@ -473,20 +487,38 @@ static double max3(const double *c)
 }
 
 /* O12: front-to-back blending with early termination: stop, without blending
- * it, at the first entry that would take T below t_min (3DGS lineage). */
+ * it, at the first entry that would take T below t_min (3DGS lineage).
+ *
+ * Flag 4 marks a termination test that a float32 implementation may take the
+ * other way.  Its band is an error bound of a float32 T: every blended entry
+ * multiplies T by 1 - alpha, where alpha has a relative error of at most
+ * band_alpha (the band of the alpha test; zero when alpha is clamped at
+ * alpha_max, a value both sides hit exactly), which gives 1 - alpha a
+ * relative error of band_alpha * alpha / (1 - alpha), plus two roundings
+ * (the subtraction and the product) of 2^-24 each.  These add up over the
+ * entries blended; band_T is a floor. */
 static void blend_one(or_pixel_state *ps, const or_settings *st, or_contrib *e)
 {
     if (ps->done) return;
     double Tn = ps->T * (1.0 - e->a);
     double cm = max3(e->c);
-    if (fabs(Tn - st->t_min) <= st->band_T * st->t_min && ps->T * e->a * (cm > 1 ? cm : 1) > 5e-5) ps->flag |= 4;
-    if (Tn < st->t_min) {
+    double errTn = ps->errT + (e->clamped ? 0.0 : st->band_alpha * e->a / (1.0 - e->a)) + 2.0 * 0x1p-24;
+    double band = errTn > st->band_T ? errTn : st->band_T;
+    if (fabs(Tn - st->t_min) <= band * st->t_min && ps->T * e->a * (cm > 1 ? cm : 1) > 5e-5) {
+        ps->flag |= 4;
+        if (ps->nterm < 4) ps->term_at[ps->nterm++] = ps->ncall;
+    }
+    int stop = Tn < st->t_min;
+    if (ps->ncall == ps->flip_at) stop = !stop; /* an alternative outcome of a flagged test */
+    ps->ncall++;
+    if (stop) {
         ps->done = 1;
         return;
     }
     e->tat = ps->T;
     for (int k = 0; k < 3; ++k) ps->C[k] += ps->T * e->a * e->c[k];
     ps->T = Tn;
+    ps->errT = errTn;
     ps->nblend++;
 }
 
@@ -627,9 +659,65 @@ static void pixel_reverse(or_contrib *seq, int64_t ns, int64_t *idx, const or_ga
     }
 }
 
+/* Alternative outcomes of a flagged pixel.  Each flagged decision (a
+ * membership test within its band, an ambiguous camera-inside Gaussian, a
+ * near-tie in either ordering key, a termination test within its band) is
+ * taken the other way, one at a time, and the pixel blended again; an FP32
+ * implementation may legitimately produce any of these results. */
+#define OR_MAX_ALT 16
+typedef struct {
+    or_contrib e; /* the entry as it would contribute */
+    int in_seq;   /* it is in the sequence (the alternative removes it) */
+} or_near;
+typedef struct {
+    int kind;     /* 0: tile-order neighbours i, j swapped; 1: window-order q moved in front of p */
+    int64_t i, j;
+} or_tie;
+
+static void blend_alternative(const or_contrib *s2, int64_t ns2, or_contrib *buf, int K, const or_settings *st,
+                              const or_camera *cam, int flip_at, int64_t *win, double *out)
+{
+    memcpy(buf, s2, sizeof(or_contrib) * (size_t)ns2);
+    or_pixel_state ps = pixel_state_init(flip_at);
+    window_blend(buf, ns2, K, &ps, st, win);
+    for (int k = 0; k < 3; ++k) out[k] = ps.C[k] + ps.T * cam->bg[k];
+    out[3] = ps.T;
+}
+
+static int pixel_alternatives(const or_contrib *seq, int64_t ns, const or_near *nr, int nnear, const or_tie *ties,
+                              int nties, const or_pixel_state *ps, int K, const or_settings *st, const or_camera *cam,
+                              or_contrib *s2, or_contrib *buf, int64_t *win, double *out)
+{
+    int na = 0;
+    for (int q = 0; q < nnear && na < OR_MAX_ALT; ++q) {
+        int64_t n2 = 0;
+        for (int64_t j = 0; j < ns; ++j)
+            if (!(nr[q].in_seq && seq[j].id == nr[q].e.id)) s2[n2++] = seq[j];
+        if (!nr[q].in_seq) {
+            s2[n2++] = nr[q].e;
+            qsort(s2, n2, sizeof(or_contrib), cmp_tile_order);
+        }
+        blend_alternative(s2, n2, buf, K, st, cam, -1, win, out + 4 * na++);
+    }
+    for (int q = 0; q < nties && na < OR_MAX_ALT; ++q) {
+        memcpy(s2, seq, sizeof(or_contrib) * (size_t)ns);
+        if (ties[q].kind == 0) {
+            or_contrib t = s2[ties[q].i];
+            s2[ties[q].i] = s2[ties[q].j];
+            s2[ties[q].j] = t;
+        } else {
+            s2[ties[q].j].z = nextafter(s2[ties[q].i].z, -INFINITY);
+        }
+        blend_alternative(s2, ns, buf, K, st, cam, -1, win, out + 4 * na++);
+    }
+    for (int q = 0; q < ps->nterm && na < OR_MAX_ALT; ++q)
+        blend_alternative(seq, ns, buf, K, st, cam, ps->term_at[q], win, out + 4 * na++);
+    return na;
+}
+
 static int render_impl(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
                        double *out_rgb, double *out_T, uint8_t *out_flags, int32_t *out_ncontrib, or_stats *stats,
-                       const double *dL_drgb, double *gi)
+                       const double *dL_drgb, double *gi, const int32_t *alt_slot, double *alt_out, int32_t *alt_n)
 {
     const int64_t n = sc->n;
     const int W = cam->width, H = cam->height;
@@ -673,7 +761,9 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
 
 #pragma omp parallel reduction(+ : tot_contrib, tot_blend, tot_flag)
     {
-        or_contrib *seq = NULL;
+        or_contrib *seq = NULL, *s2 = NULL, *s3 = NULL;
+        or_near nr[OR_MAX_ALT];
+        or_tie ties[OR_MAX_ALT];
         int64_t *win = (int64_t *)malloc(sizeof(int64_t) * (K + 2));
         int64_t *ridx = NULL;
         double *dt = NULL;
@@ -687,6 +777,10 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
             if (m > cap) {
                 cap = m;
                 seq = (or_contrib *)realloc(seq, sizeof(or_contrib) * cap);
+                if (alt_slot) {
+                    s2 = (or_contrib *)realloc(s2, sizeof(or_contrib) * (cap + 1));
+                    s3 = (or_contrib *)realloc(s3, sizeof(or_contrib) * (cap + 1));
+                }
                 dt = (double *)realloc(dt, sizeof(double) * cap);
                 zi = (int64_t *)realloc(zi, sizeof(int64_t) * cap);
                 ridx = (int64_t *)realloc(ridx, sizeof(int64_t) * cap);
@@ -699,7 +793,8 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
             }
             for (int py = ty * OR_TILE; py < ty * OR_TILE + OR_TILE && py < H; ++py)
                 for (int px = tx * OR_TILE; px < tx * OR_TILE + OR_TILE && px < W; ++px) {
-                    or_pixel_state ps = {1.0, {0, 0, 0}, 0, 0, 0};
+                    or_pixel_state ps = pixel_state_init(-1);
+                    int nnear = 0, nties = 0;
                     int64_t ns = 0;
                     double x = px + 0.5, y = py + 0.5; /* pixel centre */
                     for (int64_t j = 0; j < m; ++j) {
@@ -711,14 +806,33 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                         int near_a = fabs(a - st->alpha_min) <= st->band_alpha * st->alpha_min;
                         int near_z = fabs(z - cam->znear) <= st->band_z * fabs(cam->znear);
                         int contrib = a >= st->alpha_min && z >= cam->znear;
+                        int near_member = 0;
                         if ((near_a && z >= cam->znear * (1 - st->band_z)) ||
-                            (near_z && a >= st->alpha_min * (1 - st->band_alpha)))
+                            (near_z && a >= st->alpha_min * (1 - st->band_alpha))) {
                             ps.flag |= 1;
+                            near_member = 1;
+                        }
                         if (g->status != OR_VISIBLE) {
                             /* ambiguous camera-inside Gaussian */
-                            if (a >= st->alpha_min * (1 - st->band_alpha) && z >= cam->znear * (1 - st->band_z)) ps.flag |= 8;
-                            continue;
+                            if (a >= st->alpha_min * (1 - st->band_alpha) && z >= cam->znear * (1 - st->band_z)) {
+                                ps.flag |= 8;
+                                near_member = 1;
+                            }
                         }
+                        if (near_member && alt_slot && nnear < OR_MAX_ALT) {
+                            or_contrib *q = &nr[nnear].e;
+                            q->dtile = dt[j];
+                            q->id = lists[b + j];
+                            q->z = z;
+                            q->a = a;
+                            q->c = g->color;
+                            q->tat = -1.0;
+                            q->r2 = r2;
+                            q->clamped = g->alpha_t * exp(-0.5 * r2) > st->alpha_max;
+                            nr[nnear].in_seq = contrib && g->status == OR_VISIBLE;
+                            nnear++;
+                        }
+                        if (g->status != OR_VISIBLE) continue;
                         if (contrib) {
                             seq[ns].dtile = dt[j];
                             seq[ns].id = lists[b + j];
@@ -743,8 +857,10 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                             for (int64_t j = 1; j < ns; ++j) {
                                 double d0 = seq[j - 1].dtile, d1 = seq[j].dtile;
                                 double sc = fabs(d0) > fabs(d1) ? fabs(d0) : fabs(d1);
-                                if (fabs(d1 - d0) <= st->band_tie * sc && swap_impact(&seq[j - 1], &seq[j]) > imp)
+                                if (fabs(d1 - d0) <= st->band_tie * sc && swap_impact(&seq[j - 1], &seq[j]) > imp) {
                                     ps.flag |= 2;
+                                    if (nties < OR_MAX_ALT) ties[nties++] = (or_tie){0, j - 1, j};
+                                }
                             }
                         }
                         if (K > 0) {
@@ -753,11 +869,19 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                             for (int64_t j = 1; j < ns; ++j) {
                                 const or_contrib *p0 = &seq[zi[j - 1]], *p1 = &seq[zi[j]];
                                 double sc = fabs(p0->z) > fabs(p1->z) ? fabs(p0->z) : fabs(p1->z);
-                                if (fabs(p1->z - p0->z) <= st->band_tie * sc && swap_impact(p0, p1) > imp) ps.flag |= 2;
+                                if (fabs(p1->z - p0->z) <= st->band_tie * sc && swap_impact(p0, p1) > imp) {
+                                    ps.flag |= 2;
+                                    if (nties < OR_MAX_ALT) ties[nties++] = (or_tie){1, zi[j - 1], zi[j]};
+                                }
                             }
                         }
                     }
                     int64_t pix = (int64_t)py * W + px;
+                    if (alt_slot && alt_slot[pix] >= 0) {
+                        int32_t sl = alt_slot[pix];
+                        alt_n[sl] = pixel_alternatives(seq, ns, nr, nnear, ties, nties, &ps, K, st, cam, s2, s3, win,
+                                                       alt_out + (int64_t)sl * OR_MAX_ALT * 4);
+                    }
                     if (dL_drgb) {
                         double gC[3] = {dL_drgb[pix], dL_drgb[(int64_t)H * W + pix], dL_drgb[2 * (int64_t)H * W + pix]};
                         pixel_reverse(seq, ns, ridx, gs, cam, gC, x, y, gi);
@@ -772,6 +896,8 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                 }
         }
         free(seq);
+        free(s2);
+        free(s3);
         free(win);
         free(dt);
         free(zi);
@@ -796,8 +922,27 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
 int or_render(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
               double *out_rgb, double *out_T, uint8_t *out_flags, int32_t *out_ncontrib, or_stats *stats)
 {
-    return render_impl(sc, cam, st, tile_sel, out_rgb, out_T, out_flags, out_ncontrib, stats, NULL, NULL);
+    return render_impl(sc, cam, st, tile_sel, out_rgb, out_T, out_flags, out_ncontrib, stats, NULL, NULL, NULL, NULL,
+                       NULL);
 }
+
+/* Alternative outcomes (see pixel_alternatives) of the pixels with
+ * alt_slot[pix] >= 0 ([H][W], -1 elsewhere): alt_out [slots][OR_MAX_ALT][4]
+ * (rgb + T * bg, T) and their number alt_n [slots].  Only tiles in tile_sel
+ * (NULL = all) are rendered. */
+int or_render_alternatives(const or_scene *sc, const or_camera *cam, const or_settings *st, const uint8_t *tile_sel,
+                           const int32_t *alt_slot, double *alt_out, int32_t *alt_n)
+{
+    int64_t np = (int64_t)cam->width * cam->height;
+    double *rgb = (double *)malloc(sizeof(double) * 3 * (np > 0 ? np : 1));
+    double *T = (double *)malloc(sizeof(double) * (np > 0 ? np : 1));
+    int rc = render_impl(sc, cam, st, tile_sel, rgb, T, NULL, NULL, NULL, NULL, NULL, alt_slot, alt_out, alt_n);
+    free(rgb);
+    free(T);
+    return rc;
+}
+
+int or_max_alternatives(void) { return OR_MAX_ALT; }
 
 /* ------------------------------------------------------------------------ */
 /* Per-Gaussian outputs for stage checks: status, alpha~, tau, filtered scales,
@@ -941,6 +1086,16 @@ int or_sampled_bounds(const or_scene *sc, const or_camera *cam, const or_setting
         }
     }
     return g.status;
+}
+
+/* or_sampled_bounds for each of n_ids Gaussians: out[4 * q ..] and
+ * status[q] for ids[q] (in parallel over the queries). */
+int or_sampled_bounds_many(const or_scene *sc, const or_camera *cam, const or_settings *st, int64_t n_ids,
+                           const int64_t *ids, int nt, int np, double *out, int32_t *status)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n_ids; ++q) status[q] = or_sampled_bounds(sc, cam, st, ids[q], nt, np, out + 4 * q);
+    return 0;
 }
 
 int or_num_threads(void)
@@ -1104,7 +1259,7 @@ int or_render_backward(const or_scene *sc, const or_camera *cam, const or_settin
     double *gi = (double *)calloc((size_t)(n > 0 ? n : 1) * OR_GI, sizeof(double));
     if (!gi) return 1;
     or_stats stt;
-    int rc = render_impl(sc, cam, st, NULL, out_rgb, out_T, out_flags, NULL, &stt, dL_drgb, gi);
+    int rc = render_impl(sc, cam, st, NULL, out_rgb, out_T, out_flags, NULL, &stt, dL_drgb, gi, NULL, NULL, NULL);
     if (rc) { free(gi); return rc; }
     const int deg = sc->sh_degree, nb = (deg + 1) * (deg + 1);
     const int npar = 11 + 3 * nb;

@@ -23,10 +23,13 @@ VISIBLE, INVALID, LOW_OPACITY, CAM_INSIDE, OUTSIDE = 0, 1, 2, 3, 4
 
 # Relative bands inside which an FP32 implementation may take a threshold
 # decision the other way; pixels touched by such a decision are flagged.
+# The termination band is an error bound accumulated per pixel from
+# BAND_ALPHA over the blended entries (aaa_oracle.c, blend_one); BAND_T is
+# its floor.
 BAND_ALPHA = 3e-5
 BAND_Z = 1e-5
 BAND_TIE = 2e-6
-BAND_T = 1e-3
+BAND_T = 1e-5
 
 
 def build(force: bool = False) -> str:
@@ -152,6 +155,31 @@ def render(scene, cam, settings, tile_sel=None) -> RenderResult:
                         stats.n_blended_total, stats.n_flagged)
 
 
+def render_alternatives(scene, cam, settings, pixels, tile_sel=None):
+    """Alternative outcomes of the given pixels ((y, x) pairs): every flagged
+    decision of a pixel taken the other way, one at a time (see
+    pixel_alternatives in aaa_oracle.c).  Returns a list, per pixel, of an
+    array [n_alt, 4] (r, g, b, T)."""
+    L = lib()
+    sh = _SceneHolder(scene)
+    c, s = _camera(cam), _settings(settings)
+    H, W = int(cam.height), int(cam.width)
+    pixels = np.asarray(pixels, np.int64).reshape(-1, 2)
+    slot = np.full((H, W), -1, np.int32)
+    slot[pixels[:, 0], pixels[:, 1]] = np.arange(len(pixels), dtype=np.int32)
+    ma = int(L.or_max_alternatives())
+    out = np.zeros((max(len(pixels), 1), ma, 4))
+    na = np.zeros(max(len(pixels), 1), np.int32)
+    if len(pixels):
+        sel = None if tile_sel is None else np.ascontiguousarray(tile_sel, dtype=np.uint8)
+        L.or_render_alternatives.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Settings), C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p]
+        rc = L.or_render_alternatives(C.byref(sh.s), C.byref(c), C.byref(s), None if sel is None else _p(sel),
+                                      _p(slot), _p(out), _p(na))
+        assert rc == 0
+    return [out[k, : na[k]] for k in range(len(pixels))]
+
+
 def preprocess(scene, cam, settings) -> dict:
     L = lib()
     sh = _SceneHolder(scene)
@@ -217,6 +245,20 @@ def sampled_bounds(scene, cam, settings, i, nt=256, np_=512):
     L.or_sampled_bounds.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Settings), C.c_int64, C.c_int,
                                     C.c_int, C.c_void_p]
     st = L.or_sampled_bounds(C.byref(sh.s), C.byref(c), C.byref(s), int(i), nt, np_, _p(out))
+    return st, out
+
+
+def sampled_bounds_many(scene, cam, settings, ids, nt=256, np_=512):
+    """sampled_bounds for several Gaussians: (status [q], bounds [q, 4])."""
+    L = lib()
+    sh = _SceneHolder(scene)
+    c, s = _camera(cam), _settings(settings)
+    ids = np.ascontiguousarray(ids, np.int64)
+    out = np.zeros((len(ids), 4))
+    st = np.zeros(len(ids), np.int32)
+    L.or_sampled_bounds_many.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Settings), C.c_int64,
+                                         C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    L.or_sampled_bounds_many(C.byref(sh.s), C.byref(c), C.byref(s), len(ids), _p(ids), nt, np_, _p(out), _p(st))
     return st, out
 
 

@@ -309,3 +309,83 @@ def test_sampled_bounds_behind_and_straddling_spheres():
     # camera inside the level set: discarded before any bound is taken
     sc = _sphere((0.2, 0.0, -0.3))
     assert O.preprocess(sc, cam, st)["status"][0] == O.CAM_INSIDE
+
+
+# ----------------------------------------------------------------------------
+# alternative outcomes of flagged pixels (the parity check accepts them)
+
+
+def _alts_at(sc, cam, st, py, px):
+    r = O.render(sc, cam, st)
+    return r, O.render_alternatives(sc, cam, st, [(py, px)])[0]
+
+
+def test_alternative_of_a_depth_tie_is_the_swapped_order():
+    """Two flat sheets at the same depth: the window orders them by index
+    (P, then Q), the pixel is flagged as a near-tie, and its one alternative
+    outcome is the blend Q, P written out by hand."""
+    cam = identity_camera(16, 16, 8.0, bg=(0.0, 0.0, 0.0))
+    colours = [(1.0, 0.0, 0.0), (0.0, 0.0, 1.0)]
+    sc = sheets([2.0, 2.0], [0.0, 0.0], colours)
+    st = S.Settings(ray_window=16, **OFF)
+    r, alts = _alts_at(sc, cam, st, 7, 7)
+    al = {k: closed_form(sc, cam, i, 7.5, 7.5)[1] for i, k in enumerate("PQ")}
+    col = dict(zip("PQ", colours))
+    C, T = blend("PQ", al, col, cam.bg)
+    Cs, Ts = blend("QP", al, col, cam.bg)
+    assert r.flags[7, 7] & 2
+    np.testing.assert_allclose(r.rgb[:, 7, 7], C, atol=1e-9)
+    assert alts.shape == (1, 4)
+    np.testing.assert_allclose(alts[0, :3], Cs, atol=1e-9)
+    assert alts[0, 3] == pytest.approx(Ts, abs=1e-12)
+    assert np.abs(Cs - C).max() > 0.1
+
+
+def test_alternative_of_a_termination_in_band_stops_one_entry_earlier():
+    """Two opaque flat sheets (alpha clamped at 0.99): after both, T =
+    0.01^2 = t_min up to rounding, so the test 'T (1 - alpha) < t_min' is
+    within its band: the oracle blends the second sheet (T is not below
+    t_min in FP64), flags the pixel, and its alternative stops before the
+    second sheet: C = 0.99 c1, T = 0.01."""
+    cam = identity_camera(16, 16, 8.0, bg=(0.0, 0.0, 0.0))
+    colours = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0)]
+    sc = sheets([2.0, 2.2], [0.0, 0.0], colours, logit=12.0)
+    st = S.Settings(ray_window=16, **OFF)
+    r, alts = _alts_at(sc, cam, st, 8, 8)
+    assert r.flags[8, 8] & 4
+    np.testing.assert_allclose(r.rgb[:, 8, 8], [0.99, 0.01 * 0.99, 0.0], atol=1e-9)
+    assert r.T[8, 8] == pytest.approx(1e-4, rel=1e-9)
+    assert alts.shape == (1, 4)
+    np.testing.assert_allclose(alts[0], [0.99, 0.0, 0.0, 0.01], atol=1e-12)
+
+
+def test_alternative_of_a_membership_test_in_band_drops_the_entry():
+    """A faint sheet in front whose alpha on the optical axis is 1/255 (1 +
+    1e-5), inside the alpha band: it contributes in FP64, the pixel is
+    flagged, and the alternative is the blend of the strong sheet behind it
+    alone."""
+    cam = identity_camera(16, 16, 8.0, bg=(0.0, 0.0, 0.0))
+    p = (1.0 / 255.0) * (1.0 + 1e-5)
+    colours = [(1.0, 1.0, 1.0), (0.0, 1.0, 0.0)]
+    sc = sheets([1.5, 2.2], [0.0, 0.0], colours)
+    sc.opacity_logits[:] = np.float32([math.log(p / (1 - p)), 1.0])
+    st = S.Settings(ray_window=16, **OFF)
+    # centre both sheets on the line of pixel (8, 8), direction (1/16, 1/16, 1),
+    # so that the faint one's alpha there is its opacity
+    sc.means[0, :] = np.float32(0.5 / 8.0 * 1.5)
+    sc.means[1, :] = np.float32(0.5 / 8.0 * 1.5)
+    sc.means[0, 1] = np.float32(0.5 / 8.0 * 2.2)
+    sc.means[1, 1] = np.float32(0.5 / 8.0 * 2.2)
+    r, alts = _alts_at(sc, cam, st, 8, 8)
+    a_faint = closed_form(sc, cam, 0, 8.5, 8.5)[1]
+    a_strong = closed_form(sc, cam, 1, 8.5, 8.5)[1]
+    assert abs(a_faint * 255.0 - 1.0) < 3e-5 and a_faint >= 1.0 / 255.0
+    assert r.flags[8, 8] & 1
+    al = {"F": a_faint, "S": a_strong}
+    col = {"F": colours[0], "S": colours[1]}
+    C, T = blend("FS", al, col, cam.bg)
+    Cs, Ts = blend("S", al, col, cam.bg)
+    np.testing.assert_allclose(r.rgb[:, 8, 8], C, atol=1e-9)
+    assert alts.shape == (1, 4)
+    np.testing.assert_allclose(alts[0, :3], Cs, atol=1e-9)
+    assert alts[0, 3] == pytest.approx(Ts, abs=1e-12)
