@@ -69,9 +69,11 @@ def test_server_results_equal_solo_renders(ras):
     ds = DeviceScene.from_host(scene, "cuda:0")
     st = S.Settings()
     rng = np.random.default_rng(11)
+    # requests as drawn: mixed resolutions (stereo pairs included), fields of
+    # view and zoom distances
     reqs = [random_request(rng) for _ in range(12)]
-    # keep the test quick: cap the resolution
-    reqs = [[S.pinhole(c.position, min(c.width, 640), min(c.height, 480), 60.0) for c in r] for r in reqs]
+    fov = lambda c: round(float(np.degrees(2 * np.arctan(c.width / 2 / c.fx))), 1)
+    print("requests (views, W, H, fov):", [(len(r), r[0].width, r[0].height, fov(r[0])) for r in reqs], flush=True)
     fn = gpu_render_batch(ds, st, n_workers=2)
     with Server(fn, n_gaussians=ds.n, mem_cap=8 << 30, max_batch=4, n_workers=2) as srv:
         futs = [srv.submit(r) for r in reqs]

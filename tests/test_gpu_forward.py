@@ -16,6 +16,7 @@ from paper_2504_12811_amd import scenes as S
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-4
+OVER_FRAC = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -30,40 +31,62 @@ def dev(scene):
     return DeviceScene.from_host(scene, "cuda:0")
 
 
-def compare_image(ras, scene, cam, st, tile_sel=None, label="", max_flagged=0.02):
+def compare_image(ras, scene, cam, st, tile_sel=None, label=""):
+    """Render on the GPU and with the oracle and hold the image to the bar of
+    check_image."""
     rgb, T, stats = ras.render(dev(scene), cam, st)
     torch.cuda.synchronize()
     ref = O.render(scene, cam, st, tile_sel=tile_sel)
+    alts = lambda px: O.render_alternatives(scene, cam, st, px, tile_sel=tile_sel)
+    return check_image(rgb, T, ref, cam, tile_sel, label, stats.pairs, alts) + (ref,)
+
+
+def check_image(rgb, T, ref, cam, tile_sel=None, label="", pairs=None, alternatives=None):
+    """On the selected pixels (all, or the tiles of tile_sel):
+    - every pixel the oracle does not flag matches within TOL (rgb and T);
+    - a flagged pixel (a decision within the FP32 band of its threshold)
+      that misses the oracle by more than TOL must match, within TOL, one of
+      the oracle's alternative outcomes of that pixel (each flagged decision
+      taken the other way): several results are correct there;
+    - pixels matching neither are at most OVER_FRAC of those compared;
+    the flagged fraction and the pixels over TOL are reported."""
     g = rgb.cpu().numpy().astype(np.float64)
     gT = T.cpu().numpy().astype(np.float64)
-    mask = ref.flags == 0
     if tile_sel is not None:
         tx, ty = cam.tiles
         sel = np.asarray(tile_sel, bool).reshape(ty, tx)
         pixsel = np.kron(sel, np.ones((16, 16), bool))[: cam.height, : cam.width]
-        mask &= pixsel
-        nsel = pixsel.sum()
     else:
-        nsel = cam.width * cam.height
-    err = np.abs(g - ref.rgb)[:, mask]
-    errT = np.abs(gT - ref.T)[mask]
-    emax = float(err.max()) if err.size else 0.0
-    eT = float(errT.max()) if errT.size else 0.0
-    flagged = int(nsel - mask.sum())
-    fl = (ref.flags != 0)
-    if tile_sel is not None:
-        fl &= pixsel
-    ef = np.abs(g - ref.rgb).max(0)[fl]
-    print(f"[{label}] pairs={stats.pairs} pixels={nsel} flagged={flagged} ({flagged / max(nsel, 1):.2e}) "
-          f"max|drgb|={emax:.3e} max|dT|={eT:.3e} flagged: max|drgb|={ef.max() if ef.size else 0:.3e} "
-          f"over-tol={int((ef > TOL).sum())}", flush=True)
-    if emax > TOL:
-        bad = np.argwhere(np.abs(g - ref.rgb).max(0) * mask > TOL)
-        print("worst pixels (y,x):", bad[:10].tolist(), flush=True)
+        pixsel = np.ones((cam.height, cam.width), bool)
+    nsel = int(pixsel.sum())
+    mask = (ref.flags == 0) & pixsel
+    fl = (ref.flags != 0) & pixsel
+    dpix = np.maximum(np.abs(g - ref.rgb).max(0), np.abs(gT - ref.T))
+    emax = float(np.abs(g - ref.rgb)[:, mask].max()) if mask.any() else 0.0
+    eT = float(np.abs(gT - ref.T)[mask].max()) if mask.any() else 0.0
+    flagged = int(fl.sum())
+    over_px = np.argwhere((dpix > TOL) & pixsel)
+    explained = 0
+    if len(over_px) and alternatives is not None:
+        cand = over_px[ref.flags[over_px[:, 0], over_px[:, 1]] != 0]
+        for (y, x), alt in zip(cand, alternatives(cand) if len(cand) else []):
+            mine = np.concatenate([g[:, y, x], [gT[y, x]]])
+            if len(alt) and np.abs(alt - mine[None]).max(1).min() <= TOL:
+                explained += 1
+    over = len(over_px)
+    unexplained = over - explained
+    ef = float(dpix[fl].max()) if flagged else 0.0
+    print(f"[{label}] pairs={pairs} pixels={nsel} flagged={flagged} ({flagged / max(nsel, 1):.2e}) "
+          f"max|drgb|={emax:.3e} max|dT|={eT:.3e} flagged max|d|={ef:.3e} over-tol={over} "
+          f"(matching an alternative outcome: {explained}; neither: {unexplained} = "
+          f"{unexplained / max(nsel, 1):.2e}, bar {OVER_FRAC:.0e})", flush=True)
+    if emax > TOL or unexplained:
+        print("pixels over tol (y,x):", over_px[:10].tolist(), "flags:",
+              [int(ref.flags[y, x]) for y, x in over_px[:10]], flush=True)
     assert emax <= TOL
     assert eT <= TOL
-    assert flagged <= max(8, max_flagged * nsel)
-    return rgb, T, stats, ref
+    assert unexplained <= OVER_FRAC * nsel
+    return rgb, T, pairs
 
 
 # --------------------------------------------------------------------------
@@ -144,8 +167,10 @@ def test_sort_bit_exact(ras):
     from paper_2504_12811_amd.render import sort_pairs
     rng = np.random.default_rng(5)
     # key widths with one, two, four, five, six and eight 8-bit passes
+    # 5M and 100M keys: more than 2048 blocks, so the digit scan carries
+    # across rounds
     for n, bits in [(1, 40), (7, 40), (4096, 45), (4097, 45), (300_001, 45), (1 << 20, 64), (65_537, 47),
-                    (9_999, 32), (2_049, 17), (513, 8)]:
+                    (9_999, 32), (2_049, 17), (513, 8), (5_000_011, 47), (100_000_007, 47)]:
         tiles = rng.integers(0, 8160, n, dtype=np.uint64)
         depth = rng.integers(0, 1 << 32, n, dtype=np.uint64)
         depth[: n // 3] = depth[0]  # many ties
@@ -186,9 +211,9 @@ def test_image_filter_variants(ras, mode):
 
 def test_image_without_tile_culling_is_identical(ras):
     scene, cam = S.small_scene()
-    rgb0, T0, s0, _ = compare_image(ras, scene, cam, S.Settings(), label="cull on")
+    rgb0, T0, p0, _ = compare_image(ras, scene, cam, S.Settings(), label="cull on")
     rgb1, T1, s1 = ras.render(dev(scene), cam, S.Settings(tile_cull=False))
-    assert s1.pairs > s0.pairs
+    assert s1.pairs > p0
     assert torch.equal(rgb0, rgb1) or float((rgb0 - rgb1).abs().max()) <= 1e-6
 
 
@@ -203,6 +228,57 @@ def near_scene(n=3000, seed=3):
                  rng.normal(size=(4, n)).astype(np.float32), rng.normal(0.5, 1.0, n).astype(np.float32),
                  ((rng.uniform(0, 1, (1, 3, n)) - 0.5) / S.SH_C0).astype(np.float32))
     return sc, cam
+
+
+def rect_bounds_check(ras, scene, cam, st, ids, label=""):
+    """O14 (Sec. 3.3, Eq. 14-17): each visible Gaussian's tile rectangle holds
+    every tile reached by the sampled surface points of its level-tau
+    ellipsoid in front of the camera (the exact visible range contains those
+    points), and lies within that sampled range widened by one tile on every
+    side (a rectangle no wider than the bounds need).  A side whose sampled
+    edge lies within 1e-3 px of a tile boundary is not checked for
+    containment (FP32 tau and the samples may put it either way)."""
+    ds = dev(scene)
+    ras.render(ds, cam, st)
+    g = {k: v.cpu().numpy() for k, v in ras.read_gaussians(ds, cam).items()}
+    pp = O.preprocess(scene, cam, st)
+    ids = np.asarray(ids, np.int64)
+    ids = ids[(pp["status"][ids] == O.VISIBLE) & (pp["ambiguous"][ids] == 0) & (g["status"][ids] == 0)]
+    stt, b = O.sampled_bounds_many(scene, cam, st, ids)
+    assert np.all(stt == O.VISIBLE)
+    rect = g["rect"][:, ids].T.astype(np.int64)  # tx0, tx1, ty0, ty1 (half-open)
+    tx, ty = cam.tiles
+    bad_in = bad_out = edge = 0
+    for ax, (lo, hi, nt, size) in enumerate([(b[:, 0], b[:, 1], tx, cam.width), (b[:, 2], b[:, 3], ty, cam.height)]):
+        lo_c = np.clip(lo, 0, size)
+        hi_c = np.clip(hi, 0, size)
+        t0 = np.clip(np.floor(lo_c / 16), 0, nt).astype(np.int64)
+        t1 = np.clip(np.ceil(hi_c / 16), 0, nt).astype(np.int64)
+        t1 = np.where(hi_c > lo_c, np.maximum(t1, t0 + 1), t0)  # empty when the range misses the image
+        g0, g1 = rect[:, 2 * ax], rect[:, 2 * ax + 1]
+        near0 = np.abs(lo_c / 16 - np.round(lo_c / 16)) * 16 <= 1e-3
+        near1 = np.abs(hi_c / 16 - np.round(hi_c / 16)) * 16 <= 1e-3
+        edge += int((near0 | near1).sum())
+        bad_in += int(((g0 > t0) & ~near0 & (t1 > t0)).sum() + ((g1 < t1) & ~near1 & (t1 > t0)).sum())
+        bad_out += int(((g0 < t0 - 1) | (g1 > t1 + 1)).sum())
+    area = (rect[:, 1] - rect[:, 0]) * (rect[:, 3] - rect[:, 2])
+    print(f"[{label}] rectangles checked={len(ids)} (mean {area.mean():.1f} tiles) not containing the sampled "
+          f"range={bad_in} wider than it by more than a tile={bad_out} sides at a tile edge={edge}", flush=True)
+    assert len(ids) > 0
+    assert bad_in == 0
+    assert bad_out == 0
+
+
+def test_rectangles_tight_near_camera(ras):
+    """Near-plane and camera-plane straddlers at 120 deg: every visible
+    Gaussian's rectangle against its sampled bounds."""
+    scene, cam = near_scene()
+    rect_bounds_check(ras, scene, cam, S.Settings(), np.arange(scene.n), "near set rectangles")
+
+
+def test_rectangles_tight_small(ras):
+    scene, cam = S.small_scene()
+    rect_bounds_check(ras, scene, cam, S.Settings(), np.arange(scene.n), "C1 rectangles")
 
 
 def test_image_near_camera_wide_fov(ras):

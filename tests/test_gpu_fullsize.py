@@ -10,7 +10,7 @@ import torch
 from oracle import oracle as O
 from paper_2504_12811_amd import scenes as S
 
-from test_gpu_forward import compare_image
+from test_gpu_forward import compare_image, rect_bounds_check
 
 pytestmark = pytest.mark.gpu
 
@@ -43,32 +43,37 @@ def test_medium_500k_1080p_sampled(ras):
 
 
 def test_ood_3m_primary_sampled(ras, ood):
-    """3M Gaussians, 10% straddling the near plane and the camera: many
-    pixels carry a near-plane or camera-inside decision inside the FP32
-    band, so up to 15% of the sampled pixels may be flagged here; every
-    unflagged pixel must meet 2e-4."""
+    """3M Gaussians, 10% straddling the near plane and the camera plane, at
+    120 deg: 16 tiles (the two at the image centre and 14 sampled) held to
+    the image bar (flagged pixels must match the oracle or one of its
+    alternative outcomes)."""
     scene, cam, _ = ood
     tx, ty = cam.tiles
     centre = (ty // 2) * tx + tx // 2
-    sel = _sample(cam, 2, 2, extra=(centre, centre + 1))
-    from test_gpu_forward import dev
-    rgb, T, stats = ras.render(dev(scene), cam, S.Settings())
-    ref = O.render(scene, cam, S.Settings(), tile_sel=sel)
-    pixsel = np.kron(sel.reshape(ty, tx).astype(bool), np.ones((16, 16), bool))[: cam.height, : cam.width]
-    mask = (ref.flags == 0) & pixsel
-    err = np.abs(rgb.cpu().numpy().astype(np.float64) - ref.rgb)[:, mask]
-    flagged = int(pixsel.sum() - mask.sum())
-    print(f"[3M primary] pairs={stats.pairs} sampled={int(pixsel.sum())} flagged={flagged} max|drgb|={err.max():.3e}")
-    assert err.max() <= 2e-4
-    assert flagged <= 0.15 * pixsel.sum()
+    sel = _sample(cam, 14, 2, extra=(centre, centre + 1))
+    assert sel.sum() >= 16
+    compare_image(ras, scene, cam, S.Settings(), tile_sel=sel, label="3M primary")
+
+
+def test_ood_3m_rectangles_tight(ras, ood):
+    """Rectangles of 2000 near-set Gaussians (straddling the near plane and
+    the camera plane) and 2000 others against their sampled bounds."""
+    scene, cam, _ = ood
+    d = np.linalg.norm(scene.means.astype(np.float64) - cam.position[:, None], axis=0)
+    rng = np.random.default_rng(7)
+    near = np.nonzero(d <= 0.5 + 1e-3)[0]
+    rest = np.nonzero(d > 0.5 + 1e-3)[0]
+    ids = np.concatenate([rng.choice(near, 2000, replace=False), rng.choice(rest, 2000, replace=False)])
+    rect_bounds_check(ras, scene, cam, S.Settings(), ids, "3M primary rectangles")
 
 
 def test_ood_3m_far_zoom_long_route_sampled(ras, ood):
     """At 14.5 scene radii the 300k near-placed Gaussians (a 0.5-unit clump)
     land in a few tiles with lists of 10^5 entries: the long-list route.  In
     those tiles thousands of clump Gaussians share a pixel with depths inside
-    the FP32 tie band, so the oracle flags many pixels (up to 30% allowed
-    here); every unflagged pixel must meet 2e-4."""
+    the FP32 tie band, so the oracle flags many pixels; they must match the
+    oracle or one of its alternative outcomes.  The four longest lists and 12
+    other tiles with pairs are compared."""
     scene, _, zoom = ood
     cam = zoom[4]
     from test_gpu_forward import dev
@@ -80,26 +85,24 @@ def test_ood_3m_far_zoom_long_route_sampled(ras, ood):
     print("longest lists", np.sort(ln)[-4:].tolist())
     assert ln.max() > 4096
     sel = np.zeros(ln.size, np.uint8)
-    sel[np.argsort(-ln)[:4]] = 1
-    compare_image(ras, scene, cam, S.Settings(), tile_sel=sel, label="3M far zoom", max_flagged=0.30)
+    order = np.argsort(-ln)
+    sel[order[:4]] = 1
+    rest = order[4:][ln[order[4:]] > 0]
+    sel[np.random.default_rng(3).choice(rest, min(12, len(rest)), replace=False)] = 1
+    compare_image(ras, scene, cam, S.Settings(), tile_sel=sel, label="3M far zoom")
 
 
 def test_720p_16_view_batch_sampled(ras):
-    from test_gpu_forward import dev
+    from test_gpu_forward import dev, check_image
     scene, cams = S.fwd_bwd_scene()
     st = S.Settings()
     rgbs, Ts, _ = ras.render_batch(dev(scene), cams, st)
     for v in (0, 15):
         cam = cams[v]
-        sel = _sample(cam, 6, 10 + v)
-        tx, ty = cam.tiles
+        sel = _sample(cam, 16, 10 + v)
         ref = O.render(scene, cam, st, tile_sel=sel)
-        pixsel = np.kron(sel.reshape(ty, tx).astype(bool), np.ones((16, 16), bool))[: cam.height, : cam.width]
-        mask = (ref.flags == 0) & pixsel
-        err = np.abs(rgbs[v].cpu().numpy().astype(np.float64) - ref.rgb)[:, mask]
-        print(f"[720p view {v}] flagged={int(pixsel.sum() - mask.sum())} max|drgb|={err.max():.3e}")
-        assert err.max() <= 2e-4
-        assert pixsel.sum() - mask.sum() <= max(8, 0.02 * pixsel.sum())
+        alts = lambda px: O.render_alternatives(scene, cam, st, px, tile_sel=sel)
+        check_image(rgbs[v], Ts[v], ref, cam, sel, f"720p view {v}", None, alts)
 
 
 def test_720p_batched_backward_sampled(ras):
