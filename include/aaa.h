@@ -206,6 +206,24 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
                               void *stream, const float *const *out_rgb, const float *const *dL_drgb,
                               void *scratch, size_t scratch_bytes, aaa_scene_grad *grad);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): aaa_render_backward
+ * without the caller's `scratch`.  The per-contributor slots live in a static
+ * device array of AAA_STATIC_SLOT_BYTES (64 MiB) per device, held from the
+ * library's first use on that device until the process ends; the call
+ * allocates nothing.  A frame whose slots exceed it (8 bytes x 64 per
+ * contributor of each 8x8 quadrant's busiest pixel: about 128x128 pixels with
+ * tens of contributors per pixel fit) returns AAA_ERR_WORKSPACE and computes
+ * nothing.  The slots need no clearing (each one read is written first in the
+ * same call).  All calls on one device share the array: within a process the
+ * library runs them one at a time (the call returns after synchronising
+ * `stream`); anything else that used the array concurrently would race.
+ * Arguments, results and errors otherwise as aaa_render_backward. */
+#define AAA_STATIC_SLOT_BYTES (64ull << 20)
+int aaa_render_backward_noalloc(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam,
+                                const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                                void *stream, const float *out_rgb, const float *dL_drgb, aaa_scene_grad *grad);
+
 /* Accumulated stage times (milliseconds, HIP events on the render stream) of
  * every aaa_render with AAA_TIMING since the last reset, and the number of
  * such frames.  Waits for the last timed frame to finish.  ms [AAA_NUM_STAGES]

@@ -16,6 +16,7 @@ AAA_OK, AAA_ERR_INVALID, AAA_ERR_WORKSPACE, AAA_ERR_PAIR_OVERFLOW, AAA_ERR_HIP, 
 AAA_FILTER_OFF, AAA_FILTER_VOLUME, AAA_NO_TILE_CULL, AAA_STATS, AAA_TIMING, AAA_LONG_ALL = 1, 2, 4, 8, 16, 32
 AAA_WIDE_RANKS = 64
 AAA_MAX_TRAIN_CAMERAS = 4096
+AAA_STATIC_SLOT_BYTES = 64 << 20
 STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "frame"]
 
 # Every symbol include/aaa.h declares (checked by the ABI test).
@@ -23,7 +24,8 @@ EXPORTS = [
     "aaa_create", "aaa_destroy", "aaa_last_error", "aaa_version", "aaa_workspace_size", "aaa_render",
     "aaa_stage_times", "aaa_workspace_size_batch", "aaa_render_batch", "aaa_render_backward_batch",
     "aaa_backward_scratch_size", "aaa_training_frequency", "aaa_adam_step",
-    "aaa_render_backward", "aaa_read_gaussians", "aaa_read_pairs", "aaa_sort_tmp_size", "aaa_sort_pairs",
+    "aaa_render_backward", "aaa_render_backward_noalloc", "aaa_read_gaussians", "aaa_read_pairs",
+    "aaa_sort_tmp_size", "aaa_sort_pairs",
 ]
 
 
@@ -84,6 +86,8 @@ def lib():
                                  vp, vp, vp, C.POINTER(Stats)]
         L.aaa_render_backward.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp, C.c_size_t,
                                           u64, vp, vp, vp, vp, C.c_size_t, C.POINTER(SceneGrad)]
+        L.aaa_render_backward_noalloc.argtypes = [vp, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Settings), vp,
+                                                  C.c_size_t, u64, vp, vp, vp, C.POINTER(SceneGrad)]
         L.aaa_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
                                     C.c_double, vp]
         L.aaa_training_frequency.argtypes = [vp, vp, C.c_int64, C.POINTER(Camera), C.c_int, vp, vp]

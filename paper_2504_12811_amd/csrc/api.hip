@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -267,6 +268,39 @@ void set_value_bits(aaa::BlendArgs &ba, bool quads)
 
 }  // namespace
 
+// Backward slots of aaa_render_backward_noalloc: one array per device, held
+// until the process ends.  In host code `scratch` names a host-side stand-in,
+// not device memory: kernels, copies and fills take the address that
+// hipGetSymbolAddress returns for the current device (slot_array_address).
+constexpr size_t kStaticSlotBytes = AAA_STATIC_SLOT_BYTES;
+static_assert(kStaticSlotBytes == ((size_t)64 << 20), "slot array size");
+static __device__ __align__(256) unsigned char scratch[kStaticSlotBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_slot_addr_mu;
+void *g_slot_addr[kMaxDevices];
+// calls of the allocation-free backward on one device run one at a time
+std::mutex g_slot_mu[kMaxDevices];
+
+// Device address of the static slot array on `device` (which is current),
+// looked up once per device.
+hipError_t slot_array_address(int device, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_slot_addr_mu);
+    if (!g_slot_addr[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_slot_addr[device] = p;
+    }
+    *out = g_slot_addr[device];
+    return hipSuccess;
+}
+
+}  // namespace
+
 struct aaa_ctx {
     int device;
     // pinned staging for the view table (copied to the workspace per call)
@@ -279,6 +313,8 @@ struct aaa_ctx {
     // the caller's stream with these events
     hipStream_t side;
     hipEvent_t fork, join;
+    // this device's static slot array (aaa_render_backward_noalloc)
+    void *slots_static;
     // AAA_TIMING: two sets of stage events (frame i uses set i % 2); a set is
     // folded into the totals once a later frame has synchronised past it.
     static constexpr int kEvents = 9;
@@ -320,8 +356,12 @@ int aaa_create(aaa_ctx **out, int device)
     int count = 0;
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(AAA_ERR_INVALID, "device %d of %d", device, count);
+    if (device >= kMaxDevices) return fail(AAA_ERR_INVALID, "device %d: at most %d devices", device, kMaxDevices);
     HIP_TRY(hipSetDevice(device));
+    void *slots = nullptr;
+    HIP_TRY(slot_array_address(device, &slots));
     aaa_ctx *c = new aaa_ctx;
+    c->slots_static = slots;
     c->device = device;
     c->views_host = nullptr;
     c->train_host = nullptr;
@@ -628,10 +668,13 @@ int aaa_backward_scratch_size(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     return AAA_OK;
 }
 
-int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
-                              const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
-                              void *stream, const float *const *out_rgb, const float *const *dL_drgb,
-                              void *scratch, size_t scratch_bytes, aaa_scene_grad *grad)
+// Backward of the last render into `ws`.  `scratch` holds the per-contributor
+// slots; with `fixed` it is the context's device's static slot array, whose
+// size is checked here instead of being the caller's.
+static int backward_run(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                        const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs, void *stream,
+                        const float *const *out_rgb, const float *const *dL_drgb, void *scratch, size_t scratch_bytes,
+                        bool fixed, aaa_scene_grad *grad)
 {
     if (!ctx) return fail(AAA_ERR_INVALID, "null context");
     int rc = check_common(scene, n_views, cams, settings);
@@ -650,6 +693,11 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     bool rank16 = false;
     rc = backward_slots(ctx, sh, L, ws, s, &total, &rank16);
     if (rc) return rc;
+    if (fixed && total * sizeof(float2) > scratch_bytes)
+        return fail(AAA_ERR_WORKSPACE,
+                    "this frame needs %zu bytes of backward slots; the static slot array holds %zu "
+                    "(use aaa_render_backward with caller scratch)",
+                    (size_t)(total * sizeof(float2)), scratch_bytes);
     if (total > 0 && (!scratch || scratch_bytes < total * sizeof(float2)))
         return fail(AAA_ERR_WORKSPACE, "backward scratch %zu < %zu bytes (aaa_backward_scratch_size)", scratch_bytes,
                     (size_t)(total * sizeof(float2)));
@@ -698,6 +746,26 @@ int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views,
     // the pinned view table is reused by the next call on this context
     HIP_TRY(hipStreamSynchronize(s));
     return AAA_OK;
+}
+
+int aaa_render_backward_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aaa_camera *cams,
+                              const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                              void *stream, const float *const *out_rgb, const float *const *dL_drgb,
+                              void *scratch, size_t scratch_bytes, aaa_scene_grad *grad)
+{
+    return backward_run(ctx, scene, n_views, cams, settings, ws, ws_bytes, max_pairs, stream, out_rgb, dL_drgb,
+                        scratch, scratch_bytes, false, grad);
+}
+
+int aaa_render_backward_noalloc(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam,
+                                const aaa_settings *settings, void *ws, size_t ws_bytes, uint64_t max_pairs,
+                                void *stream, const float *out_rgb, const float *dL_drgb, aaa_scene_grad *grad)
+{
+    if (!ctx) return fail(AAA_ERR_INVALID, "null context");
+    // one call at a time per device: every call on a device shares its array
+    std::lock_guard<std::mutex> lock(g_slot_mu[ctx->device]);
+    return backward_run(ctx, scene, 1, cam, settings, ws, ws_bytes, max_pairs, stream, &out_rgb, &dL_drgb,
+                        ctx->slots_static, kStaticSlotBytes, true, grad);
 }
 
 int aaa_render_backward(aaa_ctx *ctx, const aaa_scene *scene, const aaa_camera *cam, const aaa_settings *settings,
