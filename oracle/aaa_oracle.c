@@ -67,6 +67,10 @@ typedef struct {
     double alpha_min, alpha_max, t_min;
     /* relative bands inside which an FP32 decision may legitimately differ */
     double band_alpha, band_z, band_tie, band_T;
+    /* 1: the middle level of the hierarchical sort, an exact re-sort of each
+     * 8x8 sub-tile's entries by the depth on the sub-tile-centre line */
+    int32_t subtile_sort;
+    int32_t pad_;
 } or_settings;
 
 enum { OR_VISIBLE = 0, OR_INVALID = 1, OR_LOW_OPACITY = 2, OR_CAM_INSIDE = 3, OR_OUTSIDE = 4 };
@@ -781,20 +785,30 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                     s2 = (or_contrib *)realloc(s2, sizeof(or_contrib) * (cap + 1));
                     s3 = (or_contrib *)realloc(s3, sizeof(or_contrib) * (cap + 1));
                 }
-                dt = (double *)realloc(dt, sizeof(double) * cap);
+                dt = (double *)realloc(dt, sizeof(double) * 4 * cap);
                 zi = (int64_t *)realloc(zi, sizeof(int64_t) * cap);
                 ridx = (int64_t *)realloc(ridx, sizeof(int64_t) * cap);
             }
-            /* O9: tile depth = depth of maximum response on the tile-centre line */
-            for (int64_t j = 0; j < m; ++j) {
-                double r2, z;
-                or_response(&gs[lists[b + j]], cam, tx * OR_TILE + 0.5 * OR_TILE, ty * OR_TILE + 0.5 * OR_TILE, &r2, &z);
-                dt[j] = z;
+            /* O9: tile depth = depth of maximum response on the tile-centre
+             * line; with the sub-tile level, one depth per 8x8 sub-tile on
+             * the line through its centre (dt[q * m + j], q = 2 qy + qx) */
+            for (int q = 0; q < (st->subtile_sort ? 4 : 1); ++q) {
+                const double cx = st->subtile_sort ? tx * OR_TILE + (q & 1) * 8 + 4.0 : tx * OR_TILE + 0.5 * OR_TILE;
+                const double cy = st->subtile_sort ? ty * OR_TILE + (q >> 1) * 8 + 4.0 : ty * OR_TILE + 0.5 * OR_TILE;
+                for (int64_t j = 0; j < m; ++j) {
+                    double r2, z;
+                    or_response(&gs[lists[b + j]], cam, cx, cy, &r2, &z);
+                    dt[q * m + j] = z;
+                }
             }
             for (int py = ty * OR_TILE; py < ty * OR_TILE + OR_TILE && py < H; ++py)
                 for (int px = tx * OR_TILE; px < tx * OR_TILE + OR_TILE && px < W; ++px) {
                     or_pixel_state ps = pixel_state_init(-1);
                     int nnear = 0, nties = 0;
+                    /* this pixel's row of ordering depths: its sub-tile's, or the tile's */
+                    const double *dq = st->subtile_sort
+                                           ? dt + (int64_t)(2 * ((py - ty * OR_TILE) >= 8) + ((px - tx * OR_TILE) >= 8)) * m
+                                           : dt;
                     int64_t ns = 0;
                     double x = px + 0.5, y = py + 0.5; /* pixel centre */
                     for (int64_t j = 0; j < m; ++j) {
@@ -821,7 +835,7 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                         }
                         if (near_member && alt_slot && nnear < OR_MAX_ALT) {
                             or_contrib *q = &nr[nnear].e;
-                            q->dtile = dt[j];
+                            q->dtile = dq[j];
                             q->id = lists[b + j];
                             q->z = z;
                             q->a = a;
@@ -834,7 +848,7 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                         }
                         if (g->status != OR_VISIBLE) continue;
                         if (contrib) {
-                            seq[ns].dtile = dt[j];
+                            seq[ns].dtile = dq[j];
                             seq[ns].id = lists[b + j];
                             seq[ns].z = z;
                             seq[ns].a = a;
@@ -845,7 +859,7 @@ static int render_impl(const or_scene *sc, const or_camera *cam, const or_settin
                             ns++;
                         }
                     }
-                    /* O10: order by (tile depth, id) */
+                    /* O10: order by (tile depth, id), or (sub-tile depth, id) */
                     qsort(seq, ns, sizeof(or_contrib), cmp_tile_order);
                     window_blend(seq, ns, K, &ps, st, win);
                     /* Near-ties in either ordering key whose swap would move the

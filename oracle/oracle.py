@@ -57,7 +57,8 @@ class _Camera(C.Structure):
 class _Settings(C.Structure):
     _fields_ = [("filter_k", C.c_double), ("ray_window", C.c_int32), ("filter_mode", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
-                ("band_alpha", C.c_double), ("band_z", C.c_double), ("band_tie", C.c_double), ("band_T", C.c_double)]
+                ("band_alpha", C.c_double), ("band_z", C.c_double), ("band_tie", C.c_double), ("band_T", C.c_double),
+                ("subtile_sort", C.c_int32), ("_pad", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -112,6 +113,7 @@ def _settings(st) -> _Settings:
     s.filter_mode = int(st.filter_mode)
     s.alpha_min, s.alpha_max, s.t_min = float(st.alpha_min), float(st.alpha_max), float(st.t_min)
     s.band_alpha, s.band_z, s.band_tie, s.band_T = BAND_ALPHA, BAND_Z, BAND_TIE, BAND_T
+    s.subtile_sort = int(bool(getattr(st, "subtile_sort", False)))
     return s
 
 

@@ -107,6 +107,7 @@ class Settings:
     t_min: float = 1e-4
     filter_mode: int = 0           # 0 adaptive (Eq.12), 1 off, 2 volume-normalised (Eq.8)
     tile_cull: bool = True         # 3D per-tile culling (Sec. 3.4); False = rectangle only
+    subtile_sort: bool = False     # middle level: exact re-sort per 8x8 sub-tile by its centre-line depth
 
 
 def look_at(position, target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0)) -> np.ndarray:

@@ -389,3 +389,50 @@ def test_alternative_of_a_membership_test_in_band_drops_the_entry():
     assert alts.shape == (1, 4)
     np.testing.assert_allclose(alts[0, :3], Cs, atol=1e-9)
     assert alts[0, 3] == pytest.approx(Ts, abs=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# the middle level: sub-tile key (depth on the 8x8 sub-tile-centre line)
+
+
+def test_subtile_key_is_the_subtile_centre_depth():
+    """Three sheets P (flat), Q and R on a 16x16 image (one tile, four 8x8
+    sub-tiles).  On the tile-centre line (x = 8) the depths are P < Q < R, on
+    the left sub-tiles' centre line (x = 4) R < P < Q, on the right ones'
+    (x = 12) Q < P < R.  With the window off (K = 0) every pixel of the tile
+    blends P Q R at the tile level alone, and with the sub-tile level every
+    pixel of a left sub-tile blends R P Q and of a right one Q P R, also
+    where the pixel's own depth order differs; a window holding every
+    contributor restores the pixel's own order either way."""
+    cam = identity_camera(16, 16, 8.0, bg=(0.0, 0.0, 0.0))
+    names = "PQR"
+    colours = [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0)]
+    sc = sheets([2.0, 2.05, 2.1], [0.0, 0.2, -0.3], colours, big=6.0)
+
+    def order(x, y):
+        z = [closed_form(sc, cam, i, x, y)[0] for i in range(3)]
+        return "".join(names[i] for i in np.argsort(z))
+
+    assert order(8.0, 8.0) == "PQR"
+    assert order(4.0, 4.0) == "RPQ" and order(4.0, 12.0) == "RPQ"
+    assert order(12.0, 4.0) == "QPR" and order(12.0, 12.0) == "QPR"
+    col = {names[i]: colours[i] for i in range(3)}
+    tile0 = O.render(sc, cam, S.Settings(ray_window=0, **OFF))
+    sub0 = O.render(sc, cam, S.Settings(ray_window=0, subtile_sort=True, **OFF))
+    subK = O.render(sc, cam, S.Settings(ray_window=16, subtile_sort=True, **OFF))
+    checked = 0
+    for (px, py, sub_seq) in [(1, 2, "RPQ"), (6, 13, "RPQ"), (7, 7, "RPQ"), (8, 8, "QPR"), (10, 1, "QPR"),
+                              (15, 14, "QPR")]:
+        x, y = px + 0.5, py + 0.5
+        al = {names[i]: closed_form(sc, cam, i, x, y)[1] for i in range(3)}
+        assert min(al.values()) > 0.2
+        C_tile, _ = blend("PQR", al, col, cam.bg)
+        C_sub, _ = blend(sub_seq, al, col, cam.bg)
+        C_own, _ = blend(order(x, y), al, col, cam.bg)
+        np.testing.assert_allclose(tile0.rgb[:, py, px], C_tile, atol=1e-9, err_msg=f"tile level ({px},{py})")
+        np.testing.assert_allclose(sub0.rgb[:, py, px], C_sub, atol=1e-9, err_msg=f"sub-tile level ({px},{py})")
+        np.testing.assert_allclose(subK.rgb[:, py, px], C_own, atol=1e-9, err_msg=f"window ({px},{py})")
+        if order(x, y) != sub_seq:
+            checked += 1
+        assert np.abs(C_sub - C_tile).max() > 1e-2
+    assert checked >= 2  # pixels whose own order differs from their sub-tile's
