@@ -97,6 +97,14 @@ typedef struct {
 #define AAA_TIMING 16u         /* time each stage with HIP events on `stream` (see aaa_stage_times) */
 #define AAA_LONG_ALL 32u       /* diagnostic: every tile takes the long-list blend path (same results) */
 #define AAA_WIDE_RANKS 64u     /* diagnostic: the backward replay keeps 32-bit contributor ranks (same results) */
+/* The middle level of the hierarchical sort (Sec. 3.1, blending sort order;
+ * Sec. 4): every 8x8 sub-tile gets its own list, holding the Gaussians whose
+ * screen box reaches it (sub-tile culling), in the exact order of their depth
+ * of maximum response on the sub-tile-centre line (ties by index), before the
+ * per-ray window.  Without it the tile's list is ordered by the depth on the
+ * tile-centre line.  Keys carry the sub-tile number 4 tile + q (q = 2 qy +
+ * qx); the long-list route is not taken. */
+#define AAA_SUBTILE_SORT 128u
 
 /* Method settings.  filter_k: filter size k (0.3 in Sec. 4).  ray_window:
  * capacity K of the per-ray re-sort window (0 = blend in tile order; the
@@ -293,6 +301,18 @@ int aaa_training_frequency(aaa_ctx *ctx, const float *means, int64_t n, const aa
  * or eps <= 0. */
 int aaa_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, int64_t step, double lr, double beta1,
                   double beta2, double eps, void *stream);
+
+/* ---- machine rates (for roofline fractions) ----------------------------- */
+
+/* Measures, on `stream`, the device's FP32 fused multiply-add rate (non-packed;
+ * out[0], TFLOP/s at 2 flops per FMA), its v_exp_f32 rate (out[1], G/s) and
+ * its copy bandwidth (out[2], GB/s counting bytes read plus written, a copy
+ * between the two halves of `buf`), each the best of `reps` timed runs after
+ * one warm-up, with HIP events.  buf: DEVICE scratch of `bytes` (>= 1 MiB,
+ * 256-byte aligned; ~1 GiB gives a steady copy rate), overwritten.
+ * Synchronises `stream`.  Errors: AAA_ERR_INVALID for bad arguments,
+ * AAA_ERR_HIP. */
+int aaa_measure_peaks(void *buf, size_t bytes, int reps, void *stream, double *out);
 
 #ifdef __cplusplus
 }

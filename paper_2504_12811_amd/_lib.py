@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libaaa_hip.so")
 AAA_OK, AAA_ERR_INVALID, AAA_ERR_WORKSPACE, AAA_ERR_PAIR_OVERFLOW, AAA_ERR_HIP, AAA_ERR_UNSUPPORTED = range(6)
 AAA_FILTER_OFF, AAA_FILTER_VOLUME, AAA_NO_TILE_CULL, AAA_STATS, AAA_TIMING, AAA_LONG_ALL = 1, 2, 4, 8, 16, 32
 AAA_WIDE_RANKS = 64
+AAA_SUBTILE_SORT = 128
 AAA_MAX_TRAIN_CAMERAS = 4096
 AAA_STATIC_SLOT_BYTES = 64 << 20
 STAGES = ["preprocess", "count", "scan", "write", "sort", "ranges", "blend", "frame"]
@@ -25,7 +26,7 @@ EXPORTS = [
     "aaa_stage_times", "aaa_workspace_size_batch", "aaa_render_batch", "aaa_render_backward_batch",
     "aaa_backward_scratch_size", "aaa_training_frequency", "aaa_adam_step",
     "aaa_render_backward", "aaa_render_backward_noalloc", "aaa_read_gaussians", "aaa_read_pairs",
-    "aaa_sort_tmp_size", "aaa_sort_pairs",
+    "aaa_sort_tmp_size", "aaa_sort_pairs", "aaa_measure_peaks",
 ]
 
 
@@ -107,6 +108,7 @@ def lib():
         L.aaa_stage_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64), C.c_int]
         L.aaa_sort_tmp_size.argtypes = [u64, C.POINTER(C.c_size_t)]
         L.aaa_sort_pairs.argtypes = [vp, vp, u64, C.c_int, vp, C.c_size_t, vp]
+        L.aaa_measure_peaks.argtypes = [vp, C.c_size_t, C.c_int, vp, C.POINTER(C.c_double)]
         for f in EXPORTS:
             if f not in ("aaa_destroy", "aaa_last_error", "aaa_version"):
                 getattr(L, f).restype = C.c_int
@@ -142,6 +144,8 @@ def make_settings(st, extra_flags: int = 0) -> Settings:
         flags |= AAA_FILTER_VOLUME
     if not st.tile_cull:
         flags |= AAA_NO_TILE_CULL
+    if getattr(st, "subtile_sort", False):
+        flags |= AAA_SUBTILE_SORT
     s.flags = flags
     s.alpha_min, s.alpha_max, s.t_min = float(st.alpha_min), float(st.alpha_max), float(st.t_min)
     return s

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaaa_hip.so")
-SOURCES = ["api.hip", "preprocess.hip", "emit.hip", "sort.hip", "blend.hip", "backward.hip", "train_freq.hip", "adam.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "emit.hip", "sort.hip", "blend.hip", "backward.hip", "train_freq.hip", "adam.hip",
+           "peaks.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -255,16 +255,20 @@ hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams
 // number below 2^32.
 hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t keep_cap, uint32_t *chunk_item,
                               hipStream_t s);
+// subtile: count one pair per 8x8 sub-tile a kept test's box reaches (bbox)
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull,
                               unsigned long long *tests, uint64_t *keep_bits, uint32_t *chunk_cnt,
-                              const uint32_t *chunk_item, uint64_t keep_cap, hipStream_t s);
-// quads: pack the quadrant bits of each pair (from bbox) into its value
+                              const uint32_t *chunk_item, uint64_t keep_cap, const float4 *bbox, bool subtile,
+                              hipStream_t s);
+// quads: pack the quadrant bits of each pair (from bbox) into its value;
+// subtile: write one pair per reached sub-tile, keyed by sub-tile number and
+// sub-tile-centre depth (values carry no quadrant bits)
 hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, const uint64_t *keep_bits,
                               const uint32_t *chunk_item, const uint64_t *kept_before, uint64_t keep_cap,
                               uint64_t max_pairs, uint64_t *keys, uint32_t *vals, const float4 *bbox, bool quads,
-                              hipStream_t s);
+                              bool tile_cull, bool subtile, hipStream_t s);
 // host[0] = *a, host[1] = *b (host: pinned host memory), visible to the host
 // once the stream has synchronised: one launch instead of two small copies
 hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, hipStream_t s);
@@ -288,7 +292,8 @@ struct BlendArgs {
     const uint32_t *vals;
     uint32_t id_mask;              // Gaussian index bits of a value (kQuadIdMask when values carry quadrant bits)
     uint32_t quad_on;              // bits forced on before the quadrant test (~kQuadIdMask when they carry none)
-    const uint32_t *ranges;        // per global tile
+    const uint32_t *ranges;        // per global tile, or per 8x8 sub-tile (4 tile + quadrant) with quad_lists
+    bool quad_lists;               // every quadrant wave walks its own sub-tile's list
     const ViewDev *views;
     int nviews;
     int total_tiles;

@@ -116,7 +116,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.vals = take(mp * 4);
     L.vals_alt = take(mp * 4);
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
-    L.ranges = take((size_t)sh.total_tiles * 8);
+    L.ranges = take((size_t)sh.total_tiles * 4 * 8);  // per tile, or per 8x8 sub-tile with AAA_SUBTILE_SORT
     L.long_tiles = take((size_t)sh.total_tiles * 4);
     L.masks = take((mp / 64 + (uint64_t)sh.total_tiles + 2) * 256 * 8);  // per-pixel masks of long lists
     L.summary = take(summary_words(sh, mp) * 8);
@@ -259,6 +259,12 @@ bool quad_values(int64_t n, const aaa_settings *st)
 {
     return n < aaa::kQuadMaxGaussians && (st->flags & AAA_NO_TILE_CULL) == 0;
 }
+
+// The middle level of the hierarchical sort: one list per 8x8 sub-tile.
+bool subtile_lists(const aaa_settings *st) { return (st->flags & AAA_SUBTILE_SORT) != 0; }
+
+// Lists the sort keys number: tiles, or their 8x8 sub-tiles.
+int64_t list_count(int64_t ntiles, const aaa_settings *st) { return subtile_lists(st) ? 4 * ntiles : ntiles; }
 
 void set_value_bits(aaa::BlendArgs &ba, bool quads)
 {
@@ -514,8 +520,11 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *kept_before = at<uint64_t>(ws, L.kept_before);
     const uint64_t keep_cap = keep_cap_of(max_pairs), chunks = keep_cap / 64;
     HIP_TRY(aaa::launch_chunk_items(area_off, items, keep_cap, chunk_item, s));
+    const bool subtile = subtile_lists(settings);
+    const int64_t nlists = list_count(ntiles, settings);
     HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull,
-                                    want_stats ? ctr : nullptr, keep_bits, chunk_cnt, chunk_item, keep_cap, s));
+                                    want_stats ? ctr : nullptr, keep_bits, chunk_cnt, chunk_item, keep_cap, pa.bbox,
+                                    subtile, s));
     STAGE_MARK(2);
     // the chunks of this batch's C tests only (the host does not know C yet)
     HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s,
@@ -535,17 +544,18 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
     uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
     STAGE_MARK(4);
-    const bool quads = quad_values(n, settings);
+    const bool quads = quad_values(n, settings) && !subtile;
     HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, keep_bits,
-                                    chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads, s));
+                                    chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads,
+                                    tile_cull, subtile, s));
     STAGE_MARK(5);
     bool in_alt = false;
-    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(ntiles), at<void>(ws, L.sort_tmp), s,
+    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(nlists), at<void>(ws, L.sort_tmp), s,
                                   &in_alt));
-    if (P > 1 && in_alt != sorted_in_alt(ntiles)) return fail(AAA_ERR_HIP, "internal: sort parity");
+    if (P > 1 && in_alt != sorted_in_alt(nlists)) return fail(AAA_ERR_HIP, "internal: sort parity");
     const uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
     const uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
-    if (P <= 1 && sorted_in_alt(ntiles)) {
+    if (P <= 1 && sorted_in_alt(nlists)) {
         // keep the invariant "sorted pairs live where sorted_in_alt says"
         HIP_TRY(hipMemcpyAsync(keys_alt, keys, P * 8, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(vals_alt, vals, P * 4, hipMemcpyDeviceToDevice, s));
@@ -554,7 +564,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     }
     STAGE_MARK(6);
     uint32_t *ranges = at<uint32_t>(ws, L.ranges);
-    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)ntiles, s));
+    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s));
     STAGE_MARK(7);
 
     aaa::BlendArgs ba;
@@ -562,6 +572,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.vals = svals;
     set_value_bits(ba, quads);
     ba.ranges = ranges;
+    ba.quad_lists = subtile;
     ba.views = pa.views;
     ba.nviews = n_views;
     ba.total_tiles = (int)ntiles;
@@ -577,7 +588,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.rank16 = false;
     const int K = settings->ray_window;
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
-    ba.long_list = K > 16 ? 0xffffffffu : (long_all ? 0u : aaa::kLongList);
+    // the long-list route walks whole tiles: not with sub-tile lists
+    ba.long_list = (K > 16 || subtile) ? 0xffffffffu : (long_all ? 0u : aaa::kLongList);
     uint32_t *n_long = (uint32_t *)(ctr + 8);  // zeroed with the counters
     ba.n_long = n_long;
     if (ba.long_list != 0xffffffffu && P > ba.long_list) {
@@ -709,12 +721,14 @@ static int backward_run(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
-    const bool alt = sorted_in_alt(ntiles);
+    const bool subtile = subtile_lists(settings);
+    const bool alt = sorted_in_alt(list_count(ntiles, settings));
     aaa::BlendArgs ba;
     ba.rec = pa.rec;
     ba.vals = at<uint32_t>(ws, alt ? L.vals_alt : L.vals);
-    set_value_bits(ba, quad_values(n, settings));
+    set_value_bits(ba, quad_values(n, settings) && !subtile);
     ba.ranges = at<uint32_t>(ws, L.ranges);
+    ba.quad_lists = subtile;
     ba.views = pa.views;
     ba.nviews = n_views;
     ba.total_tiles = (int)ntiles;

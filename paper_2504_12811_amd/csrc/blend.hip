@@ -182,27 +182,38 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
     const bool inside = px < vw.cam.width && py < vw.cam.height;
     const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    // wave-uniform (readfirstlane): the list walk stays on scalar loads
+    const int list = __builtin_amdgcn_readfirstlane(a.quad_lists ? 4 * tile + wave : tile);
+    const uint32_t start = a.ranges[2 * list], end = a.ranges[2 * list + 1];
     // k_blend_long renders long lists when they are few (see k_find_long)
     if (!PASS1 && end - start > a.long_list && *a.n_long <= kMaxLongTiles) return;
     const size_t hw = (size_t)vw.cam.width * vw.cam.height;
     const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
     const size_t gpix = vw.pix_base + pix;
 
-    // Per-ray window: depths and slot numbers in registers, kept sorted by
-    // depth; each slot's payload (item, alpha and, in pass 1, the
-    // contributor rank) sits in LDS at [wave][slot][lane] and never moves.
-    // A popped entry's slot takes the entry inserted in its place, so only
-    // two registers per position take part in the sorting network.
+    // Per-ray window, kept sorted by depth in registers; each entry's payload
+    // (item, alpha and, in pass 1, the contributor rank) sits in LDS at
+    // [wave][slot][lane] and never moves: a popped entry's slot takes the
+    // entry inserted in its place.
+    //  - K <= 16: one 32-bit key per entry, the depth's offset above znear in
+    //    float ulps (order-preserving for positive floats; contributors have
+    //    depth >= znear) in the high 28 bits and the slot in the low 4, so
+    //    the whole insertion is one v_med3_u32 per position.  Depths are
+    //    ordered exactly up to 2^32 znear; farther ones compare equal (and
+    //    then order by slot, as exactly equal depths do).
+    //  - K = 32: depths and slot numbers in two registers per position.
     constexpr int KS = K > 0 ? K : 1;
+    constexpr bool kKeyed = K > 0 && K <= 16;
     __shared__ uint2 pay[K > 0 ? WPB : 1][KS][64];
     __shared__ RankT pay_rank[PASS1 && K > 0 ? WPB : 1][PASS1 ? KS : 1][64];
     float wz[KS];
     uint32_t ws[KS];
+    uint32_t wk[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         wz[k] = -INFINITY;  // fillers: popped first, with alpha 0
         ws[k] = (uint32_t)k;
+        wk[k] = (uint32_t)k;  // filler keys: depth offset 0, slot k
         if constexpr (K > 0) pay[wl][k][lane] = make_uint2(0u, 0u);
     }
     PixelState ps;
@@ -225,6 +236,7 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
     uint32_t n_eval = 0, n_near = 0;
     uint32_t w_steps = 0, w_near = 0, w_contrib = 0;  // wave-uniform
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
+    const uint32_t zbits = __float_as_uint(znear);
 
     for (uint32_t i = start; i < end; ++i) {
         if (__builtin_amdgcn_ballot_w64(!ps.done) == 0ull) break;
@@ -257,31 +269,48 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
         if constexpr (K == 0) {
             blend_entry<PASS1>(ps, rec, id, c_new, my_rank, contrib ? al : 0.0f, tmin, bp, cap);
         } else {
-            // Non-contributing lanes insert a NaN depth: every comparison is
-            // false, the window stays as it is and the popped entry is the
-            // NaN one with alpha 0 (a no-op blend).
-            const float zk = contrib ? z : __builtin_nanf("");
             const float ak = contrib ? al : 0.0f;
-            // pop min(new, front); insert new behind equal depths, into the
-            // slot the front leaves
-            const uint32_t fs = ws[0];
+            // pop min(new, front); insert the new entry behind equal depths,
+            // into the slot the front leaves
+            uint32_t fs;
+            bool front_out;
+            uint32_t key = 0u;
+            float zk = 0.0f;
+            if constexpr (kKeyed) {
+                // a non-contributing lane inserts key 0: below every key, so
+                // the window stays as it is (at most a filler pops, a no-op)
+                fs = wk[0] & 15u;
+                const uint32_t doff = min(__float_as_uint(z) - zbits + 1u, (1u << 28) - 1u);
+                key = contrib ? (doff << 4) | fs : 0u;
+                front_out = wk[0] <= key;
+            } else {
+                // a non-contributing lane inserts a NaN depth: every
+                // comparison is false and the window stays as it is
+                zk = contrib ? z : __builtin_nanf("");
+                fs = ws[0];
+                front_out = wz[0] <= zk;
+            }
             const uint2 fp = pay[wl][fs][lane];
             const uint32_t frk = PASS1 ? pay_rank[wl][fs][lane] : 0u;
-            const bool front_out = wz[0] <= zk;
-            // forward: gather the popped entry's colour before the sorting
-            // network, so that its latency overlaps the network (the register
-            // starts as the new entry's colour, which pops when the front
-            // stays; the compiler then issues one load for both cases)
+            // forward: gather the popped entry's colour before the window
+            // update, so that its latency overlaps it (the register starts as
+            // the new entry's colour, which pops when the front stays; the
+            // compiler then issues one load for both cases)
             float4 fc = make_float4(c_new.x, c_new.y, c_new.z, 0.0f);
             if (!PASS1 && front_out) fc = rec[(size_t)fp.x * kRecQuads + 7];
-            // For a sorted window the new k-th depth is the median of the old
-            // k-th, zk and the old (k+1)-th: one v_med3_f32 instead of two
-            // selects.  With zk a quiet NaN, med3 returns the minimum of the
-            // other two (the old k-th) and every comparison is false, so a
-            // non-inserting lane moves neither depths nor slots.  (Kept
-            // written out here: as a shared helper the compiler stopped
-            // updating the window registers in place.)
-            {
+            if constexpr (kKeyed) {
+                // For a sorted window the new k-th key is the median of the
+                // old k-th, the new key and the old (k+1)-th; the last is the
+                // larger of the old last and the new key.  (Written in place,
+                // so that the compiler keeps the window registers where they
+                // are.)
+#pragma unroll
+                for (int k = 0; k + 1 < K; ++k)
+                    asm("v_med3_u32 %0, %0, %1, %2" : "+v"(wk[k]) : "v"(key), "v"(wk[k + 1]));
+                wk[K - 1] = max(wk[K - 1], key);
+            } else {
+                // the same median rule for the depths; the slots follow with
+                // two selects per position
                 bool gcur = front_out;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -310,8 +339,9 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
     if constexpr (K > 0) {
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            const uint2 q = pay[wl][ws[k]][lane];
-            const uint32_t rk = PASS1 ? pay_rank[wl][ws[k]][lane] : 0u;
+            const uint32_t sk = kKeyed ? (wk[k] & 15u) : ws[k];
+            const uint2 q = pay[wl][sk][lane];
+            const uint32_t rk = PASS1 ? pay_rank[wl][sk][lane] : 0u;
             const float3 c = PASS1 ? make_float3(0.0f, 0.0f, 0.0f) : float3_of(rec[(size_t)q.x * kRecQuads + 7]);
             blend_entry<PASS1>(ps, rec, q.x, c, rk, __uint_as_float(q.y), tmin, bp, cap);
         }
@@ -722,7 +752,9 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
     const bool inside = px < vw.cam.width && py < vw.cam.height;
     const float fxp = (float)px + 0.5f, fyp = (float)py + 0.5f;
-    const uint32_t start = a.ranges[2 * tile], end = a.ranges[2 * tile + 1];
+    // wave-uniform (readfirstlane): the list walk stays on scalar loads
+    const int list = __builtin_amdgcn_readfirstlane(a.quad_lists ? 4 * tile + wave : tile);
+    const uint32_t start = a.ranges[2 * list], end = a.ranges[2 * list + 1];
     const size_t hw = (size_t)vw.cam.width * vw.cam.height;
     const size_t pix = inside ? (size_t)py * vw.cam.width + px : 0;
     const size_t gpix = vw.pix_base + pix;

@@ -43,6 +43,19 @@ __device__ __forceinline__ float tile_depth(const TileGeom<float> &g, int tx, in
     return l / dot3(r, r);
 }
 
+// depth of the maximum on the line through the centre of 8x8 sub-tile q
+// (bit 2 qy + qx) of tile (tx, ty)
+__device__ __forceinline__ float subtile_depth(const TileGeom<float> &g, int tx, int ty, int q)
+{
+    float dX = (float)(tx * kTile + (q & 1) * 8 + 4) - g.xa;
+    float dY = (float)(ty * kTile + (q >> 1) * 8 + 4) - g.ya;
+    float r[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r[k] = g.c0[k] + dX * g.c1[k] + dY * g.c2[k];
+    float l = g.l[0] + dX * g.l[1] + dY * g.l[2];
+    return l / dot3(r, r);
+}
+
 // Quadrants (bit 2 qy + qx) of tile (tx, ty) whose 8x8 pixel square meets
 // the bounding box; pixel centres lie half a pixel inside the square.
 __device__ __forceinline__ uint32_t quad_bits(float4 box, int tx, int ty)
@@ -58,6 +71,18 @@ __device__ __forceinline__ uint32_t quad_bits(float4 box, int tx, int ty)
 }
 
 __device__ __forceinline__ uint64_t bits_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// exclusive prefix sum over the lanes of the wave
+__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v)
+{
+    const int lane = (int)__lane_id();
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    return x - v;
+}
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
 {
@@ -76,6 +101,13 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
 // follow test order (item, then tile within the rectangle), with no atomics.
 // Both passes do nothing when the batch has more than keep_cap tests (the
 // host reports that as a pair overflow, asking for a larger pair buffer).
+//
+// With `subtile` (the middle level of the hierarchical sort) a kept test
+// emits one pair per 8x8 sub-tile of its tile that the item's bounding box
+// reaches (all four in the ablation without tile culling), keyed by the
+// sub-tile number 4 tile + q and the depth on the sub-tile-centre line, so
+// that the global sort leaves every sub-tile an exact depth-ordered list of
+// its own; the counts and slots then count pairs, not tests.
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, const float4 *__restrict__ recs,
                                                const float4 *__restrict__ culls, const uint64_t *__restrict__ area_off,
@@ -85,7 +117,8 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                                                const uint32_t *__restrict__ chunk_item,
                                                const uint64_t *__restrict__ kept_before, uint64_t keep_cap,
                                                uint64_t max_pairs, uint64_t *__restrict__ keys,
-                                               uint32_t *__restrict__ vals, const float4 *__restrict__ bbox, bool quads)
+                                               uint32_t *__restrict__ vals, const float4 *__restrict__ bbox, bool quads,
+                                               bool subtile)
 {
     const uint64_t C = area_off[nitems];  // candidate tests of the whole batch
     if (C > keep_cap) return;
@@ -137,12 +170,35 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
             const float tau = recs[(size_t)g * kRecQuads + 6].y;
             const bool keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
             const uint64_t kall = __ballot(keep);
+            uint32_t cnt = (uint32_t)__popcll(kall);
+            if (subtile) {
+                const uint32_t qb = keep ? (tile_cull ? quad_bits(bbox[g], tx, ty) : 15u) : 0u;
+                cnt = __popc(qb) + wave_exclusive_sum(__popc(qb));
+                cnt = (uint32_t)__shfl((int)cnt, 63);  // the wave's total
+            }
             if (lane == 0) {
                 keep_bits[c] = kall;
-                chunk_cnt[c] = (uint32_t)__popcll(kall);
+                chunk_cnt[c] = cnt;
             }
             n_tests += valid ? 1 : 0;
             n_first += (valid && j == 0) ? 1 : 0;
+        } else if (subtile) {
+            const uint64_t kall = keep_bits[c];
+            const bool kept = valid && ((kall >> lane) & 1ull);
+            const uint32_t qb = kept ? (tile_cull ? quad_bits(bbox[g], tx, ty) : 15u) : 0u;
+            uint64_t slot = kept_before[c] + wave_exclusive_sum(__popc(qb));
+            if (kept) {
+                load_line_geom(recs + (size_t)g * kRecQuads, geo);
+                const uint32_t tile = (uint32_t)(vw.tile_base + ty * vw.cam.tiles_x + tx);
+                for (int q = 0; q < 4; ++q) {
+                    if (!((qb >> q) & 1u)) continue;
+                    if (slot < max_pairs) {
+                        keys[slot] = ((uint64_t)(4 * tile + q) << 32) | order_key(subtile_depth(geo, tx, ty, q));
+                        vals[slot] = (uint32_t)(g / nviews);
+                    }
+                    ++slot;
+                }
+            }
         } else {
             const uint64_t kall = keep_bits[c];
             if (valid && ((kall >> lane) & 1ull)) {
@@ -304,12 +360,13 @@ hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t 
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull,
                               unsigned long long *tests, uint64_t *keep_bits, uint32_t *chunk_cnt,
-                              const uint32_t *chunk_item, uint64_t keep_cap, hipStream_t s)
+                              const uint32_t *chunk_item, uint64_t keep_cap, const float4 *bbox, bool subtile,
+                              hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
                        nviews, tile_cull, tests, keep_bits, chunk_cnt, chunk_item, (const uint64_t *)nullptr, keep_cap,
-                       (uint64_t)0, (uint64_t *)nullptr, (uint32_t *)nullptr, (const float4 *)nullptr, false);
+                       (uint64_t)0, (uint64_t *)nullptr, (uint32_t *)nullptr, bbox, false, subtile);
     return hipGetLastError();
 }
 
@@ -317,12 +374,13 @@ hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 
                               int64_t items, const ViewDev *views, int nviews, const uint64_t *keep_bits,
                               const uint32_t *chunk_item, const uint64_t *kept_before, uint64_t keep_cap,
                               uint64_t max_pairs, uint64_t *keys, uint32_t *vals, const float4 *bbox, bool quads,
-                              hipStream_t s)
+                              bool tile_cull, bool subtile, hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pairs<true>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
-                       nviews, true, (unsigned long long *)nullptr, const_cast<uint64_t *>(keep_bits),
-                       (uint32_t *)nullptr, chunk_item, kept_before, keep_cap, max_pairs, keys, vals, bbox, quads);
+                       nviews, tile_cull, (unsigned long long *)nullptr, const_cast<uint64_t *>(keep_bits),
+                       (uint32_t *)nullptr, chunk_item, kept_before, keep_cap, max_pairs, keys, vals, bbox, quads,
+                       subtile);
     return hipGetLastError();
 }
 
