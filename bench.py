@@ -91,7 +91,7 @@ def blend_traffic_bytes():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=96)
+    ap.add_argument("--steps", type=int, default=128)
     ap.add_argument("--warmup", type=int, default=16)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--window", type=int, default=16)
@@ -101,14 +101,14 @@ def main():
                     help="after the timed region, copy this many MiB once (counter calibration)")
     ap.add_argument("--bwd-steps", type=int, default=32)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-rates", type=str, default="50,100,200,400")
-    ap.add_argument("--serve-rates-single", type=str, default="50,100,200,400",
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of Poisson arrivals per rate and mode (60 for the full protocol)")
+    ap.add_argument("--serve-rates", type=str, default="50,100,200,400,800")
+    ap.add_argument("--serve-rates-single", type=str, default="50,100,200,400,800",
                     help="rates for the one-request-at-a-time baseline")
-    ap.add_argument("--suite", action="store_true",
-                    help="also time the ablations (no tile culling, no per-ray window) and the other workloads: "
-                         "500k 1080p, 3M 2064x2208 120deg with its zoom sweep, 1M 1280x720 16-view training "
-                         "steps (adds a few minutes)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other workloads (500k 1080p, 3M 2064x2208 120deg and its zoom sweep, the "
+                         "1M 720p 16-view training step) and the Tab. 5 ablations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -139,15 +139,20 @@ def main():
     torch.cuda.synchronize()
     ras.stage_times(reset=True)
 
-    # timed region
+    # timed region (HIP events around every frame on the render stream give
+    # the per-frame times; the wall clock gives the throughput)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        evs[k][0].record()
         ras.render(ds, cams[k % len(cams)], st, timing=True)
+        evs[k][1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stage_ms, frames = ras.stage_times(reset=True)
     assert frames == args.steps, (frames, args.steps)
+    frame_ms = np.array([a.elapsed_time(b) for a, b in evs])
 
     if args.copy_probe_mib:
         nb = args.copy_probe_mib << 20
@@ -156,6 +161,20 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+
+    # measured machine rates beside the spec peaks (FMA and exp rates,
+    # copy bandwidth over a 1 GiB buffer)
+    import ctypes
+    from paper_2504_12811_amd import _lib as L
+    pk_buf = torch.empty((1 << 30) + 256, dtype=torch.uint8, device="cuda:0")
+    pk = (ctypes.c_double * 3)()
+    L.check(L.lib().aaa_measure_peaks(pk_buf.data_ptr() + (-pk_buf.data_ptr()) % 256, 1 << 30, 5,
+                                      torch.cuda.current_stream().cuda_stream, pk))
+    del pk_buf
+    peaks_measured = {"fp32_fma_tflops": round(pk[0], 2), "exp_g_per_s": round(pk[1], 1),
+                      "copy_gbps": round(pk[2], 1),
+                      "spec": {"fp32_vector_tflops_nonpacked": round(PEAK_VALU_TFLOPS, 1),
+                               "fp32_vector_tflops_packed": 157.3, "hbm_gbps": PEAK_HBM_GBS}}
 
     fps = args.steps / elapsed
     ms_step = 1000.0 * elapsed / args.steps
@@ -169,14 +188,18 @@ def main():
     blend_ms = stage_ms["blend"] / frames
     flops = FLOPS_EVAL * E.mean() + FLOPS_NEAR * NE.mean() + (args.window + FLOPS_CONTRIB_BASE) * CT.mean()
     achieved = flops / (blend_ms * 1e-3) / 1e12
-    # HBM-bound stages
+    # HBM-bound stages, algorithmic bytes: the preprocess reads the 12
+    # non-SH floats of every Gaussian and writes its status, and reads the SH
+    # coefficients and writes a ~96-byte render record only for the visible
+    # ones; the sort reads every key once for the histograms (8 B) and reads
+    # and writes key and value once per 8-bit pass (24 B)
     n = ds.n
     sh_floats = 3 * (scene.sh_degree + 1) ** 2
-    pre_bytes = n * (4 * (3 + 3 + 4 + 1 + 1 + sh_floats) + 4 + 16 + 128 + 128)
+    pre_bytes = n * (4 * 12 + 4) + VIS.mean() * (4 * sh_floats + 96)
     ntiles = cams[0].tiles[0] * cams[0].tiles[1]
     bits = 32 + int(np.ceil(np.log2(ntiles)))
     passes = (bits + 7) // 8
-    sort_bytes = P.mean() * 32 * passes
+    sort_bytes = P.mean() * (8 + 24 * passes)
     pre_ms = stage_ms["preprocess"] / frames
     sort_ms = stage_ms["sort"] / frames
 
@@ -197,6 +220,8 @@ def main():
                                f"K={args.window}, 32 poses r=12", "n_gaussians": n, "width": 1920,
                    "height": 1080, "fov_deg": 60, "sh_degree": 3, "ray_window": args.window},
         "mpix_per_s": round(fps * 1920 * 1080 / 1e6, 2),
+        "frame_ms": {"median": round(float(np.median(frame_ms)), 4), "p99": round(float(np.percentile(frame_ms, 99)), 4),
+                     "frames": int(len(frame_ms)), "timer": "HIP events around each frame on the render stream"},
         "roofline": {
             "kernel": "k_blend<16>",
             "bound": "alu",
@@ -209,12 +234,15 @@ def main():
             "valu_busy": (lambda kv: float(kv["valu_busy"]) if "valu_busy" in kv else None)(blend_counters()),
             "avg_ms": round(blend_ms, 4),
             "flops_per_launch": flops,
+            "frac_of_measured_fma_rate": round(achieved / peaks_measured["fp32_fma_tflops"], 4)
+            if peaks_measured["fp32_fma_tflops"] > 0 else None,
         },
+        "peaks_measured": peaks_measured,
         "stages_ms": {k: round(v / frames, 4) for k, v in stage_ms.items()},
         "hbm_stages": {
-            "preprocess": {"bytes": pre_bytes, "GBps": round(pre_bytes / (pre_ms * 1e-3) / 1e9, 1),
+            "preprocess": {"bytes": round(pre_bytes), "GBps": round(pre_bytes / (pre_ms * 1e-3) / 1e9, 1),
                            "frac": round(pre_bytes / (pre_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
-            "sort": {"bytes": sort_bytes, "passes": passes, "GBps": round(sort_bytes / (sort_ms * 1e-3) / 1e9, 1),
+            "sort": {"bytes": round(sort_bytes), "passes": passes, "GBps": round(sort_bytes / (sort_ms * 1e-3) / 1e9, 1),
                      "frac": round(sort_bytes / (sort_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         },
         "per_frame": {"pairs": P.mean(), "visible": VIS.mean(), "evaluations": E.mean(),
@@ -252,11 +280,14 @@ def main():
     if not args.no_serving:
         from paper_2504_12811_amd.serve import Server, gpu_render_batch, run_load
         serving = {}
+        cap = 16 << 30
         for mode, (workers, maxb) in {"batched": (2, 8), "one_at_a_time": (1, 1)}.items():
-            fn = gpu_render_batch(ds, st, n_workers=workers)
+            # each worker's workspace (its share of the cap) is allocated here,
+            # before any request arrives
+            fn = gpu_render_batch(ds, st, n_workers=workers, worker_bytes=cap // workers)
             rates = args.serve_rates if mode == "batched" else args.serve_rates_single
             for rate in [float(r) for r in rates.split(",")]:
-                with Server(fn, n_gaussians=ds.n, mem_cap=16 << 30, max_batch=maxb, n_workers=workers) as srv:
+                with Server(fn, n_gaussians=ds.n, mem_cap=cap, max_batch=maxb, n_workers=workers) as srv:
                     run_load(srv, rate, 0.5, seed=99)  # warm-up (allocations, code paths)
                     lat, frames, wall, rej = run_load(srv, rate, args.serve_seconds, seed=int(rate))
                     batches = list(srv.batches)
@@ -264,12 +295,15 @@ def main():
                     "rate_req_s": rate, "requests": int(len(lat)), "rejected": rej,
                     "p50_ms": round(1000 * float(np.percentile(lat, 50)), 2) if len(lat) else None,
                     "p99_ms": round(1000 * float(np.percentile(lat, 99)), 2) if len(lat) else None,
-                    "frames_per_s": round(frames / wall, 2), "mean_batch": round(float(np.mean(batches)), 2)}
+                    "frames_per_s": round(frames / wall, 2), "mean_batch": round(float(np.mean(batches)), 2),
+                    "seconds": args.serve_seconds}
                 print(f"# serving {mode} {rate}: {serving[f'{mode}@{int(rate)}']}", file=sys.stderr, flush=True)
+            del fn
+            torch.cuda.empty_cache()
         res["serving"] = serving
 
-    if args.suite:
-        res["suite"] = run_suite(ras, st, args)
+    if not args.no_workloads:
+        res["workloads"] = run_workloads(ras, st, args)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -279,34 +313,52 @@ def main():
             O.render(scene, cams[p], st)
         cpu_s = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": round(k / cpu_s, 4), "unit": "frames/s", "cores": O.num_threads(),
-                               "kind": "oracle",
+                               "kind": "oracle", "cpu_model": cpu_model(),
                                "sample": f"{k} full 1920x1080 frames (poses 0..{k - 1}) of the same 1M scene, "
                                          f"FP64 oracle, {cpu_s:.1f}s wall"}
     print(json.dumps(res), flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _time_frames(ras, ds, cams, st, steps, warmup):
-    """Forward frames over `cams` (cycled): frames/s, per-stage ms (HIP events)."""
+    """Forward frames over `cams` (cycled): frames/s, median and p99 frame
+    time (HIP events around each frame), per-stage ms (HIP events)."""
     import torch
     for k in range(warmup):
         ras.render(ds, cams[k % len(cams)], st)
     torch.cuda.synchronize()
     ras.stage_times(reset=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
+        evs[k][0].record()
         ras.render(ds, cams[k % len(cams)], st, timing=True)
+        evs[k][1].record()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms, frames = ras.stage_times(reset=True)
+    fm = np.array([a.elapsed_time(b) for a, b in evs])
     _, _, s0 = ras.render(ds, cams[0], st, stats=True)
     c = cams[0]
     return {"frames_per_s": round(steps / el, 3), "ms_per_frame": round(1000 * el / steps, 4),
-            "mpix_per_s": round(steps / el * c.width * c.height / 1e6, 2),
+            "median_ms": round(float(np.median(fm)), 4), "p99_ms": round(float(np.percentile(fm, 99)), 4),
+            "frames": steps, "mpix_per_s": round(steps / el * c.width * c.height / 1e6, 2),
             "stages_ms": {k: round(v / frames, 4) for k, v in ms.items()},
             "pairs": int(s0.pairs), "evaluations": int(s0.evaluations), "contributors": int(s0.contributors)}
 
 
-def run_suite(ras, st, args):
+def run_workloads(ras, st, args):
     """The other workloads of the benchmark family, each timed on its own."""
     import torch
     from paper_2504_12811_amd import scenes as S
@@ -316,37 +368,41 @@ def run_suite(ras, st, args):
     # (rectangles only) and without the per-ray window (K = 0: tile order)
     scene, cams = S.headline()
     ds = DeviceScene.from_host(scene, "cuda:0")
-    full = _time_frames(ras, ds, cams, st, steps=32, warmup=4)
-    no_cull = _time_frames(ras, ds, cams, S.Settings(ray_window=st.ray_window, tile_cull=False), steps=32, warmup=4)
-    no_sort = _time_frames(ras, ds, cams, S.Settings(ray_window=0), steps=32, warmup=4)
+    full = _time_frames(ras, ds, cams, st, steps=64, warmup=8)
+    no_cull = _time_frames(ras, ds, cams, S.Settings(ray_window=st.ray_window, tile_cull=False), steps=64, warmup=8)
+    no_sort = _time_frames(ras, ds, cams, S.Settings(ray_window=0), steps=64, warmup=8)
+    # the three-level hierarchy: tile culling, the exact per-8x8 sub-tile
+    # re-sort and the per-ray window
+    three = _time_frames(ras, ds, cams, S.Settings(ray_window=st.ray_window, subtile_sort=True), steps=64, warmup=8)
     out["ablation_1M_1080p"] = {
         "full_ms": full["ms_per_frame"], "no_tile_cull_ms": no_cull["ms_per_frame"],
-        "no_ray_window_ms": no_sort["ms_per_frame"],
+        "no_ray_window_ms": no_sort["ms_per_frame"], "three_level_ms": three["ms_per_frame"],
         "culling_speedup": round(no_cull["ms_per_frame"] / full["ms_per_frame"], 3),
         "ray_window_cost": round(full["ms_per_frame"] / no_sort["ms_per_frame"], 3),
-        "pairs": {"full": full["pairs"], "no_tile_cull": no_cull["pairs"]},
+        "hier_sort_cost_three_level": round(three["ms_per_frame"] / no_sort["ms_per_frame"], 3),
+        "pairs": {"full": full["pairs"], "no_tile_cull": no_cull["pairs"], "three_level": three["pairs"]},
         "stages_ms": {"full": full["stages_ms"], "no_tile_cull": no_cull["stages_ms"],
-                      "no_ray_window": no_sort["stages_ms"]},
+                      "no_ray_window": no_sort["stages_ms"], "three_level": three["stages_ms"]},
         "paper_tab5_ratios": {"culling_speedup": [1.87, 2.16, 1.82, 1.53], "hier_sort_cost": [1.88, 1.69, 1.91, 1.67],
                               "hardware": "RTX 4090, trained scenes"}}
-    print(f"# suite ablation: {out['ablation_1M_1080p']}", file=sys.stderr, flush=True)
+    print(f"# workload ablation: {out['ablation_1M_1080p']}", file=sys.stderr, flush=True)
     del ds
     # 500k Gaussians, 1920x1080, 60 deg, the 32 poses
     scene, cams = S.medium()
     ds = DeviceScene.from_host(scene, "cuda:0")
-    out["500k_1080p"] = _time_frames(ras, ds, cams, st, steps=64, warmup=8)
-    print(f"# suite 500k: {out['500k_1080p']}", file=sys.stderr, flush=True)
+    out["500k_1080p"] = _time_frames(ras, ds, cams, st, steps=128, warmup=16)
+    print(f"# workload 500k: {out['500k_1080p']}", file=sys.stderr, flush=True)
     del ds
     # 3M Gaussians (10% straddling the near plane), 2064x2208, 120 deg; zoom sweep 2x..64x scene radius
     scene, cam, zoom = S.ood_scene()
     ds = DeviceScene.from_host(scene, "cuda:0")
-    out["3M_2064x2208_120deg"] = _time_frames(ras, ds, [cam], st, steps=8, warmup=2)
-    print(f"# suite 3M primary: {out['3M_2064x2208_120deg']}", file=sys.stderr, flush=True)
+    out["3M_2064x2208_120deg"] = _time_frames(ras, ds, [cam], st, steps=100, warmup=4)
+    print(f"# workload 3M primary: {out['3M_2064x2208_120deg']}", file=sys.stderr, flush=True)
     sweep = []
     for z in zoom:
-        r = _time_frames(ras, ds, [z], st, steps=8, warmup=2)
+        r = _time_frames(ras, ds, [z], st, steps=100, warmup=4)
         sweep.append({"distance": round(float(np.linalg.norm(z.position)), 2), **r})
-        print(f"# suite 3M zoom {sweep[-1]['distance']}: {r['frames_per_s']} fps", file=sys.stderr, flush=True)
+        print(f"# workload 3M zoom {sweep[-1]['distance']}: {r['frames_per_s']} fps", file=sys.stderr, flush=True)
     out["3M_zoom_sweep"] = sweep
     del ds
     # 1M Gaussians, 1280x720, 70 deg: one training step = 16 views forward
@@ -372,7 +428,7 @@ def run_suite(ras, st, args):
     out["1M_720p_16view_fwd_bwd"] = {"steps_per_s": round(n_steps / el, 3), "ms_per_step": round(1000 * el / n_steps, 3),
                                      "views_per_s": round(16 * n_steps / el, 2), "views_per_step": 16,
                                      "loss": "L1 vs seeded U[0,1] noise image", "optimizer": "Adam (fused kernel)"}
-    print(f"# suite 720p fwd+bwd: {out['1M_720p_16view_fwd_bwd']}", file=sys.stderr, flush=True)
+    print(f"# workload 720p fwd+bwd: {out['1M_720p_16view_fwd_bwd']}", file=sys.stderr, flush=True)
     return out
 
 

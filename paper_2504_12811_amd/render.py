@@ -144,10 +144,36 @@ class Rasterizer:
             return rgb, T, out
         raise L.AAAError(L.AAA_ERR_PAIR_OVERFLOW, "pair buffer kept overflowing")
 
+    def batch_pair_capacity(self, scene: DeviceScene, cams, settings, nbytes: int) -> int:
+        """The largest max_pairs whose workspace for this batch fits in
+        `nbytes` (0 if not even an empty pair buffer fits).  The workspace
+        grows linearly with max_pairs."""
+        sc = scene.abi()
+        V = len(cams)
+        carr = (L.Camera * V)(*[L.make_camera(c) for c in cams])
+        st = L.make_settings(settings)
+        a, b = C.c_size_t(), C.c_size_t()
+        m1 = 1 << 20
+        L.check(L.lib().aaa_workspace_size_batch(C.byref(sc), V, carr, C.byref(st), 1, C.byref(a)))
+        L.check(L.lib().aaa_workspace_size_batch(C.byref(sc), V, carr, C.byref(st), m1 + 1, C.byref(b)))
+        if a.value > nbytes:
+            return 0
+        per = (b.value - a.value) / m1
+        mp = min(int((nbytes - a.value) / per), (1 << 32) - 1)
+        while mp > 1:  # alignment padding: step down until it fits
+            L.check(L.lib().aaa_workspace_size_batch(C.byref(sc), V, carr, C.byref(st), mp, C.byref(a)))
+            if a.value <= nbytes:
+                break
+            mp -= max(1, mp // 1000)
+        return mp
+
     def render_batch(self, scene: DeviceScene, cams, settings, stats: bool = False, max_pairs: Optional[int] = None,
-                     fresh_ws: bool = False, flags: int = 0):
+                     fresh_ws: bool = False, flags: int = 0, ws: Optional[Workspace] = None):
         """Render several views of one scene in one launch sequence; returns
-        ([rgb_v], [T_v], Stats).  Each view equals its single-view render."""
+        ([rgb_v], [T_v], Stats).  Each view equals its single-view render.
+        With `ws` (and max_pairs) the batch renders into that workspace and
+        nothing is allocated beyond the output images: a batch that does not
+        fit raises AAAError (AAA_ERR_WORKSPACE or AAA_ERR_PAIR_OVERFLOW)."""
         sc = scene.abi()
         V = len(cams)
         carr = (L.Camera * V)(*[L.make_camera(c) for c in cams])
@@ -156,6 +182,15 @@ class Rasterizer:
         Ts = [torch.empty((int(c.height), int(c.width)), dtype=torch.float32, device=self.device) for c in cams]
         prgb = (C.c_void_p * V)(*[t.data_ptr() for t in rgbs])
         pT = (C.c_void_p * V)(*[t.data_ptr() for t in Ts])
+        if ws is not None:
+            mp = max_pairs if max_pairs is not None else ws.max_pairs
+            out = L.Stats()
+            L.check(L.lib().aaa_render_batch(self._ctx, C.byref(sc), V, carr, C.byref(st), ws.ptr, ws.nbytes, mp,
+                                             _stream_ptr(self.device), prgb, pT, C.byref(out)))
+            self.last_pairs = int(out.pairs)
+            self.last_ws = ws
+            ws.max_pairs = mp
+            return rgbs, Ts, out
         own = not fresh_ws
         cur = self._ws if own else None
         npix = sum(int(c.width) * int(c.height) for c in cams)

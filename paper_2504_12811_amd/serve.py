@@ -1,11 +1,13 @@
 """Serving: a resident scene, continuous batching of render requests.
 
 Requests (one or two views each: a pinhole camera per view) enter a FIFO
-queue.  Each worker owns a library context, a HIP stream and a workspace.  A
+queue.  Each worker owns a library context, a HIP stream and a workspace of
+its share of the memory cap, allocated when the server starts, so nothing is
+allocated on the request path and the workspaces never exceed the cap.  A
 worker that becomes free takes, from the head of the queue, as many requests
-as fit both the batch limit and the memory admission cap (the estimated
-device memory of everything in flight must stay under the cap), renders them
-with one batched launch sequence on its stream, and completes their futures.
+as fit both the batch limit and its share of the cap (estimated device
+memory of the batch), renders them with one batched launch sequence on its
+stream into its workspace, and completes their futures.
 Requests that arrive while batches are on the GPU are admitted as soon as a
 worker and memory free up; with two or more workers, batches overlap on the
 device.  Every view in a batch is bit-identical to rendering it alone (the
@@ -76,6 +78,8 @@ class Server:
         self.mem_cap = int(mem_cap)
         self.max_batch = int(max_batch)
         self.n_workers = int(n_workers)
+        # each worker renders into a workspace of its share of the cap
+        self.worker_bytes = self.mem_cap // self.n_workers
         self.pairs_per_pixel = pairs_per_pixel
         self._q: collections.deque = collections.deque()
         self._cv = threading.Condition()
@@ -91,9 +95,11 @@ class Server:
     def submit(self, cams, t_arrival: Optional[float] = None) -> Future:
         req = Request(list(cams), time.perf_counter() if t_arrival is None else t_arrival)
         req.est_bytes = estimate_bytes(self.n, req.cams, self.pairs_per_pixel)
-        if req.est_bytes > self.mem_cap:
+        fixed = estimate_bytes(self.n, req.cams, 0.0)  # without the pair buffers
+        if fixed > self.worker_bytes:
             req.future.set_exception(AdmissionError(
-                f"request needs ~{req.est_bytes >> 20} MiB, above the {self.mem_cap >> 20} MiB cap"))
+                f"request needs ~{fixed >> 20} MiB before any pair, above a worker's {self.worker_bytes >> 20} MiB "
+                f"share of the {self.mem_cap >> 20} MiB cap"))
             return req.future
         with self._cv:
             self._q.append(req)
@@ -116,15 +122,21 @@ class Server:
     # ------------------------------------------------------------------
     def _take_batch(self) -> List[Request]:
         """Called with the lock held: FIFO requests that fit the batch limit
-        and the memory still free under the cap."""
+        and a worker's share of the cap.  A request whose estimate alone
+        exceeds the share (the pair estimate is conservative) goes alone; its
+        worker renders it with the pair buffer that fits, and reports it
+        rejected if its pairs do not."""
         batch, need = [], 0
         while self._q and len(batch) < self.max_batch:
             r = self._q[0]
-            if self._mem_in_use + need + r.est_bytes > self.mem_cap:
+            if need + r.est_bytes > self.worker_bytes and batch:
                 break
             batch.append(self._q.popleft())
             need += r.est_bytes
+            if need > self.worker_bytes:
+                break
         if batch:
+            need = min(need, self.worker_bytes)
             self._mem_in_use += need
             self.peak_mem = max(self.peak_mem, self._mem_in_use)
             self.batches.append(len(batch))
@@ -158,25 +170,49 @@ class Server:
                         r.future.set_exception(e)
             finally:
                 with self._cv:
-                    self._mem_in_use -= sum(r.est_bytes for r in batch)
+                    self._mem_in_use -= min(sum(r.est_bytes for r in batch), self.worker_bytes)
                     self._cv.notify_all()
 
 
-def gpu_render_batch(scene, settings, n_workers: int, device: int = 0):
-    """Batch render functions for `Server`: one rasteriser (library context,
-    workspace) and one HIP stream per worker."""
+def gpu_render_batch(scene, settings, n_workers: int, device: int = 0, worker_bytes: int = 8 << 30):
+    """Batch render functions for `Server`: one rasteriser (library
+    context), one HIP stream and one workspace of `worker_bytes` per worker,
+    allocated here.  A batch renders into its worker's workspace with the
+    largest pair buffer that fits; if its pairs overflow that buffer it is
+    rendered in two halves (a single view that cannot fit raises)."""
     import torch
-    from .render import Rasterizer
+    from . import _lib as L
+    from .render import Rasterizer, Workspace
 
     rasters = [Rasterizer(device) for _ in range(n_workers)]
     streams = [torch.cuda.Stream(device=device) for _ in range(n_workers)]
+    spaces = [Workspace(torch.device("cuda", device), int(worker_bytes), 0) for _ in range(n_workers)]
+
+    def render(wid, cams):
+        ras, ws = rasters[wid], spaces[wid]
+        mp = ras.batch_pair_capacity(scene, cams, settings, ws.nbytes)
+        try:
+            if mp <= 0:
+                raise L.AAAError(L.AAA_ERR_WORKSPACE, "batch does not fit the worker's workspace")
+            rgbs, _, st = ras.render_batch(scene, cams, settings, ws=ws, max_pairs=mp)
+            return rgbs, int(st.pairs)
+        except L.AAAError as e:
+            if e.code not in (L.AAA_ERR_PAIR_OVERFLOW, L.AAA_ERR_WORKSPACE):
+                raise
+            if len(cams) == 1:
+                raise AdmissionError(f"view does not fit the worker's {ws.nbytes >> 20} MiB workspace: {e}") from e
+        h = len(cams) // 2
+        a, pa = render(wid, cams[:h])
+        b, pb = render(wid, cams[h:])
+        return a + b, pa + pb
 
     def fn(wid: int, cams):
         with torch.cuda.stream(streams[wid]):
-            rgbs, Ts, st = rasters[wid].render_batch(scene, cams, settings)
+            rgbs, pairs = render(wid, cams)
             streams[wid].synchronize()
-        return rgbs, int(st.pairs)
+        return rgbs, pairs
 
+    fn.worker_bytes = int(worker_bytes)
     return fn
 
 

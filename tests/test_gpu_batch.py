@@ -74,7 +74,7 @@ def test_server_results_equal_solo_renders(ras):
     reqs = [random_request(rng) for _ in range(12)]
     fov = lambda c: round(float(np.degrees(2 * np.arctan(c.width / 2 / c.fx))), 1)
     print("requests (views, W, H, fov):", [(len(r), r[0].width, r[0].height, fov(r[0])) for r in reqs], flush=True)
-    fn = gpu_render_batch(ds, st, n_workers=2)
+    fn = gpu_render_batch(ds, st, n_workers=2, worker_bytes=4 << 30)
     with Server(fn, n_gaussians=ds.n, mem_cap=8 << 30, max_batch=4, n_workers=2) as srv:
         futs = [srv.submit(r) for r in reqs]
         results = [f.result(timeout=120) for f in futs]

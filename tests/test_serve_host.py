@@ -44,13 +44,18 @@ def test_results_match_their_requests_and_batches_respect_the_limit():
 
 
 def test_memory_admission_bounds_in_flight_bytes():
+    """Each worker renders into its share of the cap: a batch holds only as
+    many requests as fit that share, and the bytes in flight never exceed
+    the cap."""
     fr = FakeRender(0.01)
     one = estimate_bytes(1000, [cam(64, 64)])
-    with Server(fr, n_gaussians=1000, mem_cap=int(2.5 * one), max_batch=8, n_workers=3) as srv:
+    cap = int(2 * 2.5 * one)
+    with Server(fr, n_gaussians=1000, mem_cap=cap, max_batch=8, n_workers=2) as srv:
+        assert srv.worker_bytes == cap // 2
         futs = [srv.submit([cam(64, 64)]) for _ in range(12)]
         for f in futs:
             f.result(timeout=10)
-        assert srv.peak_mem <= int(2.5 * one)
+        assert srv.peak_mem <= cap
         assert max(srv.batches) <= 2
 
 
@@ -60,6 +65,33 @@ def test_request_above_the_cap_is_rejected():
         f = srv.submit([cam(1920, 1080)])
         with pytest.raises(AdmissionError):
             f.result(timeout=5)
+
+
+def test_request_above_a_workers_share_is_rejected():
+    """A request whose records alone (no pair buffer) exceed one worker's
+    share of the cap can never be rendered (a batch renders in one worker's
+    workspace)."""
+    fr = FakeRender()
+    fixed = estimate_bytes(1000, [cam(64, 64)], 0.0)
+    with Server(fr, n_gaussians=1000, mem_cap=int(1.5 * fixed), max_batch=4, n_workers=2) as srv:
+        f = srv.submit([cam(64, 64)])
+        with pytest.raises(AdmissionError):
+            f.result(timeout=5)
+    assert fr.calls == []
+
+
+def test_request_whose_pair_estimate_exceeds_the_share_goes_alone():
+    """The pair estimate is conservative: a request above the share whose
+    records fit is rendered, in a batch of its own."""
+    fr = FakeRender(0.01)
+    one = estimate_bytes(1000, [cam(64, 64)])
+    fixed = estimate_bytes(1000, [cam(64, 64)], 0.0)
+    share = (fixed + one) // 2
+    with Server(fr, n_gaussians=1000, mem_cap=2 * share, max_batch=4, n_workers=2) as srv:
+        futs = [srv.submit([cam(64, 64)]) for _ in range(5)]
+        for f in futs:
+            f.result(timeout=10)
+    assert srv.batches and max(srv.batches) == 1 and sum(srv.batches) == 5
 
 
 def test_requests_arriving_during_a_batch_run_on_the_other_worker():
