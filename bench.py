@@ -132,7 +132,8 @@ def main():
     counts = []
     for cam in cams:
         _, _, s = ras.render(ds, cam, st, stats=True)
-        counts.append((s.pairs, s.evaluations, s.near, s.contributors, s.visible))
+        counts.append((s.pairs, s.evaluations, s.near, s.contributors, s.visible, s.wave_steps, s.wave_near_steps,
+                       s.wave_contrib_steps))
     torch.cuda.synchronize()
     for k in range(args.warmup):
         ras.render(ds, cams[k % len(cams)], st)
@@ -246,7 +247,10 @@ def main():
                      "frac": round(sort_bytes / (sort_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
         },
         "per_frame": {"pairs": P.mean(), "visible": VIS.mean(), "evaluations": E.mean(),
-                      "prefilter_passes": NE.mean(), "contributors": CT.mean()},
+                      "prefilter_passes": NE.mean(), "contributors": CT.mean(),
+                      "wave_steps": float(np.mean([u[5] for u in used])),
+                      "wave_steps_prefilter": float(np.mean([u[6] for u in used])),
+                      "wave_steps_contributor": float(np.mean([u[7] for u in used]))},
     }
 
     # forward + backward: L1 loss against a seeded noise target, one pose per step
