@@ -33,6 +33,17 @@ namespace aaa {
 
 namespace {
 
+// A wave-uniform read of a buffer that the kernel never writes, through the
+// constant address space: the compiler then issues a scalar load even in a
+// kernel that also stores to global memory (for a generic pointer it cannot
+// rule out that those stores alias the buffer, and falls back to a vector
+// load that waits behind every store in flight).
+template <typename T>
+__device__ __forceinline__ T uniform_read(const T *p)
+{
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 struct PixelState {
     float T, C[3];
     bool done;
@@ -176,7 +187,10 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
     const int nv = a.nviews;
     const int lt = tile - vw.tile_base;
     const int tx = lt % vw.cam.tiles_x, ty = lt / vw.cam.tiles_x;
-    const int wave = WPB == 4 ? (int)(threadIdx.x >> 6) : (wq & 3), lane = threadIdx.x & 63;
+    // wave-uniform (readfirstlane): the quadrant tests on list entries are
+    // then scalar branches, and the list loads stay scalar loads
+    const int wave = WPB == 4 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (wq & 3);
+    const int lane = threadIdx.x & 63;
     const int wl = WPB == 4 ? wave : 0;  // this wave's LDS rows
     const int px = tx * kTile + (wave & 1) * 8 + (lane & 7);
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
@@ -232,6 +246,10 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
         bp.slots = a.slots + a.wave_off[4 * tile + wave] * 64 + lane;
         cap = a.n_ins[gpix];
     }
+    // pass 1 of a quadrant without contributors has no slot to write.  (The
+    // test also waits for `cap` here, once: the loop's uses of it would
+    // otherwise each wait for every slot store in flight.)
+    if (PASS1 && __builtin_amdgcn_ballot_w64(cap != 0u) == 0ull) return;
     uint32_t consumed = 0, rank = 0;
     uint32_t n_eval = 0, n_near = 0;
     uint32_t w_steps = 0, w_near = 0, w_contrib = 0;  // wave-uniform
@@ -240,7 +258,7 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
 
     for (uint32_t i = start; i < end; ++i) {
         if (__builtin_amdgcn_ballot_w64(!ps.done) == 0ull) break;
-        const uint32_t raw = vals[i];
+        const uint32_t raw = uniform_read(vals + i);
         if ((((raw | a.quad_on) >> (kQuadShift + wave)) & 1u) == 0u) continue;  // box misses this quadrant
         const uint32_t id = (raw & a.id_mask) * (uint32_t)nv + (uint32_t)v;  // item of (Gaussian, view)
         const float4 *r = rec + (size_t)id * kRecQuads;
@@ -765,7 +783,22 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
     float g[3];
     for (int c = 0; c < 3; ++c) g[c] = inside ? vw.dL_drgb[c * hw + pix] : 0.0f;
     const float amin = a.alpha_min, amax = a.alpha_max, znear = (float)vw.cam.znear;
+    // A quadrant without contributors, or without an incoming gradient (every
+    // slot then holds dL/dalpha = 0 and every value below is 0), adds
+    // nothing.  The test also waits for `cap` and `g` here, once: the loop's
+    // uses of them would otherwise each wait for every atomic in flight.
+    if (__builtin_amdgcn_ballot_w64(cap != 0u && (g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f)) == 0ull) return;
     uint32_t rank = 0;
+    // The slot of this lane's next contributor is loaded one contributor
+    // ahead, so that its latency overlaps the steps in between.  Every lane
+    // reloads it at every wave step with a contributor (lanes without one
+    // reload the same row), from a row clamped to the quadrant's rows: the
+    // load is then unconditional and lands in the same registers each time
+    // (no copy that would wait for it); rows at or past the pixel's own count
+    // are zeroed at use.
+    uint32_t wcap = cap;  // the quadrant's largest count: its slot rows (>= 1 here)
+    for (int off = 32; off > 0; off >>= 1) wcap = max(wcap, (uint32_t)__shfl_xor((int)wcap, off));
+    float2 s_next = slots[0];
 
     const uint32_t qbit = 1u << (kQuadShift + wave);
     auto step = [&](uint32_t i, uint32_t raw, const Hot &h) {
@@ -782,11 +815,9 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
         const float z = __fmaf_rn(dy, h.l2, __fmaf_rn(dx, h.l1, h.l0)) * inv;
         const bool contrib = near && al >= amin && z >= znear;
         if (__builtin_amdgcn_ballot_w64(contrib) == 0ull) return;
-        float2 s = make_float2(0.0f, 0.0f);
-        if (contrib) {
-            if (rank < cap) s = slots[(size_t)rank * 64];
-            ++rank;
-        }
+        const float2 s = (contrib && rank < cap) ? s_next : make_float2(0.0f, 0.0f);
+        rank += contrib ? 1u : 0u;
+        s_next = slots[(size_t)min(rank, wcap - 1u) * 64];
         // 22 record gradients of this lane (zero when not blended)
         const float ga = s.x, W = s.y;
         const bool moves = contrib && al < amax && W > 0.0f;  // a clamped alpha does not move
