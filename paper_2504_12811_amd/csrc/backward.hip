@@ -164,9 +164,12 @@ __device__ __forceinline__ void preprocess_bwd_item(const PreArgs &a, int64_t i,
     glogit_out += glogit;
 }
 
-// Gaussians with a visible item in some view, compacted (order irrelevant:
-// every Gaussian is handled by one thread).  A block takes kTouchPer
-// consecutive Gaussians and claims its slots with one atomic.
+// Gaussians with a visible item in some view, compacted in increasing
+// order, so that neighbouring threads of the adjoint read neighbouring
+// parameters.  A block takes kTouchPer rounds of 256 consecutive Gaussians;
+// each wave's visibility ballot of a round is counted, the counts are
+// scanned in (round, wave) order, and the block claims its slots with one
+// atomic: its slots then hold its Gaussians in increasing order.
 constexpr int kTouchPer = 16;
 
 __device__ __forceinline__ bool gauss_visible(const int32_t *status, int64_t i, int64_t n, int nviews)
@@ -180,29 +183,33 @@ __device__ __forceinline__ bool gauss_visible(const int32_t *status, int64_t i, 
 __global__ __launch_bounds__(256) void k_touched(const int32_t *__restrict__ status, int64_t n, int nviews,
                                                  uint32_t *__restrict__ list, uint32_t *__restrict__ count)
 {
-    __shared__ uint32_t pre[256];
+    __shared__ uint32_t pre[kTouchPer * 4 + 1];  // exclusive offsets in (round, wave) order, then the total
     __shared__ uint32_t base;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int64_t b0 = (int64_t)blockIdx.x * 256 * kTouchPer;
-    uint32_t mine = 0;
-#pragma unroll
-    for (int k = 0; k < kTouchPer; ++k) mine += gauss_visible(status, b0 + (int64_t)k * 256 + t, n, nviews) ? 1u : 0u;
-    // inclusive scan of the per-thread counts over the block
-    pre[t] = mine;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t y = t >= off ? pre[t - off] : 0u;
-        __syncthreads();
-        pre[t] += y;
-        __syncthreads();
-    }
-    if (t == 255) base = pre[255] ? atomicAdd(count, pre[255]) : 0u;
-    __syncthreads();
-    uint32_t pos = base + pre[t] - mine;
+    uint64_t m[kTouchPer];
 #pragma unroll
     for (int k = 0; k < kTouchPer; ++k) {
-        const int64_t i = b0 + (int64_t)k * 256 + t;
-        if (gauss_visible(status, i, n, nviews)) list[pos++] = (uint32_t)i;
+        m[k] = __ballot(gauss_visible(status, b0 + (int64_t)k * 256 + t, n, nviews));
+        if (lane == 0) pre[k * 4 + wave] = (uint32_t)__popcll(m[k]);
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < kTouchPer * 4; ++k) {
+            const uint32_t c = pre[k];
+            pre[k] = acc;
+            acc += c;
+        }
+        pre[kTouchPer * 4] = acc;
+        base = acc ? atomicAdd(count, acc) : 0u;
+    }
+    __syncthreads();
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int k = 0; k < kTouchPer; ++k) {
+        if ((m[k] >> lane) & 1ull)
+            list[base + pre[k * 4 + wave] + (uint32_t)__popcll(m[k] & below)] = (uint32_t)(b0 + (int64_t)k * 256 + t);
     }
 }
 

@@ -14,12 +14,16 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kBoundEps = 1e-3;  // clamp margin of the angular bounds (rad)
+constexpr double kBoundTan = 999.9996666666443;  // 1 / tan(kBoundEps): the tangent at pi/2 - kBoundEps
 
-// Angular bounds of the level-tau ellipsoid seen from the camera in one view
-// plane (Sec. 3.3, Eq. 14-17).  Rows a (lateral: view x or y) and c (depth)
-// of M = R_V R S~ and the matching mean coordinates.  Returns false when the
-// visible wedge is empty; sets full = true when the lateral axis line meets
-// the ellipsoid (negative discriminant: the whole screen range).
+// Bounds of the level-tau ellipsoid seen from the camera in one view plane
+// (Sec. 3.3, Eq. 14-17), as the tangents lo < hi of the two bounding angles
+// (lateral over depth: screen offsets over focal length).  Rows a (lateral:
+// view x or y) and c (depth) of M = R_V R S~ and the matching mean
+// coordinates.  Returns false when the visible wedge is empty; sets full =
+// true when the lateral axis line meets the ellipsoid (negative
+// discriminant: the whole screen range).  Angles are clamped to
+// (-pi/2, pi/2) by kBoundEps.
 __device__ bool view_bounds(const double *Ma, const double *Mc, double ma, double mc, double tau, double &lo,
                             double &hi, bool &full)
 {
@@ -38,6 +42,17 @@ __device__ bool view_bounds(const double *Ma, const double *Mc, double ma, doubl
     double sac = tau * dot3(Ma, Mc) - ma * mc;
     double scc = tau * dot3(Mc, Mc) - mc * mc;
     double sq = sqrt(D);
+    if (mc > 0.0 && scc < 0.0) {
+        // The ellipsoid lies in front of the camera (its depth extent
+        // sqrt(tau |M_c|^2) is below the mean's depth): both bounding angles
+        // are in (-pi/2, pi/2), where the tangent is monotonic, and the
+        // tangent of each angle atan2(s_ac +- sqrt(D), s_cc) is the quotient
+        // itself.
+        double r1 = (sac + sq) / scc, r2 = (sac - sq) / scc;
+        lo = fmax(fmin(r1, r2), -kBoundTan);
+        hi = fmin(fmax(r1, r2), kBoundTan);
+        return lo < hi;
+    }
     double ra = atan2(sac + sq, scc);
     double rb = atan2(sac - sq, scc);
     double tm = atan2(ma, mc);
@@ -57,8 +72,8 @@ __device__ bool view_bounds(const double *Ma, const double *Mc, double ma, doubl
     t1 = fmax(t1, -0.5 * kPi + kBoundEps);
     t2 = fmin(t2, 0.5 * kPi - kBoundEps);
     if (!(t1 < t2)) return false;
-    lo = t1;
-    hi = t2;
+    lo = tan(t1);
+    hi = tan(t2);
     return true;
 }
 
@@ -170,14 +185,14 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
     int x0 = 0, x1 = cam.tiles_x, y0 = 0, y1 = cam.tiles_y;
     float4 box = make_float4(-INFINITY, INFINITY, -INFINITY, INFINITY);
     if (!fullx) {
-        double px_lo = cam.cx + cam.fx * tan(tx_lo) - 1e-3, px_hi = cam.cx + cam.fx * tan(tx_hi) + 1e-3;
+        double px_lo = cam.cx + cam.fx * tx_lo - 1e-3, px_hi = cam.cx + cam.fx * tx_hi + 1e-3;
         x0 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_lo / kTile)));
         x1 = (int)fmax(0.0, fmin((double)cam.tiles_x, floor(px_hi / kTile) + 1.0));
         box.x = (float)px_lo;
         box.y = (float)px_hi;
     }
     if (!fully) {
-        double py_lo = cam.cy + cam.fy * tan(ty_lo) - 1e-3, py_hi = cam.cy + cam.fy * tan(ty_hi) + 1e-3;
+        double py_lo = cam.cy + cam.fy * ty_lo - 1e-3, py_hi = cam.cy + cam.fy * ty_hi + 1e-3;
         y0 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_lo / kTile)));
         y1 = (int)fmax(0.0, fmin((double)cam.tiles_y, floor(py_hi / kTile) + 1.0));
         box.z = (float)py_lo;
