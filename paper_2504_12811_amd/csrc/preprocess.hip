@@ -151,7 +151,10 @@ __device__ __forceinline__ bool mean_in_view(const TileGeom<double> &g, const Ca
 // per batch.  Returns true when the item is visible so far but its mean
 // lies outside the view pyramid: the cull of Sec. 3.4 against the whole view
 // is then left to k_view_cull (its double-precision pyramid minimum needs
-// more registers than the rest of this pass).
+// more registers than the rest of this pass).  The SH degree is a template
+// parameter, so that the colour's coefficient loads unroll and are all in
+// flight together.
+template <int DEG>
 __device__ bool preprocess_item(const PreArgs &a, int64_t item)
 {
     const int64_t i = item / a.nviews;
@@ -205,16 +208,6 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
     TileGeom<double> g;
     build_geom(S, cam, x0, x1, y0, y1, g);
     const bool pending = !mean_in_view(g, cam);
-    // colour from real SH along the camera->mean direction
-    double Y[16];
-    sh_eval(a.sh_degree, d[0], d[1], d[2], Y);
-    const int nb = (a.sh_degree + 1) * (a.sh_degree + 1);
-    float col[3];
-    for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.5;
-        for (int b = 0; b < nb; ++b) acc += Y[b] * (double)a.sh[((int64_t)b * 3 + ch) * n + i];
-        col[ch] = (float)fmax(acc, 0.0);
-    }
     float4 *rec = a.rec + (size_t)item * kRecQuads;
     rec[0] = make_float4(g.c0[0], g.c0[1], g.c0[2], g.c1[0]);
     rec[1] = make_float4(g.c1[1], g.c1[2], g.c2[0], g.c2[1]);
@@ -225,7 +218,6 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
     // prefilter level slightly above tau so that it never rejects an
     // evaluation the exact alpha test would accept
     rec[6] = make_float4((float)(tau * (1.0 + 1e-4) + 1e-6), (float)tau, (float)og2, 0.f);
-    rec[7] = make_float4(col[0], col[1], col[2], 0.f);
     float4 *cu = a.cull + (size_t)item * kCullQuads;
     cu[0] = make_float4(g.dx0, g.dx1, g.dy0, g.dy1);
     cu[1] = make_float4(g.nx0[0], g.nx0[1], g.nx0[2], g.nx1[0]);
@@ -239,6 +231,23 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
     a.bbox[item] = box;
     a.area[item] = (uint32_t)((x1 - x0) * (y1 - y0));
     a.status[item] = kVisible;
+    // colour from real SH along the camera->mean direction (after the
+    // geometry is stored, so that its registers are free for the loads)
+    constexpr int nb = (DEG + 1) * (DEG + 1);
+    float c[3 * nb];
+#pragma unroll
+    for (int k = 0; k < 3 * nb; ++k) c[k] = a.sh[(int64_t)k * n + i];  // coefficient b, channel ch at k = 3 b + ch
+    double Y[16];
+    sh_eval(DEG, d[0], d[1], d[2], Y);
+    float col[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.5;
+#pragma unroll
+        for (int b = 0; b < nb; ++b) acc += Y[b] * (double)c[3 * b + ch];
+        col[ch] = (float)fmax(acc, 0.0);
+    }
+    rec[7] = make_float4(col[0], col[1], col[2], 0.f);
     return pending;
 }
 
@@ -246,13 +255,14 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
 // (pending[256 b + k], k < pending_n[b]) for k_view_cull.  Four waves per
 // SIMD (128 VGPRs, a few spilled) hide the double-precision latency better
 // than three.
+template <int DEG>
 __global__ __launch_bounds__(256, 4) void k_preprocess(PreArgs a)
 {
     __shared__ uint32_t n_pend;
     if (threadIdx.x == 0) n_pend = 0;
     __syncthreads();
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool pend = item < a.n * a.nviews && preprocess_item(a, item);
+    const bool pend = item < a.n * a.nviews && preprocess_item<DEG>(a, item);
     const uint64_t m = __ballot(pend);
     uint32_t base = 0;
     if (__lane_id() == 0 && m) base = atomicAdd(&n_pend, (uint32_t)__popcll(m));
@@ -313,7 +323,12 @@ hipError_t launch_preprocess(const PreArgs &a, hipStream_t s)
 {
     if (a.n <= 0 || a.nviews <= 0) return hipSuccess;
     int64_t blocks = (a.n * a.nviews + 255) / 256;
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    switch (a.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, dim3((unsigned)blocks), dim3(256), 0, s, a); break;
+    }
     hipLaunchKernelGGL(k_view_cull, dim3((unsigned)((blocks + kViewCullGroup - 1) / kViewCullGroup)), dim3(256), 0, s,
                        a, blocks);
     return hipGetLastError();
