@@ -76,7 +76,7 @@ uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 
 
 struct Layout {
     size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, bwd_list, keep_bits, chunk_item, chunk_cnt, kept_before, chunk_scan_tmp, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
-        ranges, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
+        ranges, seg_long, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
 uint64_t summary_words(const Shape &sh, uint64_t mp) { return ((mp / 64 + (uint64_t)sh.total_tiles + 2) / 64 + 1) * 256; }
@@ -117,6 +117,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.vals_alt = take(mp * 4);
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
     L.ranges = take((size_t)sh.total_tiles * 4 * 8);  // per tile, or per 8x8 sub-tile with AAA_SUBTILE_SORT
+    L.seg_long = take((size_t)sh.total_tiles * 4 * 4);  // lists queued for the long segment sort
     L.long_tiles = take((size_t)sh.total_tiles * 4);
     L.masks = take((mp / 64 + (uint64_t)sh.total_tiles + 2) * 256 * 8);  // per-pixel masks of long lists
     L.summary = take(summary_words(sh, mp) * 8);
@@ -138,8 +139,9 @@ int key_bits(int64_t ntiles)
     return 32 + b;
 }
 
-// The sort runs ceil(bits/8) passes, ping-ponging between the two buffers.
-bool sorted_in_alt(int64_t ntiles) { return ((key_bits(ntiles) + 7) / 8) % 2 == 1; }
+// The pair sort runs ceil(list bits / 8) LSD passes over the high word,
+// ping-ponging between the two buffers, then sorts each list in place.
+bool sorted_in_alt(int64_t ntiles) { return ((key_bits(ntiles) - 32 + 7) / 8) % 2 == 1; }
 
 int check_camera(const aaa_camera *cam)
 {
@@ -323,7 +325,7 @@ struct aaa_ctx {
     void *slots_static;
     // AAA_TIMING: two sets of stage events (frame i uses set i % 2); a set is
     // folded into the totals once a later frame has synchronised past it.
-    static constexpr int kEvents = 9;
+    static constexpr int kEvents = 10;
     hipEvent_t ev[2][kEvents];
     bool pending[2];
     int cur;
@@ -337,13 +339,16 @@ void fold_events(aaa_ctx *c, int set)
 {
     if (!c->pending[set]) return;
     hipEvent_t *e = c->ev[set];
-    // e0 start | preprocess | e1 | count | e2 | scan | e3 .. host wait .. e4 | write | e5 | sort | e6 | ranges | e7 | blend | e8
-    const int a[AAA_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 7, 0};
-    const int b[AAA_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 8, 8};
+    // e0 start | preprocess | e1 | count | e2 | scan | e3 .. host wait .. e4 | write | e5 | sort (list bits) | e6 |
+    // ranges | e7 | sort (within lists) | e8 | blend | e9
+    const int a[AAA_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 8, 0};
+    const int b[AAA_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 9, 9};
     for (int k = 0; k < AAA_NUM_STAGES; ++k) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, e[a[k]], e[b[k]]) == hipSuccess) c->total_ms[k] += t;
     }
+    float t2 = 0.f;  // the sort's second phase
+    if (hipEventElapsedTime(&t2, e[7], e[8]) == hipSuccess) c->total_ms[4] += t2;
     c->frames++;
     c->pending[set] = false;
 }
@@ -504,7 +509,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8]
+    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8], long-list count of the sort [9]
 
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
@@ -549,12 +554,13 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
                                     chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads,
                                     tile_cull, subtile, s));
     STAGE_MARK(5);
+    // pair sort, phase 1: LSD passes over the list bits (the high word)
     bool in_alt = false;
-    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 0, key_bits(nlists), at<void>(ws, L.sort_tmp), s,
+    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 32, key_bits(nlists), at<void>(ws, L.sort_tmp), s,
                                   &in_alt));
     if (P > 1 && in_alt != sorted_in_alt(nlists)) return fail(AAA_ERR_HIP, "internal: sort parity");
-    const uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
-    const uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
+    uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
+    uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
     if (P <= 1 && sorted_in_alt(nlists)) {
         // keep the invariant "sorted pairs live where sorted_in_alt says"
         HIP_TRY(hipMemcpyAsync(keys_alt, keys, P * 8, hipMemcpyDeviceToDevice, s));
@@ -566,6 +572,11 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint32_t *ranges = at<uint32_t>(ws, L.ranges);
     HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s));
     STAGE_MARK(7);
+    // phase 2: each list sorted by the depth key in place (the other pair
+    // buffer is scratch for very long lists)
+    HIP_TRY(aaa::launch_segment_sort(skeys, svals, skeys == keys ? keys_alt : keys, svals == vals ? vals_alt : vals, P,
+                                     ranges, nlists, at<uint32_t>(ws, L.seg_long), (uint32_t *)(ctr + 9), s));
+    STAGE_MARK(8);
 
     aaa::BlendArgs ba;
     ba.rec = pa.rec;
@@ -611,7 +622,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
         HIP_TRY(aaa::launch_blend(ba, K, want_stats, false, s));
     }
     if (timing) {
-        STAGE_MARK(8);
+        STAGE_MARK(9);
         ctx->pending[ctx->cur] = true;
         ctx->cur ^= 1;
     }

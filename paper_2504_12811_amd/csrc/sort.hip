@@ -15,6 +15,8 @@
 // stages its pairs in LDS in digit order (wave order, then rank: stable) and
 // writes each digit's run to consecutive global positions from the digit's
 // global prefix, so stores coalesce.
+#include <algorithm>
+
 #include "aaa_internal.h"
 
 namespace aaa {
@@ -212,6 +214,299 @@ __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t
     if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[2 * (uint64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
+
+// --------------------------------------------------------- segment sort
+//
+// Second phase of the pair sort.  The LSD passes over the high word of the
+// keys (the list number) leave every list a contiguous run in pair-writing
+// order; each run is then sorted by the low word (the depth key), stably,
+// which gives the order of a full LSD sort of the 64-bit keys.  One
+// workgroup per list:
+//  - k_seg_small (4 waves): runs of 2..kSegSmall entries, in registers and
+//    LDS; longer runs are queued for
+//  - k_seg_large (16 waves): runs up to kSegLarge entries the same way,
+//    longer runs by 8-bit LSD passes over the run in global memory (the
+//    other pair buffer holds the intermediate order), in chunks of
+//    kSegLarge.
+// Entries sit in registers, kSegItems per thread: wave w holds entries
+// w S + 64 r + lane (r < S / 64) of the run or chunk, so that wave order,
+// then round, then lane is entry order.  A pass ranks each entry among the
+// equal digits of its wave (ballot match, as in k_scatter), scans the
+// per-wave digit counts in (digit, wave) order and moves the entries
+// through LDS to their new places.  A pass whose digit is the same for
+// every entry of the run is skipped.
+
+constexpr int kSegItems = 8;
+constexpr int kSegSmall = 4 * 64 * kSegItems;    // 2048
+constexpr int kSegLarge = 16 * 64 * kSegItems;   // 8192
+
+template <int W>
+struct SegShared {
+    uint32_t cnt[W][kBins];   // per-wave digit counts, then per-wave prefixes
+    uint32_t lbase[kBins];    // start of each digit in the run or chunk
+    uint32_t tot[kBins];      // digit totals of the run or chunk
+    uint32_t wsum[4];
+    uint32_t skip[4];         // per pass: one digit holds the whole run (set once, never reset)
+    uint32_t key[W * 64 * kSegItems];
+    uint32_t val[W * 64 * kSegItems];
+};
+
+// Rank the wave's valid entries (e < m) by digit; per-wave counts in
+// sh.cnt[wave].  Returns the digits and ranks in d[] and rank[].
+template <int W>
+__device__ __forceinline__ void seg_rank(SegShared<W> &sh, const uint32_t (&k)[kSegItems], uint32_t e0, uint32_t m,
+                                         int shift, int rounds, uint32_t (&d)[kSegItems], uint32_t (&rank)[kSegItems])
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+        if (r >= rounds) break;
+        const bool valid = e0 + (uint32_t)(r * 64 + lane) < m;
+        const uint32_t dg = (k[r] >> shift) & (kBins - 1);
+        d[r] = dg;
+        uint64_t mm = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kBits; ++b) {
+            const uint64_t bb = __ballot((dg >> b) & 1u);
+            mm &= ((dg >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t before = (uint32_t)__popcll(mm & lt);
+        uint32_t base = 0;
+        if (valid) base = sh.cnt[wave][dg];
+        rank[r] = base + before;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) sh.cnt[wave][dg] = base + (uint32_t)__popcll(mm);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Threads of digits t < 256 (the first four waves): per-wave prefixes in
+// sh.cnt, totals in sh.tot, exclusive digit starts in sh.lbase; *flag (if
+// given) set when one digit holds all m entries.  Ends with a barrier.
+template <int W>
+__device__ __forceinline__ void seg_scan(SegShared<W> &sh, uint32_t m, uint32_t *flag)
+{
+    const int t = threadIdx.x, lane = t & 63;
+    if (t < kBins) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint32_t c = sh.cnt[w][t];
+            sh.cnt[w][t] = tot;
+            tot += c;
+        }
+        sh.tot[t] = tot;
+        if (flag && tot == m) *flag = 1u;
+        uint32_t x = tot;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) sh.wsum[t >> 6] = x;
+        sh.lbase[t] = x - tot;  // wave-local so far
+    }
+    __syncthreads();
+    if (t < kBins) {
+        uint32_t wpre = 0;
+        for (int w = 0; w < (t >> 6); ++w) wpre += sh.wsum[w];
+        sh.lbase[t] += wpre;
+    }
+    __syncthreads();
+}
+
+// One in-LDS pass over m <= W * 512 register-resident entries.
+template <int W>
+__device__ __forceinline__ void seg_pass(SegShared<W> &sh, uint32_t (&k)[kSegItems], uint32_t (&v)[kSegItems],
+                                         uint32_t m, int shift, uint32_t S)
+{
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int rounds = (int)(S / 64);
+    const uint32_t e0 = (uint32_t)wave * S;
+    for (int i = t; i < W * kBins; i += W * 64) (&sh.cnt[0][0])[i] = 0u;
+    __syncthreads();
+    uint32_t d[kSegItems], rank[kSegItems];
+    seg_rank<W>(sh, k, e0, m, shift, rounds, d, rank);
+    __syncthreads();
+    seg_scan<W>(sh, m, &sh.skip[shift / kBits]);
+    if (sh.skip[shift / kBits]) return;  // uniform: every entry has the same digit
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+        if (r >= rounds) break;
+        if (e0 + (uint32_t)(r * 64 + lane) < m) {
+            const uint32_t pos = sh.lbase[d[r]] + sh.cnt[wave][d[r]] + rank[r];
+            sh.key[pos] = k[r];
+            sh.val[pos] = v[r];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+        if (r >= rounds) break;
+        const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
+        if (e < m) {
+            k[r] = sh.key[e];
+            v[r] = sh.val[e];
+        }
+    }
+    __syncthreads();
+}
+
+// Sort a run of m <= W * 512 entries at keys/vals + start in place.
+template <int W>
+__device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                             uint64_t start, uint32_t m, uint64_t hi)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // per-wave segment: a multiple of 64, at most 512
+    const uint32_t S = ((m + W * 64 - 1) / (W * 64)) * 64;
+    const uint32_t e0 = (uint32_t)wave * S;
+    if (threadIdx.x < 4) sh.skip[threadIdx.x] = 0u;  // ordered by the first pass's barrier
+    uint32_t k[kSegItems], v[kSegItems];
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+        const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
+        const bool ok = r * 64 < (int)S && e < m;
+        k[r] = ok ? (uint32_t)keys[start + e] : 0u;
+        v[r] = ok ? vals[start + e] : 0u;
+    }
+    for (int shift = 0; shift < 32; shift += kBits) seg_pass<W>(sh, k, v, m, shift, S);
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) {
+        const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
+        if (r * 64 < (int)S && e < m) {
+            keys[start + e] = hi | k[r];
+            vals[start + e] = v[r];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_seg_small(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                   const uint32_t *__restrict__ ranges, uint32_t nlists,
+                                                   uint32_t *__restrict__ long_lists, uint32_t *__restrict__ n_long)
+{
+    __shared__ SegShared<4> sh;
+    const uint32_t list = blockIdx.x;
+    if (list >= nlists) return;
+    const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
+    const uint32_t m = end > start ? end - start : 0u;
+    if (m > (uint32_t)kSegSmall) {
+        if (threadIdx.x == 0) long_lists[atomicAdd(n_long, 1u)] = list;
+        return;
+    }
+    if (m < 2) return;
+    seg_sort_lds<4>(sh, keys, vals, start, m, (uint64_t)list << 32);
+}
+
+// Runs longer than kSegLarge: LSD passes over the run in global memory,
+// chunk after chunk (stable), ping-ponging with the other buffer; a copy
+// brings the result back when an odd number of passes moved it.
+__device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                uint64_t *__restrict__ keys_alt, uint32_t *__restrict__ vals_alt, uint64_t start,
+                                uint32_t m, uint64_t hi)
+{
+    constexpr int W = 16;
+    __shared__ uint32_t hist[kBins], run[kBins];
+    __shared__ uint32_t gbase[kBins];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int nthr = W * 64;
+    uint64_t *ksrc = keys, *kdst = keys_alt;
+    uint32_t *vsrc = vals, *vdst = vals_alt;
+    int moved = 0;
+    if (t < 4) sh.skip[t] = 0u;
+    for (int shift = 0; shift < 32; shift += kBits) {
+        uint32_t *skip = &sh.skip[shift / kBits];
+        // digit totals of the whole run
+        if (t < kBins) hist[t] = 0u;
+        __syncthreads();
+        for (uint32_t e = t; e < m; e += nthr) atomicAdd(&hist[((uint32_t)ksrc[start + e] >> shift) & (kBins - 1)], 1u);
+        __syncthreads();
+        if (t < kBins) {
+            const uint32_t c = hist[t];
+            if (c == m) *skip = 1u;
+            uint32_t x = c;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off);
+                if (lane >= off) x += y;
+            }
+            if (lane == 63) sh.wsum[t >> 6] = x;
+            gbase[t] = x - c;
+            run[t] = 0u;
+        }
+        __syncthreads();
+        if (*skip) continue;  // uniform
+        if (t < kBins) {
+            uint32_t wpre = 0;
+            for (int w = 0; w < (t >> 6); ++w) wpre += sh.wsum[w];
+            gbase[t] += wpre;
+        }
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < m; c0 += (uint32_t)kSegLarge) {
+            const uint32_t mc = m - c0 < (uint32_t)kSegLarge ? m - c0 : (uint32_t)kSegLarge;
+            const uint32_t e0 = (uint32_t)wave * 512u;
+            uint32_t k[kSegItems], v[kSegItems], d[kSegItems], rank[kSegItems];
+#pragma unroll
+            for (int r = 0; r < kSegItems; ++r) {
+                const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
+                k[r] = e < mc ? (uint32_t)ksrc[start + c0 + e] : 0u;
+                v[r] = e < mc ? vsrc[start + c0 + e] : 0u;
+            }
+            for (int i = t; i < W * kBins; i += nthr) (&sh.cnt[0][0])[i] = 0u;
+            __syncthreads();
+            seg_rank<W>(sh, k, e0, mc, shift, kSegItems, d, rank);
+            __syncthreads();
+            seg_scan<W>(sh, mc, nullptr);
+            // stage in digit order, then write each digit's run to its place
+#pragma unroll
+            for (int r = 0; r < kSegItems; ++r) {
+                if (e0 + (uint32_t)(r * 64 + lane) < mc) {
+                    const uint32_t pos = sh.lbase[d[r]] + sh.cnt[wave][d[r]] + rank[r];
+                    sh.key[pos] = k[r];
+                    sh.val[pos] = v[r];
+                }
+            }
+            __syncthreads();
+            for (uint32_t i = t; i < mc; i += nthr) {
+                const uint32_t kk = sh.key[i];
+                const uint32_t dg = (kk >> shift) & (kBins - 1);
+                const uint64_t pos = start + gbase[dg] + run[dg] + (i - sh.lbase[dg]);
+                kdst[pos] = hi | kk;
+                vdst[pos] = sh.val[i];
+            }
+            __syncthreads();
+            if (t < kBins) run[t] += sh.tot[t];
+            __syncthreads();
+        }
+        uint64_t *tk = ksrc; ksrc = kdst; kdst = tk;
+        uint32_t *tv = vsrc; vsrc = vdst; vdst = tv;
+        ++moved;
+    }
+    if (moved & 1) {
+        for (uint32_t e = t; e < m; e += nthr) {
+            keys[start + e] = keys_alt[start + e];
+            vals[start + e] = vals_alt[start + e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_seg_large(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                    uint64_t *__restrict__ keys_alt, uint32_t *__restrict__ vals_alt,
+                                                    const uint32_t *__restrict__ ranges,
+                                                    const uint32_t *__restrict__ long_lists,
+                                                    const uint32_t *__restrict__ n_long)
+{
+    __shared__ SegShared<16> sh;
+    if (blockIdx.x >= *n_long) return;
+    const uint32_t list = long_lists[blockIdx.x];
+    const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
+    const uint32_t m = end - start;
+    const uint64_t hi = (uint64_t)list << 32;
+    if (m <= (uint32_t)kSegLarge)
+        seg_sort_lds<16>(sh, keys, vals, start, m, hi);
+    else
+        seg_sort_global(sh, keys, vals, keys_alt, vals_alt, start, m, hi);
+}
+
 }  // namespace
 
 static uint32_t sort_blocks(uint64_t n) { return (uint32_t)((n + kPerBlock - 1) / kPerBlock); }
@@ -249,6 +544,21 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
         *result_in_alt = !*result_in_alt;
     }
     return hipSuccess;
+}
+
+hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
+                               const uint32_t *ranges, int64_t nlists, uint32_t *long_lists, uint32_t *n_long,
+                               hipStream_t s)
+{
+    if (n <= 1 || nlists <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_small, dim3((unsigned)nlists), dim3(256), 0, s, keys, vals, ranges, (uint32_t)nlists,
+                       long_lists, n_long);
+    // at most n / (kSegSmall + 1) runs are longer than kSegSmall
+    const uint64_t bound = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
+    if (bound)
+        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)bound), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
+                           (const uint32_t *)long_lists, (const uint32_t *)n_long);
+    return hipGetLastError();
 }
 
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s)

@@ -92,6 +92,39 @@ def test_ood_3m_far_zoom_long_route_sampled(ras, ood):
     compare_image(ras, scene, cam, S.Settings(), tile_sel=sel, label="3M far zoom")
 
 
+@pytest.mark.parametrize("view", ["primary", "zoom2", "zoom4"])
+def test_pair_order_long_lists(ras, ood, view):
+    """The pair sort in its two phases (LSD passes over the list number, then
+    each list sorted by its depth key: in LDS up to 8192 entries, by passes
+    over the list in global memory beyond) must leave the order of a full
+    stable sort: keys ascending and, within equal keys, Gaussians in
+    increasing order, each list's entries inside its range.  (List,
+    Gaussian) pairs are unique, so strict increase of (key, Gaussian) also
+    rules out a lost or repeated entry.  The 3M primary view has lists of
+    2k-18k entries, the zoomed views a few lists of 10^5."""
+    scene, cam0, zoom = ood
+    cam = {"primary": cam0, "zoom2": zoom[2], "zoom4": zoom[4]}[view]
+    from test_gpu_forward import dev
+    ds = dev(scene)
+    ras.render(ds, cam, S.Settings())
+    keys, vals, ranges = ras.read_pairs(ds, cam)
+    k = keys.cpu().numpy().view(np.uint64)
+    v = vals.cpu().numpy().view(np.uint32)
+    rg = ranges.cpu().numpy().astype(np.int64)
+    ln = rg[:, 1] - rg[:, 0]
+    print(f"[{view}] pairs={k.size} longest lists {np.sort(ln)[-3:].tolist()} "
+          f"lists over 2048: {(ln > 2048).sum()}, over 8192: {(ln > 8192).sum()}", flush=True)
+    assert ln.max() > 8192
+    assert ln.sum() == k.size
+    inc = (k[1:] > k[:-1]) | ((k[1:] == k[:-1]) & (v[1:] > v[:-1]))
+    assert inc.all(), f"{(~inc).sum()} adjacent pairs out of order"
+    # sorted keys: the first and last entry of each range carry the list's number
+    full = np.nonzero(ln > 0)[0]
+    lists = k >> np.uint64(32)
+    assert np.array_equal(lists[rg[full, 0]], full.astype(np.uint64))
+    assert np.array_equal(lists[rg[full, 1] - 1], full.astype(np.uint64))
+
+
 def test_720p_16_view_batch_sampled(ras):
     from test_gpu_forward import dev, check_image
     scene, cams = S.fwd_bwd_scene()
