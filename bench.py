@@ -192,15 +192,15 @@ def main():
     # HBM-bound stages, algorithmic bytes: the preprocess reads the 12
     # non-SH floats of every Gaussian and writes its status, and reads the SH
     # coefficients and writes a ~96-byte render record only for the visible
-    # ones; the sort reads every key once for the histograms (8 B) and reads
-    # and writes key and value once per 8-bit pass (24 B)
+    # ones; the sort's passes over the list bits read every key for the
+    # histogram (8 B) and read and write key and value (24 B), then the
+    # per-list sort reads and writes each pair once more (24 B)
     n = ds.n
     sh_floats = 3 * (scene.sh_degree + 1) ** 2
     pre_bytes = n * (4 * 12 + 4) + VIS.mean() * (4 * sh_floats + 96)
     ntiles = cams[0].tiles[0] * cams[0].tiles[1]
-    bits = 32 + int(np.ceil(np.log2(ntiles)))
-    passes = (bits + 7) // 8
-    sort_bytes = P.mean() * (8 + 24 * passes)
+    passes = (int(np.ceil(np.log2(ntiles))) + 7) // 8
+    sort_bytes = P.mean() * (32 * passes + 24)
     pre_ms = stage_ms["preprocess"] / frames
     sort_ms = stage_ms["sort"] / frames
 

@@ -287,10 +287,10 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
                             int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt);
 // Phase 2 of the pair sort: every list [ranges[2 l], ranges[2 l + 1]) of
 // keys/vals sorted in place by the low word of its keys (stable); the other
-// buffers are scratch for lists longer than 8192 entries.  long_lists holds
-// nlists entries; *n_long must be zero.
+// buffers are scratch for lists longer than 8192 entries.  queues holds
+// 2 nlists entries; n_queued[0..1] must be zero.
 hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
-                               const uint32_t *ranges, int64_t nlists, uint32_t *long_lists, uint32_t *n_long,
+                               const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
                                hipStream_t s);
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
 

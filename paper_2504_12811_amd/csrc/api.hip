@@ -117,7 +117,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.vals_alt = take(mp * 4);
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
     L.ranges = take((size_t)sh.total_tiles * 4 * 8);  // per tile, or per 8x8 sub-tile with AAA_SUBTILE_SORT
-    L.seg_long = take((size_t)sh.total_tiles * 4 * 4);  // lists queued for the long segment sort
+    L.seg_long = take((size_t)sh.total_tiles * 8 * 4);  // the two queues of lists for the longer segment sorts
     L.long_tiles = take((size_t)sh.total_tiles * 4);
     L.masks = take((mp / 64 + (uint64_t)sh.total_tiles + 2) * 256 * 8);  // per-pixel masks of long lists
     L.summary = take(summary_words(sh, mp) * 8);
@@ -509,7 +509,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8], long-list count of the sort [9]
+    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8], the sort's queue counts [9]
 
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));

@@ -222,8 +222,9 @@ __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t
 // order; each run is then sorted by the low word (the depth key), stably,
 // which gives the order of a full LSD sort of the 64-bit keys.  One
 // workgroup per list:
-//  - k_seg_small (4 waves): runs of 2..kSegSmall entries, in registers and
+//  - k_seg_first (1 wave): runs of 2..kSegWave entries, in registers and
 //    LDS; longer runs are queued for
+//  - k_seg_mid (4 waves): runs up to kSegSmall entries the same way, or
 //  - k_seg_large (16 waves): runs up to kSegLarge entries the same way,
 //    longer runs by 8-bit LSD passes over the run in global memory (the
 //    other pair buffer holds the intermediate order), in chunks of
@@ -237,14 +238,15 @@ __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t
 // every entry of the run is skipped.
 
 constexpr int kSegItems = 8;
+constexpr int kSegWave = 64 * kSegItems;         // 512
 constexpr int kSegSmall = 4 * 64 * kSegItems;    // 2048
 constexpr int kSegLarge = 16 * 64 * kSegItems;   // 8192
 
 template <int W>
 struct SegShared {
-    uint32_t cnt[W][kBins];   // per-wave digit counts, then per-wave prefixes
-    uint32_t lbase[kBins];    // start of each digit in the run or chunk
-    uint32_t tot[kBins];      // digit totals of the run or chunk
+    alignas(16) uint32_t cnt[W][kBins];   // per-wave digit counts, then per-wave prefixes
+    alignas(16) uint32_t lbase[kBins];    // start of each digit in the run or chunk
+    alignas(16) uint32_t tot[kBins];      // digit totals of the run or chunk
     uint32_t wsum[4];
     uint32_t skip[4];         // per pass: one digit holds the whole run (set once, never reset)
     uint32_t key[W * 64 * kSegItems];
@@ -281,36 +283,40 @@ __device__ __forceinline__ void seg_rank(SegShared<W> &sh, const uint32_t (&k)[k
     }
 }
 
-// Threads of digits t < 256 (the first four waves): per-wave prefixes in
-// sh.cnt, totals in sh.tot, exclusive digit starts in sh.lbase; *flag (if
-// given) set when one digit holds all m entries.  Ends with a barrier.
+// Lane l of the first wave owns digits 4 l .. 4 l + 3: per-wave prefixes in
+// sh.cnt, totals in sh.tot, exclusive digit starts in sh.lbase (a lane-local
+// prefix, then one scan over the wave); *flag (if given) set when one digit
+// holds all m entries.  Ends with a barrier.
 template <int W>
 __device__ __forceinline__ void seg_scan(SegShared<W> &sh, uint32_t m, uint32_t *flag)
 {
-    const int t = threadIdx.x, lane = t & 63;
-    if (t < kBins) {
-        uint32_t tot = 0;
+    const int t = threadIdx.x;
+    if (t < 64) {
+        uint4 tot = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const uint32_t c = sh.cnt[w][t];
-            sh.cnt[w][t] = tot;
-            tot += c;
+            uint4 *row = (uint4 *)&sh.cnt[w][4 * t];
+            const uint4 c = *row;
+            *row = tot;
+            tot.x += c.x;
+            tot.y += c.y;
+            tot.z += c.z;
+            tot.w += c.w;
         }
-        sh.tot[t] = tot;
-        if (flag && tot == m) *flag = 1u;
-        uint32_t x = tot;
+        *(uint4 *)&sh.tot[4 * t] = tot;
+        if (flag && (tot.x == m || tot.y == m || tot.z == m || tot.w == m)) *flag = 1u;
+        const uint32_t mine = tot.x + tot.y + tot.z + tot.w;
+        uint32_t x = mine;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
+            if (t >= off) x += y;
         }
-        if (lane == 63) sh.wsum[t >> 6] = x;
-        sh.lbase[t] = x - tot;  // wave-local so far
-    }
-    __syncthreads();
-    if (t < kBins) {
-        uint32_t wpre = 0;
-        for (int w = 0; w < (t >> 6); ++w) wpre += sh.wsum[w];
-        sh.lbase[t] += wpre;
+        uint4 lb;
+        lb.x = x - mine;
+        lb.y = lb.x + tot.x;
+        lb.z = lb.y + tot.y;
+        lb.w = lb.z + tot.z;
+        *(uint4 *)&sh.lbase[4 * t] = lb;
     }
     __syncthreads();
 }
@@ -367,7 +373,7 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     for (int r = 0; r < kSegItems; ++r) {
         const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
         const bool ok = r * 64 < (int)S && e < m;
-        k[r] = ok ? (uint32_t)keys[start + e] : 0u;
+        k[r] = ok ? ((const uint32_t *)(keys + start + e))[0] : 0u;  // the low (depth) word
         v[r] = ok ? vals[start + e] : 0u;
     }
     for (int shift = 0; shift < 32; shift += kBits) seg_pass<W>(sh, k, v, m, shift, S);
@@ -381,21 +387,38 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     }
 }
 
-__global__ __launch_bounds__(256) void k_seg_small(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                   const uint32_t *__restrict__ ranges, uint32_t nlists,
-                                                   uint32_t *__restrict__ long_lists, uint32_t *__restrict__ n_long)
+__global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                  const uint32_t *__restrict__ ranges, uint32_t nlists,
+                                                  uint32_t *__restrict__ queue_mid, uint32_t *__restrict__ queue_large,
+                                                  uint32_t *__restrict__ n_queued)
 {
-    __shared__ SegShared<4> sh;
+    __shared__ SegShared<1> sh;
     const uint32_t list = blockIdx.x;
     if (list >= nlists) return;
     const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
     const uint32_t m = end > start ? end - start : 0u;
-    if (m > (uint32_t)kSegSmall) {
-        if (threadIdx.x == 0) long_lists[atomicAdd(n_long, 1u)] = list;
+    if (m > (uint32_t)kSegWave) {
+        if (threadIdx.x == 0) {
+            if (m > (uint32_t)kSegSmall)
+                queue_large[atomicAdd(&n_queued[1], 1u)] = list;
+            else
+                queue_mid[atomicAdd(&n_queued[0], 1u)] = list;
+        }
         return;
     }
     if (m < 2) return;
-    seg_sort_lds<4>(sh, keys, vals, start, m, (uint64_t)list << 32);
+    seg_sort_lds<1>(sh, keys, vals, start, m, (uint64_t)list << 32);
+}
+
+__global__ __launch_bounds__(256) void k_seg_mid(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                 const uint32_t *__restrict__ ranges, const uint32_t *__restrict__ queue,
+                                                 const uint32_t *__restrict__ n_queued)
+{
+    __shared__ SegShared<4> sh;
+    if (blockIdx.x >= *n_queued) return;
+    const uint32_t list = queue[blockIdx.x];
+    const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
+    seg_sort_lds<4>(sh, keys, vals, start, end - start, (uint64_t)list << 32);
 }
 
 // Runs longer than kSegLarge: LSD passes over the run in global memory,
@@ -492,12 +515,12 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
 __global__ __launch_bounds__(1024) void k_seg_large(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                     uint64_t *__restrict__ keys_alt, uint32_t *__restrict__ vals_alt,
                                                     const uint32_t *__restrict__ ranges,
-                                                    const uint32_t *__restrict__ long_lists,
-                                                    const uint32_t *__restrict__ n_long)
+                                                    const uint32_t *__restrict__ queue,
+                                                    const uint32_t *__restrict__ n_queued)
 {
     __shared__ SegShared<16> sh;
-    if (blockIdx.x >= *n_long) return;
-    const uint32_t list = long_lists[blockIdx.x];
+    if (blockIdx.x >= *n_queued) return;
+    const uint32_t list = queue[blockIdx.x];
     const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
     const uint32_t m = end - start;
     const uint64_t hi = (uint64_t)list << 32;
@@ -547,17 +570,22 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 }
 
 hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
-                               const uint32_t *ranges, int64_t nlists, uint32_t *long_lists, uint32_t *n_long,
+                               const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
                                hipStream_t s)
 {
     if (n <= 1 || nlists <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_small, dim3((unsigned)nlists), dim3(256), 0, s, keys, vals, ranges, (uint32_t)nlists,
-                       long_lists, n_long);
-    // at most n / (kSegSmall + 1) runs are longer than kSegSmall
-    const uint64_t bound = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
-    if (bound)
-        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)bound), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
-                           (const uint32_t *)long_lists, (const uint32_t *)n_long);
+    uint32_t *queue_mid = queues, *queue_large = queues + nlists;
+    hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists,
+                       queue_mid, queue_large, n_queued);
+    // at most n / (L + 1) runs are longer than L entries
+    const uint64_t mid = std::min<uint64_t>((uint64_t)nlists, n / (kSegWave + 1));
+    if (mid)
+        hipLaunchKernelGGL(k_seg_mid, dim3((unsigned)mid), dim3(256), 0, s, keys, vals, ranges,
+                           (const uint32_t *)queue_mid, (const uint32_t *)n_queued);
+    const uint64_t large = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
+    if (large)
+        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
+                           (const uint32_t *)queue_large, (const uint32_t *)(n_queued + 1));
     return hipGetLastError();
 }
 
