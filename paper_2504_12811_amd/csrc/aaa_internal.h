@@ -269,9 +269,11 @@ hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 
                               const uint32_t *chunk_item, const uint64_t *kept_before, uint64_t keep_cap,
                               uint64_t max_pairs, uint64_t *keys, uint32_t *vals, const float4 *bbox, bool quads,
                               bool tile_cull, bool subtile, hipStream_t s);
-// host[0] = *a, host[1] = *b (host: pinned host memory), visible to the host
-// once the stream has synchronised: one launch instead of two small copies
-hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, hipStream_t s);
+// host[0] = *a, host[1] = *b, host[3] = *note (then *note = 0; none when
+// note is null), then host[2] = seq (system scope, in that order; host:
+// coherent pinned memory): one launch instead of small copies
+hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, uint64_t seq, uint32_t *note,
+                           hipStream_t s);
 // p[i] &= mask for i < n
 hipError_t launch_and_u32(uint32_t *p, uint64_t n, uint32_t mask, hipStream_t s);
 size_t scan_tmp_bytes(int64_t n);
@@ -288,10 +290,13 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 // Phase 2 of the pair sort: every list [ranges[2 l], ranges[2 l + 1]) of
 // keys/vals sorted in place by the low word of its keys (stable); the other
 // buffers are scratch for lists longer than 8192 entries.  queues holds
-// 2 nlists entries; n_queued[0..1] must be zero.
+// 2 nlists entries; n_queued[0..1] must be zero.  *note is set to 1 when a
+// list is longer than kSortNoteList.
 hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                                const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
-                               hipStream_t s);
+                               uint32_t *note, hipStream_t s);
+// *note = 1 when a list of ranges is longer than kSortNoteList
+hipError_t launch_note_long_lists(const uint32_t *ranges, int64_t nlists, uint32_t *note, hipStream_t s);
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
 
 struct BlendArgs {
@@ -338,6 +343,11 @@ hipError_t launch_find_long(const BlendArgs &a, uint32_t *long_tiles, uint32_t *
 hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32_t *long_tiles, const uint32_t *n_long,
                              unsigned grid, uint64_t *pixmask, uint64_t *summary, uint64_t summary_words,
                              hipStream_t s);
+// Lists longer than this are sorted by one workgroup each in the per-list
+// phase of the pair sort, far below the chip's bandwidth; a frame that had
+// one makes the next frame of the same workspace use the full-width global
+// sort instead.
+constexpr uint32_t kSortNoteList = 32768;
 constexpr uint32_t kLongList = 4096;     // entries above which a forward tile is rendered by k_blend_long
 constexpr uint32_t kMaxLongTiles = 1024; // ... when at most this many tiles are that long
 

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+#include <chrono>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -117,7 +119,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.vals_alt = take(mp * 4);
     L.sort_tmp = take(aaa::sort_tmp_bytes(mp));
     L.ranges = take((size_t)sh.total_tiles * 4 * 8);  // per tile, or per 8x8 sub-tile with AAA_SUBTILE_SORT
-    L.seg_long = take((size_t)sh.total_tiles * 8 * 4);  // the two queues of lists for the longer segment sorts
+    L.seg_long = take((size_t)sh.total_tiles * 8 * 4);  // the two queues of lists for the longer per-list sorts
     L.long_tiles = take((size_t)sh.total_tiles * 4);
     L.masks = take((mp / 64 + (uint64_t)sh.total_tiles + 2) * 256 * 8);  // per-pixel masks of long lists
     L.summary = take(summary_words(sh, mp) * 8);
@@ -140,7 +142,9 @@ int key_bits(int64_t ntiles)
 }
 
 // The pair sort runs ceil(list bits / 8) LSD passes over the high word,
-// ping-ponging between the two buffers, then sorts each list in place.
+// ping-ponging between the two buffers, then sorts each list in place (or,
+// after a frame with very long lists, four more passes over the low word):
+// either way the result is in the buffer this parity names.
 bool sorted_in_alt(int64_t ntiles) { return ((key_bits(ntiles) - 32 + 7) / 8) % 2 == 1; }
 
 int check_camera(const aaa_camera *cam)
@@ -315,8 +319,10 @@ struct aaa_ctx {
     aaa::ViewDev *views_host;
     // training-camera table of K7: pinned staging and its device copy
     aaa::TrainCam *train_host, *train_dev;
-    // pinned words the device publishes before the host's one wait per call
+    // coherent pinned words the device publishes before the host's one wait
+    // per call ([0], [1] values, [2] the call's sequence number)
     uint64_t *sync_host;
+    uint64_t sync_seq;
     // second stream for the long-list blend, forked from and joined back to
     // the caller's stream with these events
     hipStream_t side;
@@ -334,6 +340,29 @@ struct aaa_ctx {
 };
 
 namespace {
+
+// Publishes two device words (and, with a note word, that word, which the
+// kernel then clears) to the host and waits for them: the kernel writes
+// them, then the call's sequence number, into coherent pinned memory; the
+// host spins on the number for up to 2 ms (a blocking stream wait adds its
+// wake-up latency, tens of microseconds, to every frame) and then falls back
+// to the blocking wait, which also reports stream errors.  In stream order
+// the kernel follows everything the call enqueued before.
+hipError_t publish_and_wait(aaa_ctx *c, const uint64_t *a, const uint64_t *b, hipStream_t s, uint32_t *note = nullptr)
+{
+    const uint64_t seq = ++c->sync_seq;
+    hipError_t e = aaa::launch_publish2(a, b, c->sync_host, seq, note, s);
+    if (e != hipSuccess) return e;
+    volatile uint64_t *flag = c->sync_host + 2;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned k = 0; *flag != seq; ++k) {
+        if ((k & 255u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+            return hipStreamSynchronize(s);
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return hipSuccess;
+}
 
 void fold_events(aaa_ctx *c, int set)
 {
@@ -378,13 +407,15 @@ int aaa_create(aaa_ctx **out, int device)
     c->train_host = nullptr;
     c->train_dev = nullptr;
     c->sync_host = nullptr;
+    c->sync_seq = 0;
     c->side = nullptr;
     c->fork = c->join = nullptr;
     hipError_t e = hipHostMalloc((void **)&c->views_host, sizeof(aaa::ViewDev) * kMaxViews, hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->train_host, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void **)&c->train_dev, sizeof(aaa::TrainCam) * AAA_MAX_TRAIN_CAMERAS);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->sync_host, 64, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->sync_host, 64, hipHostMallocCoherent);
+    if (e == hipSuccess) memset(c->sync_host, 0, 64);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
@@ -509,7 +540,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8], the sort's queue counts [9]
+    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8], the sort's queue counts [11..12]
 
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
@@ -535,10 +566,13 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s,
                                        area_off + items));
     STAGE_MARK(3);
-    HIP_TRY(aaa::launch_publish2(kept_before + chunks, area_off + items, ctx->sync_host, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // the note word (outside the counters cleared per call) is set by a call
+    // whose pair sort met a list longer than kSortNoteList
+    uint32_t *sort_note = (uint32_t *)(ctr + 20);
+    HIP_TRY(publish_and_wait(ctx, kept_before + chunks, area_off + items, s, sort_note));
     uint64_t P = ctx->sync_host[0];
     const uint64_t C = ctx->sync_host[1];
+    const bool long_lists_before = ctx->sync_host[3] != 0;
     if (C > keep_cap) P = std::max<uint64_t>(max_pairs + 1, (C + 7) / 8);  // buffer too small to even count
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -554,10 +588,17 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
                                     chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads,
                                     tile_cull, subtile, s));
     STAGE_MARK(5);
-    // pair sort, phase 1: LSD passes over the list bits (the high word)
+    // Pair sort.  Phase 1: LSD passes over the list bits (the high word);
+    // phase 2 (below) sorts each list by the depth word.  After a call of
+    // this workspace that met a list longer than kSortNoteList (far views:
+    // most pairs in a few lists, which phase 2 gives one workgroup each), the
+    // global passes run over the whole key instead and phase 2 is left out.
+    // Both give the order of a full stable sort of the 64-bit keys, and the
+    // same number of passes modulo 2 (32 bits are four passes).
+    const bool full_sort = long_lists_before;
     bool in_alt = false;
-    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 32, key_bits(nlists), at<void>(ws, L.sort_tmp), s,
-                                  &in_alt));
+    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, full_sort ? 0 : 32, key_bits(nlists),
+                                  at<void>(ws, L.sort_tmp), s, &in_alt));
     if (P > 1 && in_alt != sorted_in_alt(nlists)) return fail(AAA_ERR_HIP, "internal: sort parity");
     uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
     uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
@@ -573,9 +614,14 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s));
     STAGE_MARK(7);
     // phase 2: each list sorted by the depth key in place (the other pair
-    // buffer is scratch for very long lists)
-    HIP_TRY(aaa::launch_segment_sort(skeys, svals, skeys == keys ? keys_alt : keys, svals == vals ? vals_alt : vals, P,
-                                     ranges, nlists, at<uint32_t>(ws, L.seg_long), (uint32_t *)(ctr + 9), s));
+    // buffer is scratch for very long lists); after the full sort, only the
+    // note of long lists for the next call
+    if (full_sort)
+        HIP_TRY(aaa::launch_note_long_lists(ranges, nlists, sort_note, s));
+    else
+        HIP_TRY(aaa::launch_segment_sort(skeys, svals, skeys == keys ? keys_alt : keys, svals == vals ? vals_alt : vals,
+                                         P, ranges, nlists, at<uint32_t>(ws, L.seg_long), (uint32_t *)(ctr + 11),
+                                         sort_note, s));
     STAGE_MARK(8);
 
     aaa::BlendArgs ba;
@@ -663,8 +709,7 @@ static int backward_slots(aaa_ctx *ctx, const Shape &sh, const Layout &L, void *
                                   at<uint32_t>(ws, L.n_ins), at<uint32_t>(ws, L.wave_caps), max_big, s));
     HIP_TRY(aaa::launch_exclusive_scan(at<uint32_t>(ws, L.wave_caps), at<uint64_t>(ws, L.wave_off), quads,
                                        at<void>(ws, L.wave_scan_tmp), s));
-    HIP_TRY(aaa::launch_publish2(at<uint64_t>(ws, L.wave_off) + quads, (const uint64_t *)max_big, ctx->sync_host, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(publish_and_wait(ctx, at<uint64_t>(ws, L.wave_off) + quads, (const uint64_t *)max_big, s));
     const uint64_t rows = ctx->sync_host[0];
     const uint32_t big = (uint32_t)ctx->sync_host[1];  // the low word of the 8 bytes at max_big
     *total = rows * 64;

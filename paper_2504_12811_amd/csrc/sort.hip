@@ -205,6 +205,12 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
     if (i < n) p[i] = v;
 }
 
+__global__ void k_note_long(const uint32_t *__restrict__ ranges, int64_t nlists, uint32_t *__restrict__ note)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < nlists && ranges[2 * l + 1] - ranges[2 * l] > kSortNoteList) *note = 1u;
+}
+
 __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t *__restrict__ ranges)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -390,7 +396,7 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
 __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                   const uint32_t *__restrict__ ranges, uint32_t nlists,
                                                   uint32_t *__restrict__ queue_mid, uint32_t *__restrict__ queue_large,
-                                                  uint32_t *__restrict__ n_queued)
+                                                  uint32_t *__restrict__ n_queued, uint32_t *__restrict__ note)
 {
     __shared__ SegShared<1> sh;
     const uint32_t list = blockIdx.x;
@@ -403,6 +409,7 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
                 queue_large[atomicAdd(&n_queued[1], 1u)] = list;
             else
                 queue_mid[atomicAdd(&n_queued[0], 1u)] = list;
+            if (m > kSortNoteList) *note = 1u;
         }
         return;
     }
@@ -571,12 +578,12 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 
 hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                                const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
-                               hipStream_t s)
+                               uint32_t *note, hipStream_t s)
 {
     if (n <= 1 || nlists <= 0) return hipSuccess;
     uint32_t *queue_mid = queues, *queue_large = queues + nlists;
     hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists,
-                       queue_mid, queue_large, n_queued);
+                       queue_mid, queue_large, n_queued, note);
     // at most n / (L + 1) runs are longer than L entries
     const uint64_t mid = std::min<uint64_t>((uint64_t)nlists, n / (kSegWave + 1));
     if (mid)
@@ -586,6 +593,13 @@ hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_al
     if (large)
         hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
                            (const uint32_t *)queue_large, (const uint32_t *)(n_queued + 1));
+    return hipGetLastError();
+}
+
+hipError_t launch_note_long_lists(const uint32_t *ranges, int64_t nlists, uint32_t *note, hipStream_t s)
+{
+    if (nlists > 0)
+        hipLaunchKernelGGL(k_note_long, dim3((unsigned)((nlists + 255) / 256)), dim3(256), 0, s, ranges, nlists, note);
     return hipGetLastError();
 }
 

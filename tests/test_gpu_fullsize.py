@@ -125,6 +125,28 @@ def test_pair_order_long_lists(ras, ood, view):
     assert np.array_equal(lists[rg[full, 1] - 1], full.astype(np.uint64))
 
 
+def test_sort_routes_agree(ras, ood):
+    """A view with lists of 10^5 entries rendered twice: after a view without
+    long lists its lists are sorted one workgroup each, the second time (the
+    workspace noted the long lists) by global passes over the whole key.
+    Pairs and images must be identical."""
+    scene, cam0, zoom = ood
+    from test_gpu_forward import dev
+    ds = dev(scene)
+    small = S.pinhole(cam0.position, 256, 256, 60.0)
+    ras.render(ds, small, S.Settings())  # no list longer than the note's threshold
+    out = []
+    for _ in range(2):
+        rgb, T, _ = ras.render(ds, zoom[4], S.Settings())
+        keys, vals, ranges = ras.read_pairs(ds, zoom[4])
+        out.append((rgb.cpu().numpy(), T.cpu().numpy(), keys.cpu().numpy(), vals.cpu().numpy(),
+                    ranges.cpu().numpy()))
+    ln = out[0][4][:, 1] - out[0][4][:, 0]
+    assert ln.max() > 32768
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_720p_16_view_batch_sampled(ras):
     from test_gpu_forward import dev, check_image
     scene, cams = S.fwd_bwd_scene()
