@@ -290,12 +290,13 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 // Phase 2 of the pair sort: every list [ranges[2 l], ranges[2 l + 1]) of
 // keys/vals sorted in place by the low word of its keys (stable); the other
 // buffers are scratch for lists longer than 8192 entries.  queues holds
-// 2 nlists entries; n_queued[0..1] must be zero.  *note is set to 1 when a
-// list is longer than kSortNoteList.
+// 2 nlists entries; n_queued[0..1] must be zero.  Lists longer than
+// kLongList or kSortNoteList set the bits kNoteLongRoute / kNoteSortWide of
+// *note.
 hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                                const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
                                uint32_t *note, hipStream_t s);
-// *note = 1 when a list of ranges is longer than kSortNoteList
+// the note bits of launch_segment_sort, from the list lengths of ranges
 hipError_t launch_note_long_lists(const uint32_t *ranges, int64_t nlists, uint32_t *note, hipStream_t s);
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
 
@@ -348,7 +349,11 @@ hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32
 // one makes the next frame of the same workspace use the full-width global
 // sort instead.
 constexpr uint32_t kSortNoteList = 32768;
-constexpr uint32_t kLongList = 4096;     // entries above which a forward tile is rendered by k_blend_long
+constexpr uint32_t kLongList = 4096;
+// Bits of the note a frame leaves for the next frame of its workspace (a
+// hint only: either choice gives the same result).
+constexpr uint32_t kNoteSortWide = 1u;   // a list longer than kSortNoteList
+constexpr uint32_t kNoteLongRoute = 2u;  // a list longer than kLongList     // entries above which a forward tile is rendered by k_blend_long
 constexpr uint32_t kMaxLongTiles = 1024; // ... when at most this many tiles are that long
 
 struct GradOut {

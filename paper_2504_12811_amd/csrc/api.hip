@@ -566,13 +566,14 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s,
                                        area_off + items));
     STAGE_MARK(3);
-    // the note word (outside the counters cleared per call) is set by a call
-    // whose pair sort met a list longer than kSortNoteList
+    // the note word (outside the counters cleared per call) holds what the
+    // previous call of this workspace met: lists longer than kLongList or
+    // kSortNoteList (a hint for this call's choices; both give one result)
     uint32_t *sort_note = (uint32_t *)(ctr + 20);
     HIP_TRY(publish_and_wait(ctx, kept_before + chunks, area_off + items, s, sort_note));
     uint64_t P = ctx->sync_host[0];
     const uint64_t C = ctx->sync_host[1];
-    const bool long_lists_before = ctx->sync_host[3] != 0;
+    const uint32_t note = (uint32_t)ctx->sync_host[3];
     if (C > keep_cap) P = std::max<uint64_t>(max_pairs + 1, (C + 7) / 8);  // buffer too small to even count
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -595,7 +596,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     // global passes run over the whole key instead and phase 2 is left out.
     // Both give the order of a full stable sort of the 64-bit keys, and the
     // same number of passes modulo 2 (32 bits are four passes).
-    const bool full_sort = long_lists_before;
+    const bool full_sort = (note & aaa::kNoteSortWide) != 0;
     bool in_alt = false;
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, full_sort ? 0 : 32, key_bits(nlists),
                                   at<void>(ws, L.sort_tmp), s, &in_alt));
@@ -646,7 +647,14 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const int K = settings->ray_window;
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
     // the long-list route walks whole tiles: not with sub-tile lists
-    ba.long_list = (K > 16 || subtile) ? 0xffffffffu : (long_all ? 0u : aaa::kLongList);
+    // the long-list route needs a side stream, its own list scan and a
+    // fork and join (~20 us): set up only when the previous call of this
+    // workspace had a list that long (without it every tile takes k_blend,
+    // with the same result)
+    ba.long_list = (K > 16 || subtile) ? 0xffffffffu
+                   : long_all ? 0u
+                   : (note & aaa::kNoteLongRoute) ? aaa::kLongList
+                   : 0xffffffffu;
     uint32_t *n_long = (uint32_t *)(ctr + 8);  // zeroed with the counters
     ba.n_long = n_long;
     if (ba.long_list != 0xffffffffu && P > ba.long_list) {

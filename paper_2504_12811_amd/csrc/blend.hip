@@ -174,12 +174,13 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
                                                     BlendArgs a)
 {
     const int ntiles = a.total_tiles;
-    // XCD-aware order: consecutive workgroups land on different XCDs, so hand
-    // each XCD a contiguous band of tiles (neighbouring tiles share records);
-    // with one wave per workgroup the four quadrants of a tile share an XCD.
-    const int per = (ntiles + 7) / 8;
+    // Consecutive workgroups land on consecutive XCDs; tiles are dealt to the
+    // XCDs round-robin (tile t to XCD t % 8), so that each XCD gets an even
+    // share of dense and sparse image regions (contiguous bands per XCD left
+    // the XCDs with dense bands working long after the others); with one
+    // wave per workgroup the four quadrants of a tile share an XCD.
     const int wq = (int)(blockIdx.x >> 3);
-    const int tile = (int)(blockIdx.x & 7) * per + (WPB == 4 ? wq : wq >> 2);
+    const int tile = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
     if (tile >= ntiles) return;
     int v = 0;  // the view owning this tile (views are ordered by tile_base)
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
@@ -532,14 +533,16 @@ __global__ __launch_bounds__(64) void k_blend_long(const float4 *__restrict__ re
     const size_t pix = L.inside ? (size_t)L.py * vw.cam.width + L.px : 0;
     const size_t gpix = vw.pix_base + pix;
 
+    // The window of k_blend's keyed form (K <= 16 here: K = 32 keeps every
+    // tile in k_blend): the same keys, the same median update, so both routes
+    // pop the same entries in the same order, ties included (by slot).
+    static_assert(K <= 16, "the long-list route serves K <= 16");
     constexpr int KS = K > 0 ? K : 1;
     __shared__ float4 pay[1][KS][64];  // (alpha, r, g, b) per slot
-    float wz[KS];
-    uint32_t ws[KS];
+    uint32_t wk[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-        wz[k] = -INFINITY;
-        ws[k] = (uint32_t)k;
+        wk[k] = (uint32_t)k;  // filler keys: depth offset 0, slot k
         if constexpr (K > 0) pay[0][k][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
@@ -547,6 +550,7 @@ __global__ __launch_bounds__(64) void k_blend_long(const float4 *__restrict__ re
     uint32_t consumed = 0, rank = 0;
     uint32_t n_eval = 0, n_near = 0, w_steps = 0, w_near = 0, w_contrib = 0;
     const float amin = a.alpha_min, amax = a.alpha_max, tmin = a.t_min, znear = (float)vw.cam.znear;
+    const uint32_t zbits = __float_as_uint(znear);
 
     auto blend = [&](float al, float cr, float cg, float cb) {
         if (al > 0.0f && !done) {
@@ -637,20 +641,16 @@ __global__ __launch_bounds__(64) void k_blend_long(const float4 *__restrict__ re
         if constexpr (K == 0) {
             blend(contrib ? al : 0.0f, col.x, col.y, col.z);
         } else {
-            const float zk = contrib ? z : __builtin_nanf("");
             const float ak = contrib ? al : 0.0f;
-            const uint32_t fs = ws[0];
+            const uint32_t fs = wk[0] & 15u;
+            const uint32_t doff = min(__float_as_uint(z) - zbits + 1u, (1u << 28) - 1u);
+            const uint32_t key = contrib ? (doff << 4) | fs : 0u;
             const float4 fp = pay[0][fs][lane];
-            const bool front_out = wz[0] <= zk;
-            bool gcur = front_out;  // same update as k_blend's (median-of-three depths)
+            const bool front_out = wk[0] <= key;
 #pragma unroll
-            for (int kk = 0; kk < K; ++kk) {
-                const int kn = kk + 1 < K ? kk + 1 : kk;
-                const bool gnext = (kk + 1 < K) ? (wz[kn] <= zk) : false;
-                wz[kk] = (kk + 1 < K) ? __builtin_amdgcn_fmed3f(wz[kk], zk, wz[kn]) : (gcur ? zk : wz[kk]);
-                ws[kk] = gnext ? ws[kn] : (gcur ? fs : ws[kk]);
-                gcur = gnext;
-            }
+            for (int kk = 0; kk + 1 < K; ++kk)
+                asm("v_med3_u32 %0, %0, %1, %2" : "+v"(wk[kk]) : "v"(key), "v"(wk[kk + 1]));
+            wk[K - 1] = max(wk[K - 1], key);
             if (front_out) pay[0][fs][lane] = make_float4(ak, col.x, col.y, col.z);
             if (front_out)
                 blend(fp.x, fp.y, fp.z, fp.w);
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(64) void k_blend_long(const float4 *__restrict__ re
     if constexpr (K > 0) {
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            const float4 q = pay[0][ws[k]][lane];
+            const float4 q = pay[0][wk[k] & 15u][lane];
             blend(done ? 0.0f : q.x, q.y, q.z, q.w);
         }
     }
@@ -755,9 +755,8 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
                                                    BlendArgs a)
 {
     const int ntiles = a.total_tiles;
-    const int per = (ntiles + 7) / 8;
-    const int wq = (int)(blockIdx.x >> 3);
-    const int tile = (int)(blockIdx.x & 7) * per + (WPB == 4 ? wq : wq >> 2);
+    const int wq = (int)(blockIdx.x >> 3);  // tiles dealt to the XCDs round-robin, as in k_blend
+    const int tile = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
     if (tile >= ntiles) return;
     int v = 0;
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;

@@ -208,7 +208,10 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
 __global__ void k_note_long(const uint32_t *__restrict__ ranges, int64_t nlists, uint32_t *__restrict__ note)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < nlists && ranges[2 * l + 1] - ranges[2 * l] > kSortNoteList) *note = 1u;
+    if (l < nlists) {
+        const uint32_t m = ranges[2 * l + 1] - ranges[2 * l];
+        if (m > kLongList) atomicOr(note, m > kSortNoteList ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
+    }
 }
 
 __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t *__restrict__ ranges)
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
                 queue_large[atomicAdd(&n_queued[1], 1u)] = list;
             else
                 queue_mid[atomicAdd(&n_queued[0], 1u)] = list;
-            if (m > kSortNoteList) *note = 1u;
+            if (m > kLongList) atomicOr(note, m > kSortNoteList ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
         }
         return;
     }
