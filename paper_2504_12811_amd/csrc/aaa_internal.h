@@ -287,17 +287,20 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int6
 size_t sort_tmp_bytes(uint64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                             int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt);
-// Phase 2 of the pair sort: every list [ranges[2 l], ranges[2 l + 1]) of
-// keys/vals sorted in place by the low word of its keys (stable); the other
-// buffers are scratch for lists longer than 8192 entries.  queues holds
-// 2 nlists entries; n_queued[0..1] must be zero.  Lists longer than
-// kLongList or kSortNoteList set the bits kNoteLongRoute / kNoteSortWide of
-// *note.
-hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
-                               const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
-                               uint32_t *note, hipStream_t s);
-// the note bits of launch_segment_sort, from the list lengths of ranges
-hipError_t launch_note_long_lists(const uint32_t *ranges, int64_t nlists, uint32_t *note, hipStream_t s);
+// Phase 2 of the pair sort: the lists [ranges[2 l], ranges[2 l + 1]) of
+// keys/vals sorted in place by the low word of their keys (stable).  First
+// kernel: lists of up to 512 entries, the others queued (queues holds
+// 2 nlists entries, n_queued[0..1] zero at entry); lists longer than
+// kLongList / kSortNoteList set the bits kNoteLongRoute / kNoteSortWide of
+// *note, and those longer than kSortNoteList are left to global passes over
+// the whole key (the caller's).  The rest: the queued lists (the other
+// buffers are scratch for lists longer than 8192 entries).
+hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
+                                     int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
+                                     hipStream_t s);
+hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                                    uint64_t n, const uint32_t *ranges, int64_t nlists, const uint32_t *queues,
+                                    const uint32_t *n_queued, hipStream_t s);
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
 
 struct BlendArgs {
@@ -344,17 +347,15 @@ hipError_t launch_find_long(const BlendArgs &a, uint32_t *long_tiles, uint32_t *
 hipError_t launch_blend_long(const BlendArgs &a, int K, bool stats, const uint32_t *long_tiles, const uint32_t *n_long,
                              unsigned grid, uint64_t *pixmask, uint64_t *summary, uint64_t summary_words,
                              hipStream_t s);
-// Lists longer than this are sorted by one workgroup each in the per-list
-// phase of the pair sort, far below the chip's bandwidth; a frame that had
-// one makes the next frame of the same workspace use the full-width global
-// sort instead.
+// Lists longer than this are left out of the per-list phase of the pair
+// sort (one workgroup each would run far below the chip's bandwidth); when
+// one occurs, global passes over the whole key sort the pairs.
 constexpr uint32_t kSortNoteList = 32768;
-constexpr uint32_t kLongList = 4096;
-// Bits of the note a frame leaves for the next frame of its workspace (a
-// hint only: either choice gives the same result).
-constexpr uint32_t kNoteSortWide = 1u;   // a list longer than kSortNoteList
-constexpr uint32_t kNoteLongRoute = 2u;  // a list longer than kLongList     // entries above which a forward tile is rendered by k_blend_long
-constexpr uint32_t kMaxLongTiles = 1024; // ... when at most this many tiles are that long
+constexpr uint32_t kLongList = 4096;      // entries above which a forward tile is rendered by k_blend_long
+constexpr uint32_t kMaxLongTiles = 1024;  // ... when at most this many tiles are that long
+// Bits of the note the per-list sort publishes to the host.
+constexpr uint32_t kNoteSortWide = 1u;    // a list longer than kSortNoteList
+constexpr uint32_t kNoteLongRoute = 2u;   // a list longer than kLongList
 
 struct GradOut {
     float *means, *log_scales, *quats, *logits, *sh;

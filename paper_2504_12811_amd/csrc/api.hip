@@ -142,9 +142,9 @@ int key_bits(int64_t ntiles)
 }
 
 // The pair sort runs ceil(list bits / 8) LSD passes over the high word,
-// ping-ponging between the two buffers, then sorts each list in place (or,
-// after a frame with very long lists, four more passes over the low word):
-// either way the result is in the buffer this parity names.
+// ping-ponging between the two buffers, then sorts each list in place (with
+// very long lists, global passes over the whole key follow, and a copy if
+// their number was odd): the result is in the buffer this parity names.
 bool sorted_in_alt(int64_t ntiles) { return ((key_bits(ntiles) - 32 + 7) / 8) % 2 == 1; }
 
 int check_camera(const aaa_camera *cam)
@@ -341,18 +341,22 @@ struct aaa_ctx {
 
 namespace {
 
-// Publishes two device words (and, with a note word, that word, which the
-// kernel then clears) to the host and waits for them: the kernel writes
-// them, then the call's sequence number, into coherent pinned memory; the
-// host spins on the number for up to 2 ms (a blocking stream wait adds its
-// wake-up latency, tens of microseconds, to every frame) and then falls back
-// to the blocking wait, which also reports stream errors.  In stream order
-// the kernel follows everything the call enqueued before.
-hipError_t publish_and_wait(aaa_ctx *c, const uint64_t *a, const uint64_t *b, hipStream_t s, uint32_t *note = nullptr)
+// Publishing device words to the host: a kernel writes two words (and, with
+// a note word, that word, which it then clears), then the publication's
+// sequence number, into coherent pinned memory; the host spins on the number
+// for up to 2 ms (a blocking stream wait adds its wake-up latency, tens of
+// microseconds, to every frame) and then falls back to the blocking wait,
+// which also reports stream errors.  In stream order the kernel follows
+// everything enqueued before it.
+hipError_t publish(aaa_ctx *c, const uint64_t *a, const uint64_t *b, hipStream_t s, uint64_t *seq,
+                   uint32_t *note = nullptr)
 {
-    const uint64_t seq = ++c->sync_seq;
-    hipError_t e = aaa::launch_publish2(a, b, c->sync_host, seq, note, s);
-    if (e != hipSuccess) return e;
+    *seq = ++c->sync_seq;
+    return aaa::launch_publish2(a, b, c->sync_host, *seq, note, s);
+}
+
+hipError_t wait_published(aaa_ctx *c, hipStream_t s, uint64_t seq)
+{
     volatile uint64_t *flag = c->sync_host + 2;
     const auto t0 = std::chrono::steady_clock::now();
     for (unsigned k = 0; *flag != seq; ++k) {
@@ -362,6 +366,13 @@ hipError_t publish_and_wait(aaa_ctx *c, const uint64_t *a, const uint64_t *b, hi
     }
     std::atomic_thread_fence(std::memory_order_acquire);
     return hipSuccess;
+}
+
+hipError_t publish_and_wait(aaa_ctx *c, const uint64_t *a, const uint64_t *b, hipStream_t s)
+{
+    uint64_t seq = 0;
+    hipError_t e = publish(c, a, b, s, &seq);
+    return e != hipSuccess ? e : wait_published(c, s, seq);
 }
 
 void fold_events(aaa_ctx *c, int set)
@@ -566,14 +577,9 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s,
                                        area_off + items));
     STAGE_MARK(3);
-    // the note word (outside the counters cleared per call) holds what the
-    // previous call of this workspace met: lists longer than kLongList or
-    // kSortNoteList (a hint for this call's choices; both give one result)
-    uint32_t *sort_note = (uint32_t *)(ctr + 20);
-    HIP_TRY(publish_and_wait(ctx, kept_before + chunks, area_off + items, s, sort_note));
+    HIP_TRY(publish_and_wait(ctx, kept_before + chunks, area_off + items, s));
     uint64_t P = ctx->sync_host[0];
     const uint64_t C = ctx->sync_host[1];
-    const uint32_t note = (uint32_t)ctx->sync_host[3];
     if (C > keep_cap) P = std::max<uint64_t>(max_pairs + 1, (C + 7) / 8);  // buffer too small to even count
     if (stats) {
         memset(stats, 0, sizeof(*stats));
@@ -590,16 +596,10 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
                                     tile_cull, subtile, s));
     STAGE_MARK(5);
     // Pair sort.  Phase 1: LSD passes over the list bits (the high word);
-    // phase 2 (below) sorts each list by the depth word.  After a call of
-    // this workspace that met a list longer than kSortNoteList (far views:
-    // most pairs in a few lists, which phase 2 gives one workgroup each), the
-    // global passes run over the whole key instead and phase 2 is left out.
-    // Both give the order of a full stable sort of the 64-bit keys, and the
-    // same number of passes modulo 2 (32 bits are four passes).
-    const bool full_sort = (note & aaa::kNoteSortWide) != 0;
+    // phase 2 (below) sorts each list by the depth word.
     bool in_alt = false;
-    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, full_sort ? 0 : 32, key_bits(nlists),
-                                  at<void>(ws, L.sort_tmp), s, &in_alt));
+    HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 32, key_bits(nlists), at<void>(ws, L.sort_tmp),
+                                  s, &in_alt));
     if (P > 1 && in_alt != sorted_in_alt(nlists)) return fail(AAA_ERR_HIP, "internal: sort parity");
     uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
     uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
@@ -614,15 +614,33 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     uint32_t *ranges = at<uint32_t>(ws, L.ranges);
     HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s));
     STAGE_MARK(7);
-    // phase 2: each list sorted by the depth key in place (the other pair
-    // buffer is scratch for very long lists); after the full sort, only the
-    // note of long lists for the next call
-    if (full_sort)
-        HIP_TRY(aaa::launch_note_long_lists(ranges, nlists, sort_note, s));
-    else
-        HIP_TRY(aaa::launch_segment_sort(skeys, svals, skeys == keys ? keys_alt : keys, svals == vals ? vals_alt : vals,
-                                         P, ranges, nlists, at<uint32_t>(ws, L.seg_long), (uint32_t *)(ctr + 11),
-                                         sort_note, s));
+    // Phase 2: each list sorted by the depth word in place (the other pair
+    // buffer is scratch for long lists).  Its first kernel notes lists
+    // longer than kLongList and kSortNoteList and leaves the latter out (far
+    // views: most pairs in a few lists, which one workgroup each would sort
+    // far below the chip's bandwidth); the note is published while the rest
+    // of phase 2 runs.  With such a list, global passes over the whole key
+    // sort all pairs from the current order (stable: the order of a full
+    // sort; tile boundaries, and so the ranges, are unchanged).
+    uint64_t *okeys = skeys == keys ? keys_alt : keys;
+    uint32_t *ovals = svals == vals ? vals_alt : vals;
+    uint32_t *queues = at<uint32_t>(ws, L.seg_long), *n_queued = (uint32_t *)(ctr + 11);
+    uint32_t *list_note = (uint32_t *)(ctr + 13);  // zeroed with the counters
+    HIP_TRY(aaa::launch_segment_sort_first(skeys, svals, P, ranges, nlists, queues, n_queued, list_note, s));
+    uint64_t seq = 0;
+    HIP_TRY(publish(ctx, kept_before + chunks, area_off + items, s, &seq, list_note));
+    HIP_TRY(aaa::launch_segment_sort_rest(skeys, svals, okeys, ovals, P, ranges, nlists, queues, n_queued, s));
+    HIP_TRY(wait_published(ctx, s, seq));
+    const uint32_t lists = P > 1 ? (uint32_t)ctx->sync_host[3] : 0u;
+    if (lists & aaa::kNoteSortWide) {
+        bool moved = false;
+        HIP_TRY(aaa::radix_sort_pairs(skeys, svals, okeys, ovals, P, 0, key_bits(nlists), at<void>(ws, L.sort_tmp), s,
+                                      &moved));
+        if (moved) {  // an odd number of passes (more than 65536 lists): back into place
+            HIP_TRY(hipMemcpyAsync(skeys, okeys, P * 8, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(svals, ovals, P * 4, hipMemcpyDeviceToDevice, s));
+        }
+    }
     STAGE_MARK(8);
 
     aaa::BlendArgs ba;
@@ -648,12 +666,11 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
     // the long-list route walks whole tiles: not with sub-tile lists
     // the long-list route needs a side stream, its own list scan and a
-    // fork and join (~20 us): set up only when the previous call of this
-    // workspace had a list that long (without it every tile takes k_blend,
-    // with the same result)
+    // fork and join (~20 us): set up only when this call has a list that
+    // long (the note of phase 2)
     ba.long_list = (K > 16 || subtile) ? 0xffffffffu
                    : long_all ? 0u
-                   : (note & aaa::kNoteLongRoute) ? aaa::kLongList
+                   : (lists & aaa::kNoteLongRoute) ? aaa::kLongList
                    : 0xffffffffu;
     uint32_t *n_long = (uint32_t *)(ctr + 8);  // zeroed with the counters
     ba.n_long = n_long;

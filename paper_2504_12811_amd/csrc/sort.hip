@@ -205,15 +205,6 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
     if (i < n) p[i] = v;
 }
 
-__global__ void k_note_long(const uint32_t *__restrict__ ranges, int64_t nlists, uint32_t *__restrict__ note)
-{
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l < nlists) {
-        const uint32_t m = ranges[2 * l + 1] - ranges[2 * l];
-        if (m > kLongList) atomicOr(note, m > kSortNoteList ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
-    }
-}
-
 __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t *__restrict__ ranges)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -408,11 +399,14 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
     const uint32_t m = end > start ? end - start : 0u;
     if (m > (uint32_t)kSegWave) {
         if (threadIdx.x == 0) {
-            if (m > (uint32_t)kSegSmall)
-                queue_large[atomicAdd(&n_queued[1], 1u)] = list;
-            else
-                queue_mid[atomicAdd(&n_queued[0], 1u)] = list;
             if (m > kLongList) atomicOr(note, m > kSortNoteList ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
+            if (m > kSortNoteList) {
+                // left to global passes over the whole key (the host reads the note)
+            } else if (m > (uint32_t)kSegSmall) {
+                queue_large[atomicAdd(&n_queued[1], 1u)] = list;
+            } else {
+                queue_mid[atomicAdd(&n_queued[0], 1u)] = list;
+            }
         }
         return;
     }
@@ -579,30 +573,29 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     return hipSuccess;
 }
 
-hipError_t launch_segment_sort(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
-                               const uint32_t *ranges, int64_t nlists, uint32_t *queues, uint32_t *n_queued,
-                               uint32_t *note, hipStream_t s)
+hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
+                                     int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
+                                     hipStream_t s)
 {
     if (n <= 1 || nlists <= 0) return hipSuccess;
-    uint32_t *queue_mid = queues, *queue_large = queues + nlists;
     hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists,
-                       queue_mid, queue_large, n_queued, note);
-    // at most n / (L + 1) runs are longer than L entries
-    const uint64_t mid = std::min<uint64_t>((uint64_t)nlists, n / (kSegWave + 1));
-    if (mid)
-        hipLaunchKernelGGL(k_seg_mid, dim3((unsigned)mid), dim3(256), 0, s, keys, vals, ranges,
-                           (const uint32_t *)queue_mid, (const uint32_t *)n_queued);
-    const uint64_t large = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
-    if (large)
-        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
-                           (const uint32_t *)queue_large, (const uint32_t *)(n_queued + 1));
+                       queues, queues + nlists, n_queued, note);
     return hipGetLastError();
 }
 
-hipError_t launch_note_long_lists(const uint32_t *ranges, int64_t nlists, uint32_t *note, hipStream_t s)
+hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                                    uint64_t n, const uint32_t *ranges, int64_t nlists, const uint32_t *queues,
+                                    const uint32_t *n_queued, hipStream_t s)
 {
-    if (nlists > 0)
-        hipLaunchKernelGGL(k_note_long, dim3((unsigned)((nlists + 255) / 256)), dim3(256), 0, s, ranges, nlists, note);
+    if (n <= 1 || nlists <= 0) return hipSuccess;
+    // at most n / (L + 1) runs are longer than L entries
+    const uint64_t mid = std::min<uint64_t>((uint64_t)nlists, n / (kSegWave + 1));
+    if (mid)
+        hipLaunchKernelGGL(k_seg_mid, dim3((unsigned)mid), dim3(256), 0, s, keys, vals, ranges, queues, n_queued);
+    const uint64_t large = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
+    if (large)
+        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
+                           queues + nlists, n_queued + 1);
     return hipGetLastError();
 }
 
