@@ -290,7 +290,7 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 // Phase 2 of the pair sort: the lists [ranges[2 l], ranges[2 l + 1]) of
 // keys/vals sorted in place by the low word of their keys (stable).  First
 // kernel: lists of up to 512 entries, the others queued (queues holds
-// 2 nlists entries, n_queued[0..1] zero at entry); lists longer than
+// 2 nlists entries, n_queued[0..2] zero at entry); lists longer than
 // kLongList / kSortNoteList set the bits kNoteLongRoute / kNoteSortWide of
 // *note, and those longer than kSortNoteList are left to global passes over
 // the whole key (the caller's).  The rest: the queued lists (the other

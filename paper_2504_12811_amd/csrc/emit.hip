@@ -127,6 +127,11 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
     unsigned long long n_first = 0, n_tests = 0;
     for (uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u); t0 < C; t0 += stride) {
         const uint64_t c = t0 >> 6;
+        uint64_t kall = 0;
+        if (WRITE) {
+            kall = keep_bits[c];
+            if (kall == 0) continue;  // uniform: no test of this chunk was kept
+        }
         const uint64_t t = t0 + (uint64_t)lane;
         const bool valid = t < C;
         const uint64_t tq = valid ? t : C - 1;
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
             load_tile_geom(recs + (size_t)g * kRecQuads, culls + (size_t)g * kCullQuads, geo);
             const float tau = recs[(size_t)g * kRecQuads + 6].y;
             const bool keep = valid && (!tile_cull || tile_keep(geo, tx, ty, tau, vw.cam));
-            const uint64_t kall = __ballot(keep);
+            kall = __ballot(keep);
             uint32_t cnt = (uint32_t)__popcll(kall);
             if (subtile) {
                 const uint32_t qb = keep ? (tile_cull ? quad_bits(bbox[g], tx, ty) : 15u) : 0u;
@@ -183,7 +188,6 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
             n_tests += valid ? 1 : 0;
             n_first += (valid && j == 0) ? 1 : 0;
         } else if (subtile) {
-            const uint64_t kall = keep_bits[c];
             const bool kept = valid && ((kall >> lane) & 1ull);
             const uint32_t qb = kept ? (tile_cull ? quad_bits(bbox[g], tx, ty) : 15u) : 0u;
             uint64_t slot = kept_before[c] + wave_exclusive_sum(__popc(qb));
@@ -200,7 +204,6 @@ __global__ __launch_bounds__(256) void k_pairs(const int4 *__restrict__ rects, c
                 }
             }
         } else {
-            const uint64_t kall = keep_bits[c];
             if (valid && ((kall >> lane) & 1ull)) {
                 const uint64_t slot = kept_before[c] + (uint64_t)__popcll(kall & bits_below(lane));
                 if (slot < max_pairs) {

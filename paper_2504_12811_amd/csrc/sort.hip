@@ -36,6 +36,25 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// The lanes of the wave whose 8-bit digit d equals this lane's, among the
+// lanes with `valid` set.  One ballot per digit bit; each lane ORs into its
+// mask of disagreeing lanes the bit's ballot XOR its own bit spread over a
+// word (0 or ~0), one three-input bit operation per mask half.
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+{
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = ~(uint32_t)v, hi = ~(uint32_t)(v >> 32);
+#pragma unroll
+    for (int b = 0; b < kBits; ++b) {
+        uint32_t own;  // bit b of d spread over the word (written as one v_bfe_i32)
+        asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(own) : "v"(d), "i"(b));
+        const uint64_t bb = __ballot(own != 0u);
+        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, own, 0xF6);  // lo | (bb ^ own)
+        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), own, 0xF6);
+    }
+    return ~(((uint64_t)hi << 32) | lo);
+}
+
 __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift,
                                                    uint32_t *__restrict__ hist, uint32_t nblocks)
 {
@@ -129,12 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         val[r] = valid[r] ? vals_in[idx] : 0u;
         uint32_t d = (uint32_t)(key[r] >> shift) & (kBins - 1);
         dig[r] = d;
-        uint64_t m = __ballot(valid[r]);
-#pragma unroll
-        for (int b = 0; b < kBits; ++b) {
-            uint64_t bb = __ballot((d >> b) & 1u);
-            m &= ((d >> b) & 1u) ? bb : ~bb;
-        }
+        const uint64_t m = match_digit(d, valid[r]);
         uint32_t before = (uint32_t)__popcll(m & lt);
         uint32_t base = 0;
         if (valid[r]) base = cnt[wave][d];
@@ -224,62 +238,62 @@ __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t
 // workgroup per list:
 //  - k_seg_first (1 wave): runs of 2..kSegWave entries, in registers and
 //    LDS; longer runs are queued for
-//  - k_seg_mid (4 waves): runs up to kSegSmall entries the same way, or
-//  - k_seg_large (16 waves): runs up to kSegLarge entries the same way,
-//    longer runs by 8-bit LSD passes over the run in global memory (the
-//    other pair buffer holds the intermediate order), in chunks of
-//    kSegLarge.
+//  - k_seg_mid (4 waves): runs up to kSegSmall entries the same way,
+//  - k_seg_large (16 waves): runs up to kSegLarge entries the same way, or
+//  - k_seg_huge (16 waves): longer runs by 8-bit LSD passes over the run in
+//    global memory (the other pair buffer holds the intermediate order), in
+//    chunks of kSegLarge.
 // Entries sit in registers, kSegItems per thread: wave w holds entries
 // w S + 64 r + lane (r < S / 64) of the run or chunk, so that wave order,
 // then round, then lane is entry order.  A pass ranks each entry among the
 // equal digits of its wave (ballot match, as in k_scatter), scans the
 // per-wave digit counts in (digit, wave) order and moves the entries
-// through LDS to their new places.  A pass whose digit is the same for
-// every entry of the run is skipped.
+// through LDS to their new places.  The depth words are sorted as offsets
+// from the run's minimum, so only the passes that the span of the run's
+// words needs are made; a pass whose digit is the same for every entry of
+// the run moves nothing.
 
 constexpr int kSegItems = 8;
 constexpr int kSegWave = 64 * kSegItems;         // 512
 constexpr int kSegSmall = 4 * 64 * kSegItems;    // 2048
 constexpr int kSegLarge = 16 * 64 * kSegItems;   // 8192
 
+// Per-wave counts fit 16 bits (at most 512 entries per wave, prefixes at
+// most 16 * 512), which keeps the 16-wave form at two workgroups per CU.
 template <int W>
 struct SegShared {
-    alignas(16) uint32_t cnt[W][kBins];   // per-wave digit counts, then per-wave prefixes
+    alignas(16) uint16_t cnt[W][kBins];   // per-wave digit counts, then per-wave prefixes
     alignas(16) uint32_t lbase[kBins];    // start of each digit in the run or chunk
     alignas(16) uint32_t tot[kBins];      // digit totals of the run or chunk
     uint32_t wsum[4];
     uint32_t skip[4];         // per pass: one digit holds the whole run (set once, never reset)
+    uint32_t red[2][W];       // per-wave minimum and maximum of the depth words
     uint32_t key[W * 64 * kSegItems];
     uint32_t val[W * 64 * kSegItems];
 };
 
 // Rank the wave's valid entries (e < m) by digit; per-wave counts in
-// sh.cnt[wave].  Returns the digits and ranks in d[] and rank[].
+// sh.cnt[wave].  Returns digit | rank << 8 in dr[] (ranks below 2^13).
 template <int W>
 __device__ __forceinline__ void seg_rank(SegShared<W> &sh, const uint32_t (&k)[kSegItems], uint32_t e0, uint32_t m,
-                                         int shift, int rounds, uint32_t (&d)[kSegItems], uint32_t (&rank)[kSegItems])
+                                         int shift, int rounds, uint32_t (&dr)[kSegItems])
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
-        if (r >= rounds) break;
-        const bool valid = e0 + (uint32_t)(r * 64 + lane) < m;
-        const uint32_t dg = (k[r] >> shift) & (kBins - 1);
-        d[r] = dg;
-        uint64_t mm = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kBits; ++b) {
-            const uint64_t bb = __ballot((dg >> b) & 1u);
-            mm &= ((dg >> b) & 1u) ? bb : ~bb;
+        if (r < rounds) {
+            const bool valid = e0 + (uint32_t)(r * 64 + lane) < m;
+            const uint32_t dg = (k[r] >> shift) & (kBins - 1);
+            const uint64_t mm = match_digit(dg, valid);
+            const uint32_t before = (uint32_t)__popcll(mm & lt);
+            uint32_t base = 0;
+            if (valid) base = sh.cnt[wave][dg];
+            dr[r] = dg | ((base + before) << 8);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && before == 0) sh.cnt[wave][dg] = (uint16_t)(base + (uint32_t)__popcll(mm));
+            __builtin_amdgcn_wave_barrier();
         }
-        const uint32_t before = (uint32_t)__popcll(mm & lt);
-        uint32_t base = 0;
-        if (valid) base = sh.cnt[wave][dg];
-        rank[r] = base + before;
-        __builtin_amdgcn_wave_barrier();
-        if (valid && before == 0) sh.cnt[wave][dg] = base + (uint32_t)__popcll(mm);
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -295,13 +309,13 @@ __device__ __forceinline__ void seg_scan(SegShared<W> &sh, uint32_t m, uint32_t 
         uint4 tot = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            uint4 *row = (uint4 *)&sh.cnt[w][4 * t];
-            const uint4 c = *row;
-            *row = tot;
-            tot.x += c.x;
-            tot.y += c.y;
-            tot.z += c.z;
-            tot.w += c.w;
+            uint2 *row = (uint2 *)&sh.cnt[w][4 * t];
+            const uint2 c = *row;
+            *row = make_uint2(tot.x | (tot.y << 16), tot.z | (tot.w << 16));
+            tot.x += c.x & 0xffffu;
+            tot.y += c.x >> 16;
+            tot.z += c.y & 0xffffu;
+            tot.w += c.y >> 16;
         }
         *(uint4 *)&sh.tot[4 * t] = tot;
         if (flag && (tot.x == m || tot.y == m || tot.z == m || tot.w == m)) *flag = 1u;
@@ -329,18 +343,20 @@ __device__ __forceinline__ void seg_pass(SegShared<W> &sh, uint32_t (&k)[kSegIte
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int rounds = (int)(S / 64);
     const uint32_t e0 = (uint32_t)wave * S;
-    for (int i = t; i < W * kBins; i += W * 64) (&sh.cnt[0][0])[i] = 0u;
+    for (int i = t; i < W * kBins / 2; i += W * 64) ((uint32_t *)&sh.cnt[0][0])[i] = 0u;
     __syncthreads();
-    uint32_t d[kSegItems], rank[kSegItems];
-    seg_rank<W>(sh, k, e0, m, shift, rounds, d, rank);
+    uint32_t dr[kSegItems];
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) asm("" : "=v"(dr[r]));  // rounds past `rounds` keep whatever is there
+    seg_rank<W>(sh, k, e0, m, shift, rounds, dr);
     __syncthreads();
     seg_scan<W>(sh, m, &sh.skip[shift / kBits]);
     if (sh.skip[shift / kBits]) return;  // uniform: every entry has the same digit
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
-        if (r >= rounds) break;
-        if (e0 + (uint32_t)(r * 64 + lane) < m) {
-            const uint32_t pos = sh.lbase[d[r]] + sh.cnt[wave][d[r]] + rank[r];
+        if (r < rounds && e0 + (uint32_t)(r * 64 + lane) < m) {
+            const uint32_t dg = dr[r] & (kBins - 1);
+            const uint32_t pos = sh.lbase[dg] + sh.cnt[wave][dg] + (dr[r] >> 8);
             sh.key[pos] = k[r];
             sh.val[pos] = v[r];
         }
@@ -348,9 +364,8 @@ __device__ __forceinline__ void seg_pass(SegShared<W> &sh, uint32_t (&k)[kSegIte
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
-        if (r >= rounds) break;
         const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
-        if (e < m) {
+        if (r < rounds && e < m) {
             k[r] = sh.key[e];
             v[r] = sh.val[e];
         }
@@ -358,7 +373,34 @@ __device__ __forceinline__ void seg_pass(SegShared<W> &sh, uint32_t (&k)[kSegIte
     __syncthreads();
 }
 
-// Sort a run of m <= W * 512 entries at keys/vals + start in place.
+// Minimum and maximum of the workgroup's mn / mx (uniform results; one
+// barrier when W > 1).
+template <int W>
+__device__ __forceinline__ void seg_minmax(SegShared<W> &sh, uint32_t &mn, uint32_t &mx)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = min(mn, (uint32_t)__shfl_xor((int)mn, off));
+        mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+    }
+    if (W > 1) {
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            sh.red[0][wave] = mn;
+            sh.red[1][wave] = mx;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            mn = min(mn, sh.red[0][w]);
+            mx = max(mx, sh.red[1][w]);
+        }
+    }
+}
+
+// Sort a run of m <= W * 512 entries at keys/vals + start in place.  The
+// depth words are sorted as offsets from the run's minimum, over the bits
+// their span needs (a run whose words are all equal is already in order).
 template <int W>
 __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                              uint64_t start, uint32_t m, uint64_t hi)
@@ -369,24 +411,39 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     const uint32_t e0 = (uint32_t)wave * S;
     if (threadIdx.x < 4) sh.skip[threadIdx.x] = 0u;  // ordered by the first pass's barrier
     uint32_t k[kSegItems], v[kSegItems];
+    uint32_t mn = ~0u, mx = 0u;
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
         const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
         const bool ok = r * 64 < (int)S && e < m;
         k[r] = ok ? ((const uint32_t *)(keys + start + e))[0] : 0u;  // the low (depth) word
         v[r] = ok ? vals[start + e] : 0u;
+        if (ok) {
+            mn = min(mn, k[r]);
+            mx = max(mx, k[r]);
+        }
     }
-    for (int shift = 0; shift < 32; shift += kBits) seg_pass<W>(sh, k, v, m, shift, S);
+    seg_minmax<W>(sh, mn, mx);
+    const uint32_t span = mx - mn;
+    if (span == 0u) return;
+    const int bits = 32 - __clz((int)span);
+#pragma unroll
+    for (int r = 0; r < kSegItems; ++r) k[r] -= mn;
+    for (int shift = 0; shift < bits; shift += kBits) seg_pass<W>(sh, k, v, m, shift, S);
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
         const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
         if (r * 64 < (int)S && e < m) {
-            keys[start + e] = hi | k[r];
+            keys[start + e] = hi | (k[r] + mn);
             vals[start + e] = v[r];
         }
     }
 }
 
+// queue_mid: lists of kSegWave + 1 .. kSegSmall entries; queue_large: from
+// its front the lists of kSegSmall + 1 .. kSegLarge entries, from its back
+// (queue_large[nlists - 1 - j]) the longer ones up to kSortNoteList (the two
+// together hold at most nlists lists); counts in n_queued[0..2].
 __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                   const uint32_t *__restrict__ ranges, uint32_t nlists,
                                                   uint32_t *__restrict__ queue_mid, uint32_t *__restrict__ queue_large,
@@ -395,22 +452,40 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
     __shared__ SegShared<1> sh;
     const uint32_t list = blockIdx.x;
     if (list >= nlists) return;
+    if ((list & 63u) == 0u) {
+        // This workgroup files the lists list .. list + 63 that need more
+        // than one wave (one atomic per queue for the 64 lists); lists
+        // longer than kSortNoteList are left to global passes over the whole
+        // key (the host reads the note).
+        const uint32_t l = list + threadIdx.x;
+        uint32_t ml = 0u;
+        if (l < nlists) {
+            const uint32_t a = ranges[2 * l], b = ranges[2 * l + 1];
+            ml = b > a ? b - a : 0u;
+        }
+        const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
+        const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
+        const uint64_t mid = __ballot(ml > (uint32_t)kSegWave && ml <= (uint32_t)kSegSmall);
+        const uint64_t lng = __ballot(ml > kLongList);
+        const uint64_t wide = __ballot(ml > kSortNoteList);
+        uint32_t qh = 0u, qb = 0u, qm = 0u;
+        if (threadIdx.x == 0) {
+            if (huge) qh = atomicAdd(&n_queued[2], (uint32_t)__popcll(huge));
+            if (big) qb = atomicAdd(&n_queued[1], (uint32_t)__popcll(big));
+            if (mid) qm = atomicAdd(&n_queued[0], (uint32_t)__popcll(mid));
+            if (lng) atomicOr(note, wide ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
+        }
+        qh = (uint32_t)__shfl((int)qh, 0);
+        qb = (uint32_t)__shfl((int)qb, 0);
+        qm = (uint32_t)__shfl((int)qm, 0);
+        const uint64_t lt = lanemask_lt();
+        if ((huge >> threadIdx.x) & 1ull) queue_large[nlists - 1u - (qh + (uint32_t)__popcll(huge & lt))] = l;
+        if ((big >> threadIdx.x) & 1ull) queue_large[qb + (uint32_t)__popcll(big & lt)] = l;
+        if ((mid >> threadIdx.x) & 1ull) queue_mid[qm + (uint32_t)__popcll(mid & lt)] = l;
+    }
     const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
     const uint32_t m = end > start ? end - start : 0u;
-    if (m > (uint32_t)kSegWave) {
-        if (threadIdx.x == 0) {
-            if (m > kLongList) atomicOr(note, m > kSortNoteList ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
-            if (m > kSortNoteList) {
-                // left to global passes over the whole key (the host reads the note)
-            } else if (m > (uint32_t)kSegSmall) {
-                queue_large[atomicAdd(&n_queued[1], 1u)] = list;
-            } else {
-                queue_mid[atomicAdd(&n_queued[0], 1u)] = list;
-            }
-        }
-        return;
-    }
-    if (m < 2) return;
+    if (m > (uint32_t)kSegWave || m < 2) return;
     seg_sort_lds<1>(sh, keys, vals, start, m, (uint64_t)list << 32);
 }
 
@@ -441,12 +516,43 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
     uint32_t *vsrc = vals, *vdst = vals_alt;
     int moved = 0;
     if (t < 4) sh.skip[t] = 0u;
-    for (int shift = 0; shift < 32; shift += kBits) {
+    // depth words as offsets from the run's minimum, over the bits of their span
+    // (sweeps over the run load eight entries per thread before using them)
+    uint32_t mn = ~0u, mx = 0u;
+    for (uint32_t e0 = t; e0 < m; e0 += 8 * nthr) {
+        uint32_t kk[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t e = e0 + (uint32_t)(j * nthr);
+            kk[j] = e < m ? (uint32_t)keys[start + e] : ~0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (e0 + (uint32_t)(j * nthr) < m) {
+                mn = min(mn, kk[j]);
+                mx = max(mx, kk[j]);
+            }
+        }
+    }
+    seg_minmax<W>(sh, mn, mx);
+    const uint32_t span = mx - mn;
+    const int bits = span ? 32 - __clz((int)span) : 0;
+    for (int shift = 0; shift < bits; shift += kBits) {
         uint32_t *skip = &sh.skip[shift / kBits];
         // digit totals of the whole run
         if (t < kBins) hist[t] = 0u;
         __syncthreads();
-        for (uint32_t e = t; e < m; e += nthr) atomicAdd(&hist[((uint32_t)ksrc[start + e] >> shift) & (kBins - 1)], 1u);
+        for (uint32_t e0 = t; e0 < m; e0 += 8 * nthr) {
+            uint32_t kk[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t e = e0 + (uint32_t)(j * nthr);
+                kk[j] = e < m ? (uint32_t)ksrc[start + e] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (e0 + (uint32_t)(j * nthr) < m) atomicAdd(&hist[((kk[j] - mn) >> shift) & (kBins - 1)], 1u);
+        }
         __syncthreads();
         if (t < kBins) {
             const uint32_t c = hist[t];
@@ -471,23 +577,24 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
         for (uint32_t c0 = 0; c0 < m; c0 += (uint32_t)kSegLarge) {
             const uint32_t mc = m - c0 < (uint32_t)kSegLarge ? m - c0 : (uint32_t)kSegLarge;
             const uint32_t e0 = (uint32_t)wave * 512u;
-            uint32_t k[kSegItems], v[kSegItems], d[kSegItems], rank[kSegItems];
+            uint32_t k[kSegItems], v[kSegItems], dr[kSegItems];
 #pragma unroll
             for (int r = 0; r < kSegItems; ++r) {
                 const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
-                k[r] = e < mc ? (uint32_t)ksrc[start + c0 + e] : 0u;
+                k[r] = e < mc ? (uint32_t)ksrc[start + c0 + e] - mn : 0u;
                 v[r] = e < mc ? vsrc[start + c0 + e] : 0u;
             }
-            for (int i = t; i < W * kBins; i += nthr) (&sh.cnt[0][0])[i] = 0u;
+            for (int i = t; i < W * kBins / 2; i += nthr) ((uint32_t *)&sh.cnt[0][0])[i] = 0u;
             __syncthreads();
-            seg_rank<W>(sh, k, e0, mc, shift, kSegItems, d, rank);
+            seg_rank<W>(sh, k, e0, mc, shift, kSegItems, dr);
             __syncthreads();
             seg_scan<W>(sh, mc, nullptr);
             // stage in digit order, then write each digit's run to its place
 #pragma unroll
             for (int r = 0; r < kSegItems; ++r) {
                 if (e0 + (uint32_t)(r * 64 + lane) < mc) {
-                    const uint32_t pos = sh.lbase[d[r]] + sh.cnt[wave][d[r]] + rank[r];
+                    const uint32_t dg = dr[r] & (kBins - 1);
+                    const uint32_t pos = sh.lbase[dg] + sh.cnt[wave][dg] + (dr[r] >> 8);
                     sh.key[pos] = k[r];
                     sh.val[pos] = v[r];
                 }
@@ -497,7 +604,7 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
                 const uint32_t kk = sh.key[i];
                 const uint32_t dg = (kk >> shift) & (kBins - 1);
                 const uint64_t pos = start + gbase[dg] + run[dg] + (i - sh.lbase[dg]);
-                kdst[pos] = hi | kk;
+                kdst[pos] = hi | (kk + mn);
                 vdst[pos] = sh.val[i];
             }
             __syncthreads();
@@ -516,22 +623,31 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
     }
 }
 
-__global__ __launch_bounds__(1024) void k_seg_large(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                    uint64_t *__restrict__ keys_alt, uint32_t *__restrict__ vals_alt,
-                                                    const uint32_t *__restrict__ ranges,
-                                                    const uint32_t *__restrict__ queue,
-                                                    const uint32_t *__restrict__ n_queued)
+// Lists of kSegSmall + 1 .. kSegLarge entries: at most 64 registers, so that
+// two workgroups share a CU (one sorts while the other loads or stores).
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_seg_large(
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, const uint32_t *__restrict__ ranges,
+    const uint32_t *__restrict__ queue, const uint32_t *__restrict__ n_queued)
 {
     __shared__ SegShared<16> sh;
     if (blockIdx.x >= *n_queued) return;
     const uint32_t list = queue[blockIdx.x];
     const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
-    const uint32_t m = end - start;
-    const uint64_t hi = (uint64_t)list << 32;
-    if (m <= (uint32_t)kSegLarge)
-        seg_sort_lds<16>(sh, keys, vals, start, m, hi);
-    else
-        seg_sort_global(sh, keys, vals, keys_alt, vals_alt, start, m, hi);
+    seg_sort_lds<16>(sh, keys, vals, start, end - start, (uint64_t)list << 32);
+}
+
+// Lists of kSegLarge + 1 .. kSortNoteList entries, queued from the back.
+__global__ __launch_bounds__(1024) void k_seg_huge(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                   uint64_t *__restrict__ keys_alt, uint32_t *__restrict__ vals_alt,
+                                                   const uint32_t *__restrict__ ranges,
+                                                   const uint32_t *__restrict__ queue_end,
+                                                   const uint32_t *__restrict__ n_queued)
+{
+    __shared__ SegShared<16> sh;
+    if (blockIdx.x >= *n_queued) return;
+    const uint32_t list = queue_end[-1 - (int64_t)blockIdx.x];
+    const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
+    seg_sort_global(sh, keys, vals, keys_alt, vals_alt, start, end - start, (uint64_t)list << 32);
 }
 
 }  // namespace
@@ -594,8 +710,12 @@ hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *ke
         hipLaunchKernelGGL(k_seg_mid, dim3((unsigned)mid), dim3(256), 0, s, keys, vals, ranges, queues, n_queued);
     const uint64_t large = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
     if (large)
-        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
-                           queues + nlists, n_queued + 1);
+        hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, ranges, queues + nlists,
+                           n_queued + 1);
+    const uint64_t huge = std::min<uint64_t>((uint64_t)nlists, n / (kSegLarge + 1));
+    if (huge)
+        hipLaunchKernelGGL(k_seg_huge, dim3((unsigned)huge), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
+                           queues + 2 * nlists, n_queued + 2);
     return hipGetLastError();
 }
 
