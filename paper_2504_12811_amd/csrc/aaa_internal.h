@@ -288,19 +288,22 @@ size_t sort_tmp_bytes(uint64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                             int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt);
 // Phase 2 of the pair sort: the lists [ranges[2 l], ranges[2 l + 1]) of
-// keys/vals sorted in place by the low word of their keys (stable).  First
-// kernel: lists of up to 512 entries, the others queued (queues holds
-// 2 nlists entries, n_queued[0..2] zero at entry); lists longer than
-// kLongList / kSortNoteList set the bits kNoteLongRoute / kNoteSortWide of
-// *note, and those longer than kSortNoteList are left to global passes over
-// the whole key (the caller's).  The rest: the queued lists (the other
+// keys/vals sorted in place by the low word of their keys (stable).
+// Classification first: lists of more than 512 entries are queued (queues
+// holds 2 nlists entries, n_queued[0..2] zero at entry) and noted in *note
+// (kNoteSortMid / Large / Huge); lists longer than kLongList / kSortNoteList
+// set the bits kNoteLongRoute / kNoteSortWide, and those longer than
+// kSortNoteList are left to global passes over the whole key (the
+// caller's).  Then, in any order: the lists of up to 512 entries (short),
+// and the queued lists of the tiers whose bits `which` has (rest; the other
 // buffers are scratch for lists longer than 8192 entries).
-hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
-                                     int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
-                                     hipStream_t s);
+hipError_t launch_segment_classify(uint64_t n, const uint32_t *ranges, int64_t nlists, uint32_t *queues,
+                                   uint32_t *n_queued, uint32_t *note, hipStream_t s);
+hipError_t launch_segment_sort_short(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
+                                     int64_t nlists, hipStream_t s);
 hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
                                     uint64_t n, const uint32_t *ranges, int64_t nlists, const uint32_t *queues,
-                                    const uint32_t *n_queued, hipStream_t s);
+                                    const uint32_t *n_queued, uint32_t which, hipStream_t s);
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
 
 struct BlendArgs {
@@ -356,6 +359,9 @@ constexpr uint32_t kMaxLongTiles = 1024;  // ... when at most this many tiles ar
 // Bits of the note the per-list sort publishes to the host.
 constexpr uint32_t kNoteSortWide = 1u;    // a list longer than kSortNoteList
 constexpr uint32_t kNoteLongRoute = 2u;   // a list longer than kLongList
+constexpr uint32_t kNoteSortMid = 4u;     // lists queued for each of the three longer per-list sorts
+constexpr uint32_t kNoteSortLarge = 8u;
+constexpr uint32_t kNoteSortHuge = 16u;
 
 struct GradOut {
     float *means, *log_scales, *quats, *logits, *sh;

@@ -237,7 +237,7 @@ __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t
 // which gives the order of a full LSD sort of the 64-bit keys.  One
 // workgroup per list:
 //  - k_seg_first (1 wave): runs of 2..kSegWave entries, in registers and
-//    LDS; longer runs are queued for
+//    LDS; longer runs are queued (k_seg_classify, run before) for
 //  - k_seg_mid (4 waves): runs up to kSegSmall entries the same way,
 //  - k_seg_large (16 waves): runs up to kSegLarge entries the same way, or
 //  - k_seg_huge (16 waves): longer runs by 8-bit LSD passes over the run in
@@ -440,49 +440,58 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     }
 }
 
-// queue_mid: lists of kSegWave + 1 .. kSegSmall entries; queue_large: from
-// its front the lists of kSegSmall + 1 .. kSegLarge entries, from its back
-// (queue_large[nlists - 1 - j]) the longer ones up to kSortNoteList (the two
-// together hold at most nlists lists); counts in n_queued[0..2].
+// One thread per list: lists that need more than one wave are filed for
+// the longer sorts (one atomic per queue and wave).  queue_mid: lists of
+// kSegWave + 1 .. kSegSmall entries; queue_large: from its front the lists of
+// kSegSmall + 1 .. kSegLarge entries, from its back (queue_large[nlists - 1
+// - j]) the longer ones up to kSortNoteList (the two together hold at most
+// nlists lists); counts in n_queued[0..2], and the bit of each tier that
+// has lists in *note.  Lists longer than kLongList / kSortNoteList set the
+// bits kNoteLongRoute / kNoteSortWide; the latter are left to global passes
+// over the whole key (the host reads the note).
+__global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__restrict__ ranges, uint32_t nlists,
+                                                      uint32_t *__restrict__ queue_mid,
+                                                      uint32_t *__restrict__ queue_large,
+                                                      uint32_t *__restrict__ n_queued, uint32_t *__restrict__ note)
+{
+    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
+    if (blockIdx.x * 256u + (threadIdx.x & ~63u) >= nlists) return;  // uniform per wave
+    uint32_t ml = 0u;
+    if (l < nlists) {
+        const uint32_t a = ranges[2 * l], b = ranges[2 * l + 1];
+        ml = b > a ? b - a : 0u;
+    }
+    const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
+    const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
+    const uint64_t mid = __ballot(ml > (uint32_t)kSegWave && ml <= (uint32_t)kSegSmall);
+    const uint64_t lng = __ballot(ml > kLongList);
+    const uint64_t wide = __ballot(ml > kSortNoteList);
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t qh = 0u, qb = 0u, qm = 0u;
+    if (lane == 0) {
+        if (huge) qh = atomicAdd(&n_queued[2], (uint32_t)__popcll(huge));
+        if (big) qb = atomicAdd(&n_queued[1], (uint32_t)__popcll(big));
+        if (mid) qm = atomicAdd(&n_queued[0], (uint32_t)__popcll(mid));
+        const uint32_t bits = (huge ? kNoteSortHuge : 0u) | (big ? kNoteSortLarge : 0u) | (mid ? kNoteSortMid : 0u) |
+                              (lng ? kNoteLongRoute : 0u) | (wide ? kNoteSortWide : 0u);
+        if (bits) atomicOr(note, bits);
+    }
+    qh = (uint32_t)__shfl((int)qh, 0);
+    qb = (uint32_t)__shfl((int)qb, 0);
+    qm = (uint32_t)__shfl((int)qm, 0);
+    const uint64_t lt = lanemask_lt();
+    if ((huge >> lane) & 1ull) queue_large[nlists - 1u - (qh + (uint32_t)__popcll(huge & lt))] = l;
+    if ((big >> lane) & 1ull) queue_large[qb + (uint32_t)__popcll(big & lt)] = l;
+    if ((mid >> lane) & 1ull) queue_mid[qm + (uint32_t)__popcll(mid & lt)] = l;
+}
+
+// Lists of 2 .. kSegWave entries, one wave each.
 __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                  const uint32_t *__restrict__ ranges, uint32_t nlists,
-                                                  uint32_t *__restrict__ queue_mid, uint32_t *__restrict__ queue_large,
-                                                  uint32_t *__restrict__ n_queued, uint32_t *__restrict__ note)
+                                                  const uint32_t *__restrict__ ranges, uint32_t nlists)
 {
     __shared__ SegShared<1> sh;
     const uint32_t list = blockIdx.x;
     if (list >= nlists) return;
-    if ((list & 63u) == 0u) {
-        // This workgroup files the lists list .. list + 63 that need more
-        // than one wave (one atomic per queue for the 64 lists); lists
-        // longer than kSortNoteList are left to global passes over the whole
-        // key (the host reads the note).
-        const uint32_t l = list + threadIdx.x;
-        uint32_t ml = 0u;
-        if (l < nlists) {
-            const uint32_t a = ranges[2 * l], b = ranges[2 * l + 1];
-            ml = b > a ? b - a : 0u;
-        }
-        const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
-        const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
-        const uint64_t mid = __ballot(ml > (uint32_t)kSegWave && ml <= (uint32_t)kSegSmall);
-        const uint64_t lng = __ballot(ml > kLongList);
-        const uint64_t wide = __ballot(ml > kSortNoteList);
-        uint32_t qh = 0u, qb = 0u, qm = 0u;
-        if (threadIdx.x == 0) {
-            if (huge) qh = atomicAdd(&n_queued[2], (uint32_t)__popcll(huge));
-            if (big) qb = atomicAdd(&n_queued[1], (uint32_t)__popcll(big));
-            if (mid) qm = atomicAdd(&n_queued[0], (uint32_t)__popcll(mid));
-            if (lng) atomicOr(note, wide ? kNoteSortWide | kNoteLongRoute : kNoteLongRoute);
-        }
-        qh = (uint32_t)__shfl((int)qh, 0);
-        qb = (uint32_t)__shfl((int)qb, 0);
-        qm = (uint32_t)__shfl((int)qm, 0);
-        const uint64_t lt = lanemask_lt();
-        if ((huge >> threadIdx.x) & 1ull) queue_large[nlists - 1u - (qh + (uint32_t)__popcll(huge & lt))] = l;
-        if ((big >> threadIdx.x) & 1ull) queue_large[qb + (uint32_t)__popcll(big & lt)] = l;
-        if ((mid >> threadIdx.x) & 1ull) queue_mid[qm + (uint32_t)__popcll(mid & lt)] = l;
-    }
     const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
     const uint32_t m = end > start ? end - start : 0u;
     if (m > (uint32_t)kSegWave || m < 2) return;
@@ -689,30 +698,37 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     return hipSuccess;
 }
 
-hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
-                                     int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
-                                     hipStream_t s)
+hipError_t launch_segment_classify(uint64_t n, const uint32_t *ranges, int64_t nlists, uint32_t *queues,
+                                   uint32_t *n_queued, uint32_t *note, hipStream_t s)
 {
     if (n <= 1 || nlists <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists,
-                       queues, queues + nlists, n_queued, note);
+    hipLaunchKernelGGL(k_seg_classify, dim3((unsigned)((nlists + 255) / 256)), dim3(256), 0, s, ranges,
+                       (uint32_t)nlists, queues, queues + nlists, n_queued, note);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sort_short(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
+                                     int64_t nlists, hipStream_t s)
+{
+    if (n <= 1 || nlists <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists);
     return hipGetLastError();
 }
 
 hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
                                     uint64_t n, const uint32_t *ranges, int64_t nlists, const uint32_t *queues,
-                                    const uint32_t *n_queued, hipStream_t s)
+                                    const uint32_t *n_queued, uint32_t which, hipStream_t s)
 {
     if (n <= 1 || nlists <= 0) return hipSuccess;
     // at most n / (L + 1) runs are longer than L entries
-    const uint64_t mid = std::min<uint64_t>((uint64_t)nlists, n / (kSegWave + 1));
+    const uint64_t mid = (which & kNoteSortMid) ? std::min<uint64_t>((uint64_t)nlists, n / (kSegWave + 1)) : 0;
     if (mid)
         hipLaunchKernelGGL(k_seg_mid, dim3((unsigned)mid), dim3(256), 0, s, keys, vals, ranges, queues, n_queued);
-    const uint64_t large = std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1));
+    const uint64_t large = (which & kNoteSortLarge) ? std::min<uint64_t>((uint64_t)nlists, n / (kSegSmall + 1)) : 0;
     if (large)
         hipLaunchKernelGGL(k_seg_large, dim3((unsigned)large), dim3(1024), 0, s, keys, vals, ranges, queues + nlists,
                            n_queued + 1);
-    const uint64_t huge = std::min<uint64_t>((uint64_t)nlists, n / (kSegLarge + 1));
+    const uint64_t huge = (which & kNoteSortHuge) ? std::min<uint64_t>((uint64_t)nlists, n / (kSegLarge + 1)) : 0;
     if (huge)
         hipLaunchKernelGGL(k_seg_huge, dim3((unsigned)huge), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
                            queues + 2 * nlists, n_queued + 2);

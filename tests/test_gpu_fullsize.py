@@ -126,10 +126,9 @@ def test_pair_order_long_lists(ras, ood, view):
 
 
 def test_sort_routes_agree(ras, ood):
-    """A view with lists of 10^5 entries rendered twice: after a view without
-    long lists its lists are sorted one workgroup each, the second time (the
-    workspace noted the long lists) by global passes over the whole key.
-    Pairs and images must be identical."""
+    """A view with lists of 10^5 entries (sorted by global passes over the
+    whole key, a route each call chooses from its own lists) rendered twice
+    after a view without long lists: pairs and images must be identical."""
     scene, cam0, zoom = ood
     from test_gpu_forward import dev
     ds = dev(scene)
