@@ -271,7 +271,17 @@ hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 
                               bool tile_cull, bool subtile, hipStream_t s);
 // host[0] = *a, host[1] = *b, host[3] = *note (then *note = 0; none when
 // note is null), then host[2] = seq (system scope, in that order; host:
-// coherent pinned memory): one launch instead of small copies
+// coherent pinned memory).  One thread.
+__device__ __forceinline__ void publish_words(const uint64_t *a, const uint64_t *b, uint64_t *host, uint64_t seq,
+                                              uint32_t *note)
+{
+    host[0] = *a;
+    host[1] = *b;
+    if (note) host[3] = atomicExch(note, 0u);
+    __threadfence_system();
+    __hip_atomic_store(&host[2], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// publish_words in a one-thread launch (instead of small copies)
 hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, uint64_t seq, uint32_t *note,
                            hipStream_t s);
 // p[i] &= mask for i < n
@@ -285,26 +295,36 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int6
                                  const uint64_t *count_of = nullptr);
 
 size_t sort_tmp_bytes(uint64_t n);
+// Stable LSD sort by bits [begin_bit, end_bit); clear[0 .. nclear) is
+// zeroed on the way (by the first pass).
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
-                            int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt);
+                            int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt,
+                            uint32_t *clear = nullptr, uint64_t nclear = 0);
 // Phase 2 of the pair sort: the lists [ranges[2 l], ranges[2 l + 1]) of
-// keys/vals sorted in place by the low word of their keys (stable).
-// Classification first: lists of more than 512 entries are queued (queues
-// holds 2 nlists entries, n_queued[0..2] zero at entry) and noted in *note
-// (kNoteSortMid / Large / Huge); lists longer than kLongList / kSortNoteList
-// set the bits kNoteLongRoute / kNoteSortWide, and those longer than
-// kSortNoteList are left to global passes over the whole key (the
-// caller's).  Then, in any order: the lists of up to 512 entries (short),
-// and the queued lists of the tiers whose bits `which` has (rest; the other
-// buffers are scratch for lists longer than 8192 entries).
-hipError_t launch_segment_classify(uint64_t n, const uint32_t *ranges, int64_t nlists, uint32_t *queues,
-                                   uint32_t *n_queued, uint32_t *note, hipStream_t s);
-hipError_t launch_segment_sort_short(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
-                                     int64_t nlists, hipStream_t s);
+// keys/vals sorted in place by the low word of their keys (stable).  First
+// kernel: the lists of up to 512 entries; the longer ones are queued
+// (queues holds 2 nlists entries, n_queued[0..2], *note and *done zero at
+// entry) and noted in *note (kNoteSortMid / Large / Huge); lists longer
+// than kLongList / kSortNoteList set the bits kNoteLongRoute /
+// kNoteSortWide, and those longer than kSortNoteList are left to global
+// passes over the whole key (the caller's).  Once every list is filed the
+// kernel publishes (publish_words) pub_a, pub_b and the note with sequence
+// number seq.  Then: the queued lists of the tiers whose bits `which` has
+// (rest; the other buffers are scratch for lists longer than 8192 entries).
+struct SortPublish {
+    const uint64_t *a, *b;
+    uint64_t *host;
+    uint64_t seq;
+};
+hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
+                                     int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
+                                     uint32_t *done, SortPublish pub, hipStream_t s);
 hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
                                     uint64_t n, const uint32_t *ranges, int64_t nlists, const uint32_t *queues,
                                     const uint32_t *n_queued, uint32_t which, hipStream_t s);
-hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s);
+// ranges [ntiles][2] of the sorted keys (cleared first unless `cleared`)
+hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s,
+                              bool cleared = false);
 
 struct BlendArgs {
     const float4 *rec;             // per item (i * nviews + v)

@@ -598,8 +598,9 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     // Pair sort.  Phase 1: LSD passes over the list bits (the high word);
     // phase 2 (below) sorts each list by the depth word.
     bool in_alt = false;
+    uint32_t *ranges = at<uint32_t>(ws, L.ranges);  // cleared by the first pass
     HIP_TRY(aaa::radix_sort_pairs(keys, vals, keys_alt, vals_alt, P, 32, key_bits(nlists), at<void>(ws, L.sort_tmp),
-                                  s, &in_alt));
+                                  s, &in_alt, ranges, 2 * (uint64_t)nlists));
     if (P > 1 && in_alt != sorted_in_alt(nlists)) return fail(AAA_ERR_HIP, "internal: sort parity");
     uint64_t *skeys = (P > 1 && in_alt) ? keys_alt : keys;
     uint32_t *svals = (P > 1 && in_alt) ? vals_alt : vals;
@@ -611,27 +612,27 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
         svals = vals_alt;
     }
     STAGE_MARK(6);
-    uint32_t *ranges = at<uint32_t>(ws, L.ranges);
-    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s));
+    HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s, true));
     STAGE_MARK(7);
     // Phase 2: each list sorted by the depth word in place (the other pair
-    // buffer is scratch for long lists).  A classification kernel queues
-    // the lists of more than 512 entries, notes lists longer than kLongList
-    // and kSortNoteList and leaves the latter out (far views: most pairs in
-    // a few lists, which one workgroup each would sort far below the chip's
-    // bandwidth); the note is published while the per-list sorts run.  With such a list, global passes over the whole key
+    // buffer is scratch for long lists).  Its first kernel sorts the lists
+    // of up to 512 entries, queues the longer ones, notes lists longer than
+    // kLongList and kSortNoteList and leaves the latter out (far views: most
+    // pairs in a few lists, which one workgroup each would sort far below
+    // the chip's bandwidth); it publishes the note once every list is filed,
+    // while its sorts still run.  With such a list, global passes over the whole key
     // sort all pairs from the current order (stable: the order of a full
     // sort; tile boundaries, and so the ranges, are unchanged).
     uint64_t *okeys = skeys == keys ? keys_alt : keys;
     uint32_t *ovals = svals == vals ? vals_alt : vals;
     uint32_t *queues = at<uint32_t>(ws, L.seg_long), *n_queued = (uint32_t *)(ctr + 11);
-    uint32_t *list_note = (uint32_t *)(ctr + 13);  // zeroed with the counters
-    HIP_TRY(aaa::launch_segment_classify(P, ranges, nlists, queues, n_queued, list_note, s));
-    uint64_t seq = 0;
-    HIP_TRY(publish(ctx, kept_before + chunks, area_off + items, s, &seq, list_note));
+    uint32_t *list_note = (uint32_t *)(ctr + 13), *list_done = list_note + 1;  // zeroed with the counters
     // the host reads the note while the short lists sort, then enqueues only
     // the tiers that have lists
-    HIP_TRY(aaa::launch_segment_sort_short(skeys, svals, P, ranges, nlists, s));
+    const uint64_t seq = ++ctx->sync_seq;
+    HIP_TRY(aaa::launch_segment_sort_first(skeys, svals, P, ranges, nlists, queues, n_queued, list_note, list_done,
+                                           aaa::SortPublish{kept_before + chunks, area_off + items, ctx->sync_host, seq},
+                                           s));
     HIP_TRY(wait_published(ctx, s, seq));
     const uint32_t lists = P > 1 ? (uint32_t)ctx->sync_host[3] : 0u;
     if (!(lists & aaa::kNoteSortWide))

@@ -390,16 +390,7 @@ hipError_t launch_write_pairs(const int4 *rect, const float4 *rec, const float4 
 __global__ void k_publish2(const uint64_t *__restrict__ a, const uint64_t *__restrict__ b, uint64_t *host, uint64_t seq,
                            uint32_t *note)
 {
-    if (threadIdx.x == 0) {
-        host[0] = *a;
-        host[1] = *b;
-        if (note) {
-            host[3] = *note;
-            *note = 0u;
-        }
-        __threadfence_system();
-        __hip_atomic_store(&host[2], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
+    if (threadIdx.x == 0) publish_words(a, b, host, seq, note);
 }
 
 hipError_t launch_publish2(const uint64_t *a, const uint64_t *b, uint64_t *host, uint64_t seq, uint32_t *note,

@@ -36,28 +36,35 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// The lanes of the wave whose 8-bit digit d equals this lane's, among the
-// lanes with `valid` set.  One ballot per digit bit; each lane ORs into its
-// mask of disagreeing lanes the bit's ballot XOR its own bit spread over a
-// word (0 or ~0), one three-input bit operation per mask half.
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid)
+// The lanes of the wave whose digit d (nbits <= MAXB bits, the higher ones
+// zero) equals this lane's, among the lanes with `valid` set.  One ballot per
+// digit bit; each lane ORs into its mask of disagreeing lanes the bit's
+// ballot XOR its own bit spread over a word (0 or ~0), one three-input bit
+// operation per mask half.
+template <int MAXB = kBits>
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid, int nbits = MAXB)
 {
     const uint64_t v = __ballot(valid);
     uint32_t lo = ~(uint32_t)v, hi = ~(uint32_t)(v >> 32);
 #pragma unroll
-    for (int b = 0; b < kBits; ++b) {
-        uint32_t own;  // bit b of d spread over the word (written as one v_bfe_i32)
-        asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(own) : "v"(d), "i"(b));
-        const uint64_t bb = __ballot(own != 0u);
-        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, own, 0xF6);  // lo | (bb ^ own)
-        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), own, 0xF6);
+    for (int b = 0; b < MAXB; ++b) {
+        if (b < nbits) {  // uniform
+            uint32_t own;  // bit b of d spread over the word (written as one v_bfe_i32)
+            asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(own) : "v"(d), "i"(b));
+            const uint64_t bb = __ballot(own != 0u);
+            lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, own, 0xF6);  // lo | (bb ^ own)
+            hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), own, 0xF6);
+        }
     }
     return ~(((uint64_t)hi << 32) | lo);
 }
 
 __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift,
-                                                   uint32_t *__restrict__ hist, uint32_t nblocks)
+                                                   int nbits, uint32_t *__restrict__ hist, uint32_t nblocks,
+                                                   uint32_t *__restrict__ clear, uint64_t nclear)
 {
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < nclear; i += (uint64_t)gridDim.x * kThreads)
+        clear[i] = 0u;
     __shared__ uint32_t h[4][kBins];
     const int t = threadIdx.x, wave = t >> 6;
     for (int k = t; k < 4 * kBins; k += kThreads) (&h[0][0])[k] = 0;
@@ -67,13 +74,13 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
     for (int k = 0; k < kItems; ++k) {
         uint64_t idx = b0 + (uint64_t)k * kThreads + t;
         if (idx < n) {
-            uint32_t d = (uint32_t)(keys[idx] >> shift) & (kBins - 1);
+            uint32_t d = (uint32_t)(keys[idx] >> shift) & ((1u << nbits) - 1u);
             atomicAdd(&h[wave][d], 1u);
         }
     }
     __syncthreads();
     uint32_t s = h[0][t] + h[1][t] + h[2][t] + h[3][t];
-    hist[(uint64_t)t * nblocks + blockIdx.x] = s;
+    if (t < (1 << nbits)) hist[(uint64_t)t * nblocks + blockIdx.x] = s;
 }
 
 // Row d of the [digit][block] table: exclusive prefix over the blocks, in
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ 
 
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ keys_in,
                                                       const uint32_t *__restrict__ vals_in, uint64_t n, int shift,
-                                                      const uint32_t *__restrict__ offsets,
+                                                      int nbits, const uint32_t *__restrict__ offsets,
                                                       const uint32_t *__restrict__ totals, uint32_t nblocks,
                                                       uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out)
 {
@@ -146,9 +153,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         valid[r] = idx < n;
         key[r] = valid[r] ? keys_in[idx] : 0ull;
         val[r] = valid[r] ? vals_in[idx] : 0u;
-        uint32_t d = (uint32_t)(key[r] >> shift) & (kBins - 1);
+        uint32_t d = (uint32_t)(key[r] >> shift) & ((1u << nbits) - 1u);
         dig[r] = d;
-        const uint64_t m = match_digit(d, valid[r]);
+        const uint64_t m = match_digit(d, valid[r], nbits);
         uint32_t before = (uint32_t)__popcll(m & lt);
         uint32_t base = 0;
         if (valid[r]) base = cnt[wave][d];
@@ -167,7 +174,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     }
     // exclusive scans over the 256 digits of the block totals (block-local
     // starts) and of the global digit totals (global starts)
-    const uint64_t dt = totals[t];
+    const bool live = t < (1 << nbits);  // digits past 2^nbits are empty
+    const uint64_t dt = live ? totals[t] : 0u;
     uint32_t x = tot;
     uint64_t gx = dt;
     for (int off = 1; off < 64; off <<= 1) {
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         gpre += gsum[w];
     }
     lbase[t] = wpre + x - tot;
-    gbase[t] = gpre + gx - dt + offsets[(uint64_t)t * nblocks + blockIdx.x];
+    gbase[t] = gpre + gx - dt + (live ? offsets[(uint64_t)t * nblocks + blockIdx.x] : 0u);
     __syncthreads();
     // stage the block's pairs in digit order (stable: wave order, then rank)
 #pragma unroll
@@ -206,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     const uint32_t nloc = (uint32_t)(n - b0 < (uint64_t)kPerBlock ? n - b0 : (uint64_t)kPerBlock);
     for (uint32_t i = t; i < nloc; i += kThreads) {
         const uint64_t k = skey[i];
-        const uint32_t d = (uint32_t)(k >> shift) & (kBins - 1);
+        const uint32_t d = (uint32_t)(k >> shift) & ((1u << nbits) - 1u);
         const uint64_t pos = gbase[d] + (i - lbase[d]);
         keys_out[pos] = k;
         vals_out[pos] = sval[i];
@@ -237,7 +245,7 @@ __global__ void k_ranges(const uint64_t *__restrict__ keys, uint64_t n, uint32_t
 // which gives the order of a full LSD sort of the 64-bit keys.  One
 // workgroup per list:
 //  - k_seg_first (1 wave): runs of 2..kSegWave entries, in registers and
-//    LDS; longer runs are queued (k_seg_classify, run before) for
+//    LDS; longer runs are queued for
 //  - k_seg_mid (4 waves): runs up to kSegSmall entries the same way,
 //  - k_seg_large (16 waves): runs up to kSegLarge entries the same way, or
 //  - k_seg_huge (16 waves): longer runs by 8-bit LSD passes over the run in
@@ -258,38 +266,57 @@ constexpr int kSegWave = 64 * kSegItems;         // 512
 constexpr int kSegSmall = 4 * 64 * kSegItems;    // 2048
 constexpr int kSegLarge = 16 * 64 * kSegItems;   // 8192
 
-// Per-wave counts fit 16 bits (at most 512 entries per wave, prefixes at
-// most 16 * 512), which keeps the 16-wave form at two workgroups per CU.
+// Counts and digit starts fit 16 bits (at most 512 entries per wave and
+// 16 * 512 per run or chunk), which keeps the 16-wave form at two
+// workgroups per CU.  Digits of up to kB bits (9-bit digits for one and four
+// waves, a 25-27-bit span in three passes instead of four, measured slower).
+// With one wave these words are not needed (ballots instead), which keeps
+// the one-wave form at 5 KB (eight workgroups per SIMD).
 template <int W>
-struct SegShared {
-    alignas(16) uint16_t cnt[W][kBins];   // per-wave digit counts, then per-wave prefixes
-    alignas(16) uint32_t lbase[kBins];    // start of each digit in the run or chunk
-    alignas(16) uint32_t tot[kBins];      // digit totals of the run or chunk
-    uint32_t wsum[4];
+struct SegExtra {
     uint32_t skip[4];         // per pass: one digit holds the whole run (set once, never reset)
     uint32_t red[2][W];       // per-wave minimum and maximum of the depth words
+};
+template <>
+struct SegExtra<1> {};
+
+template <int W>
+struct SegShared : SegExtra<W> {
+    static constexpr int kB = 8;
+    static constexpr int kNB = 1 << kB;
+    alignas(16) uint16_t cnt[W][kNB];   // per-wave digit counts, then per-wave prefixes
+    alignas(16) uint16_t lbase[kNB];    // start of each digit in the run or chunk
     uint32_t key[W * 64 * kSegItems];
     uint32_t val[W * 64 * kSegItems];
 };
 
-// Rank the wave's valid entries (e < m) by digit; per-wave counts in
-// sh.cnt[wave].  Returns digit | rank << 8 in dr[] (ranks below 2^13).
+// Width of pass `pass` of `passes` over `bits` bits: (nearly) equal digits.
+__device__ __forceinline__ int digit_bits(int bits, int passes, int pass)
+{
+    const int done = (bits * pass) / passes;
+    return (bits * (pass + 1)) / passes - done;
+}
+
+// Rank the wave's valid entries (e < m) by their digit of nbits bits at
+// `shift`; per-wave counts in sh.cnt[wave].  Returns digit | rank << 16 in
+// dr[] (ranks below 2^13).
 template <int W>
 __device__ __forceinline__ void seg_rank(SegShared<W> &sh, const uint32_t (&k)[kSegItems], uint32_t e0, uint32_t m,
-                                         int shift, int rounds, uint32_t (&dr)[kSegItems])
+                                         int shift, int nbits, int rounds, uint32_t (&dr)[kSegItems])
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
+    const uint32_t mask = (1u << nbits) - 1u;
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
         if (r < rounds) {
             const bool valid = e0 + (uint32_t)(r * 64 + lane) < m;
-            const uint32_t dg = (k[r] >> shift) & (kBins - 1);
-            const uint64_t mm = match_digit(dg, valid);
+            const uint32_t dg = (k[r] >> shift) & mask;
+            const uint64_t mm = match_digit<SegShared<W>::kB>(dg, valid, nbits);
             const uint32_t before = (uint32_t)__popcll(mm & lt);
             uint32_t base = 0;
             if (valid) base = sh.cnt[wave][dg];
-            dr[r] = dg | ((base + before) << 8);
+            dr[r] = dg | ((base + before) << 16);
             __builtin_amdgcn_wave_barrier();
             if (valid && before == 0) sh.cnt[wave][dg] = (uint16_t)(base + (uint32_t)__popcll(mm));
             __builtin_amdgcn_wave_barrier();
@@ -297,66 +324,98 @@ __device__ __forceinline__ void seg_rank(SegShared<W> &sh, const uint32_t (&k)[k
     }
 }
 
-// Lane l of the first wave owns digits 4 l .. 4 l + 3: per-wave prefixes in
-// sh.cnt, totals in sh.tot, exclusive digit starts in sh.lbase (a lane-local
-// prefix, then one scan over the wave); *flag (if given) set when one digit
-// holds all m entries.  Ends with a barrier.
+// Lane l of the first wave owns digits P l .. P l + P - 1 (P = bins / 64):
+// per-wave prefixes in sh.cnt, exclusive digit starts in sh.lbase (a
+// lane-local prefix, then one scan over the wave).  Whether one digit holds
+// all m entries: *flag set (if given) before the closing barrier, and, on the
+// first wave, returned for the lane's digits.
 template <int W>
-__device__ __forceinline__ void seg_scan(SegShared<W> &sh, uint32_t m, uint32_t *flag)
+__device__ __forceinline__ bool seg_scan(SegShared<W> &sh, uint32_t m, uint32_t *flag)
 {
+    bool one = false;
+    constexpr int P = SegShared<W>::kNB / 64, WORDS = P / 2;
     const int t = threadIdx.x;
     if (t < 64) {
-        uint4 tot = make_uint4(0u, 0u, 0u, 0u);
+        uint32_t tot[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) tot[j] = 0u;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            uint2 *row = (uint2 *)&sh.cnt[w][4 * t];
-            const uint2 c = *row;
-            *row = make_uint2(tot.x | (tot.y << 16), tot.z | (tot.w << 16));
-            tot.x += c.x & 0xffffu;
-            tot.y += c.x >> 16;
-            tot.z += c.y & 0xffffu;
-            tot.w += c.y >> 16;
+            uint32_t c[WORDS], o[WORDS];
+            uint32_t *row = (uint32_t *)&sh.cnt[w][P * t];
+#pragma unroll
+            for (int j = 0; j < WORDS; ++j) o[j] = tot[2 * j] | (tot[2 * j + 1] << 16);
+            if constexpr (WORDS == 2) {
+                const uint2 x = *(uint2 *)row;
+                *(uint2 *)row = make_uint2(o[0], o[1]);
+                c[0] = x.x; c[1] = x.y;
+            } else {
+                const uint4 x = *(uint4 *)row;
+                *(uint4 *)row = make_uint4(o[0], o[1], o[2], o[3]);
+                c[0] = x.x; c[1] = x.y; c[2] = x.z; c[3] = x.w;
+            }
+#pragma unroll
+            for (int j = 0; j < WORDS; ++j) {
+                tot[2 * j] += c[j] & 0xffffu;
+                tot[2 * j + 1] += c[j] >> 16;
+            }
         }
-        *(uint4 *)&sh.tot[4 * t] = tot;
-        if (flag && (tot.x == m || tot.y == m || tot.z == m || tot.w == m)) *flag = 1u;
-        const uint32_t mine = tot.x + tot.y + tot.z + tot.w;
+        uint32_t mine = 0u;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            one = one || tot[j] == m;
+            mine += tot[j];
+        }
+        if (flag && one) *flag = 1u;
         uint32_t x = mine;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(x, off);
             if (t >= off) x += y;
         }
-        uint4 lb;
-        lb.x = x - mine;
-        lb.y = lb.x + tot.x;
-        lb.z = lb.y + tot.y;
-        lb.w = lb.z + tot.z;
-        *(uint4 *)&sh.lbase[4 * t] = lb;
+        uint32_t run = x - mine, lb[WORDS];
+#pragma unroll
+        for (int j = 0; j < WORDS; ++j) {
+            lb[j] = run | ((run + tot[2 * j]) << 16);
+            run += tot[2 * j] + tot[2 * j + 1];
+        }
+        uint32_t *lrow = (uint32_t *)&sh.lbase[P * t];
+        if constexpr (WORDS == 2)
+            *(uint2 *)lrow = make_uint2(lb[0], lb[1]);
+        else
+            *(uint4 *)lrow = make_uint4(lb[0], lb[1], lb[2], lb[3]);
     }
     __syncthreads();
+    return one;
 }
 
-// One in-LDS pass over m <= W * 512 register-resident entries.
+// One in-LDS pass (number `pass`) over m <= W * 512 register-resident
+// entries, by their digit of nbits bits at `shift`.
 template <int W>
 __device__ __forceinline__ void seg_pass(SegShared<W> &sh, uint32_t (&k)[kSegItems], uint32_t (&v)[kSegItems],
-                                         uint32_t m, int shift, uint32_t S)
+                                         uint32_t m, int shift, int nbits, int pass, uint32_t S)
 {
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int rounds = (int)(S / 64);
     const uint32_t e0 = (uint32_t)wave * S;
-    for (int i = t; i < W * kBins / 2; i += W * 64) ((uint32_t *)&sh.cnt[0][0])[i] = 0u;
+    for (int i = t; i < W * SegShared<W>::kNB / 2; i += W * 64) ((uint32_t *)&sh.cnt[0][0])[i] = 0u;
     __syncthreads();
     uint32_t dr[kSegItems];
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) asm("" : "=v"(dr[r]));  // rounds past `rounds` keep whatever is there
-    seg_rank<W>(sh, k, e0, m, shift, rounds, dr);
+    seg_rank<W>(sh, k, e0, m, shift, nbits, rounds, dr);
     __syncthreads();
-    seg_scan<W>(sh, m, &sh.skip[shift / kBits]);
-    if (sh.skip[shift / kBits]) return;  // uniform: every entry has the same digit
+    // a pass whose digit is the same for every entry moves nothing
+    if constexpr (W == 1) {
+        if (__ballot(seg_scan<W>(sh, m, nullptr)) != 0ull) return;
+    } else {
+        (void)seg_scan<W>(sh, m, &sh.skip[pass]);
+        if (sh.skip[pass]) return;  // uniform
+    }
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
         if (r < rounds && e0 + (uint32_t)(r * 64 + lane) < m) {
-            const uint32_t dg = dr[r] & (kBins - 1);
-            const uint32_t pos = sh.lbase[dg] + sh.cnt[wave][dg] + (dr[r] >> 8);
+            const uint32_t dg = dr[r] & 0xffffu;
+            const uint32_t pos = sh.lbase[dg] + sh.cnt[wave][dg] + (dr[r] >> 16);
             sh.key[pos] = k[r];
             sh.val[pos] = v[r];
         }
@@ -383,7 +442,7 @@ __device__ __forceinline__ void seg_minmax(SegShared<W> &sh, uint32_t &mn, uint3
         mn = min(mn, (uint32_t)__shfl_xor((int)mn, off));
         mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
     }
-    if (W > 1) {
+    if constexpr (W > 1) {
         const int wave = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             sh.red[0][wave] = mn;
@@ -409,7 +468,9 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     // per-wave segment: a multiple of 64, at most 512
     const uint32_t S = ((m + W * 64 - 1) / (W * 64)) * 64;
     const uint32_t e0 = (uint32_t)wave * S;
-    if (threadIdx.x < 4) sh.skip[threadIdx.x] = 0u;  // ordered by the first pass's barrier
+    if constexpr (W > 1) {
+        if (threadIdx.x < 4) sh.skip[threadIdx.x] = 0u;  // ordered by the first pass's barrier
+    }
     uint32_t k[kSegItems], v[kSegItems];
     uint32_t mn = ~0u, mx = 0u;
 #pragma unroll
@@ -429,7 +490,12 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     const int bits = 32 - __clz((int)span);
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) k[r] -= mn;
-    for (int shift = 0; shift < bits; shift += kBits) seg_pass<W>(sh, k, v, m, shift, S);
+    const int passes = (bits + SegShared<W>::kB - 1) / SegShared<W>::kB;
+    for (int pass = 0, shift = 0; pass < passes; ++pass) {
+        const int nb = digit_bits(bits, passes, pass);
+        seg_pass<W>(sh, k, v, m, shift, nb, pass, S);
+        shift += nb;
+    }
 #pragma unroll
     for (int r = 0; r < kSegItems; ++r) {
         const uint32_t e = e0 + (uint32_t)(r * 64 + lane);
@@ -440,58 +506,64 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
     }
 }
 
-// One thread per list: lists that need more than one wave are filed for
-// the longer sorts (one atomic per queue and wave).  queue_mid: lists of
-// kSegWave + 1 .. kSegSmall entries; queue_large: from its front the lists of
-// kSegSmall + 1 .. kSegLarge entries, from its back (queue_large[nlists - 1
-// - j]) the longer ones up to kSortNoteList (the two together hold at most
-// nlists lists); counts in n_queued[0..2], and the bit of each tier that
-// has lists in *note.  Lists longer than kLongList / kSortNoteList set the
-// bits kNoteLongRoute / kNoteSortWide; the latter are left to global passes
-// over the whole key (the host reads the note).
-__global__ __launch_bounds__(256) void k_seg_classify(const uint32_t *__restrict__ ranges, uint32_t nlists,
-                                                      uint32_t *__restrict__ queue_mid,
-                                                      uint32_t *__restrict__ queue_large,
-                                                      uint32_t *__restrict__ n_queued, uint32_t *__restrict__ note)
-{
-    const uint32_t l = blockIdx.x * 256u + threadIdx.x;
-    if (blockIdx.x * 256u + (threadIdx.x & ~63u) >= nlists) return;  // uniform per wave
-    uint32_t ml = 0u;
-    if (l < nlists) {
-        const uint32_t a = ranges[2 * l], b = ranges[2 * l + 1];
-        ml = b > a ? b - a : 0u;
-    }
-    const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
-    const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
-    const uint64_t mid = __ballot(ml > (uint32_t)kSegWave && ml <= (uint32_t)kSegSmall);
-    const uint64_t lng = __ballot(ml > kLongList);
-    const uint64_t wide = __ballot(ml > kSortNoteList);
-    const int lane = (int)(threadIdx.x & 63u);
-    uint32_t qh = 0u, qb = 0u, qm = 0u;
-    if (lane == 0) {
-        if (huge) qh = atomicAdd(&n_queued[2], (uint32_t)__popcll(huge));
-        if (big) qb = atomicAdd(&n_queued[1], (uint32_t)__popcll(big));
-        if (mid) qm = atomicAdd(&n_queued[0], (uint32_t)__popcll(mid));
-        const uint32_t bits = (huge ? kNoteSortHuge : 0u) | (big ? kNoteSortLarge : 0u) | (mid ? kNoteSortMid : 0u) |
-                              (lng ? kNoteLongRoute : 0u) | (wide ? kNoteSortWide : 0u);
-        if (bits) atomicOr(note, bits);
-    }
-    qh = (uint32_t)__shfl((int)qh, 0);
-    qb = (uint32_t)__shfl((int)qb, 0);
-    qm = (uint32_t)__shfl((int)qm, 0);
-    const uint64_t lt = lanemask_lt();
-    if ((huge >> lane) & 1ull) queue_large[nlists - 1u - (qh + (uint32_t)__popcll(huge & lt))] = l;
-    if ((big >> lane) & 1ull) queue_large[qb + (uint32_t)__popcll(big & lt)] = l;
-    if ((mid >> lane) & 1ull) queue_mid[qm + (uint32_t)__popcll(mid & lt)] = l;
-}
-
-// Lists of 2 .. kSegWave entries, one wave each.
+// Lists of 2 .. kSegWave entries, one wave each.  The first ceil(nlists /
+// 64) workgroups (dispatched first) each file 64 lists that need more than
+// one wave, workgroup g the lists 64 g .. 64 g + 63 (one atomic per queue for
+// the 64 lists): queue_mid takes lists of
+// kSegWave + 1 .. kSegSmall entries, queue_large from its front those of
+// kSegSmall + 1 .. kSegLarge and from its back (queue_large[nlists - 1 - j])
+// the longer ones up to kSortNoteList (the two together hold at most nlists
+// lists); counts in n_queued[0..2], the bit of each tier that has lists in
+// *note, with kNoteLongRoute / kNoteSortWide for lists longer than kLongList
+// / kSortNoteList (the latter are left to global passes over the whole key).
+// The last of these workgroups to finish publishes the note to the host.
 __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                                                  const uint32_t *__restrict__ ranges, uint32_t nlists)
+                                                  const uint32_t *__restrict__ ranges, uint32_t nlists,
+                                                  uint32_t *__restrict__ queue_mid, uint32_t *__restrict__ queue_large,
+                                                  uint32_t *__restrict__ n_queued, uint32_t *note, uint32_t *done,
+                                                  SortPublish pub)
 {
     __shared__ SegShared<1> sh;
     const uint32_t list = blockIdx.x;
     if (list >= nlists) return;
+    const int lane = (int)threadIdx.x;
+    const uint32_t filers = (nlists + 63u) / 64u;
+    if (list < filers) {
+        const uint32_t l = 64u * list + (uint32_t)lane;
+        uint32_t ml = 0u;
+        if (l < nlists) {
+            const uint32_t a = ranges[2 * l], b = ranges[2 * l + 1];
+            ml = b > a ? b - a : 0u;
+        }
+        const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
+        const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
+        const uint64_t mid = __ballot(ml > (uint32_t)kSegWave && ml <= (uint32_t)kSegSmall);
+        const uint64_t lng = __ballot(ml > kLongList);
+        const uint64_t wide = __ballot(ml > kSortNoteList);
+        uint32_t qh = 0u, qb = 0u, qm = 0u;
+        if (lane == 0) {
+            if (huge) qh = atomicAdd(&n_queued[2], (uint32_t)__popcll(huge));
+            if (big) qb = atomicAdd(&n_queued[1], (uint32_t)__popcll(big));
+            if (mid) qm = atomicAdd(&n_queued[0], (uint32_t)__popcll(mid));
+            const uint32_t bits = (huge ? kNoteSortHuge : 0u) | (big ? kNoteSortLarge : 0u) |
+                                  (mid ? kNoteSortMid : 0u) | (lng ? kNoteLongRoute : 0u) |
+                                  (wide ? kNoteSortWide : 0u);
+            if (bits) atomicOr(note, bits);
+            // the last filing workgroup publishes the complete note
+            __threadfence();
+            if (atomicAdd(done, 1u) == filers - 1u) {
+                __threadfence();
+                publish_words(pub.a, pub.b, pub.host, pub.seq, note);
+            }
+        }
+        qh = (uint32_t)__shfl((int)qh, 0);
+        qb = (uint32_t)__shfl((int)qb, 0);
+        qm = (uint32_t)__shfl((int)qm, 0);
+        const uint64_t lt = lanemask_lt();
+        if ((huge >> lane) & 1ull) queue_large[nlists - 1u - (qh + (uint32_t)__popcll(huge & lt))] = l;
+        if ((big >> lane) & 1ull) queue_large[qb + (uint32_t)__popcll(big & lt)] = l;
+        if ((mid >> lane) & 1ull) queue_mid[qm + (uint32_t)__popcll(mid & lt)] = l;
+    }
     const uint32_t start = ranges[2 * list], end = ranges[2 * list + 1];
     const uint32_t m = end > start ? end - start : 0u;
     if (m > (uint32_t)kSegWave || m < 2) return;
@@ -519,6 +591,7 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
     constexpr int W = 16;
     __shared__ uint32_t hist[kBins], run[kBins];
     __shared__ uint32_t gbase[kBins];
+    __shared__ uint32_t wsum[4];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int nthr = W * 64;
     uint64_t *ksrc = keys, *kdst = keys_alt;
@@ -546,8 +619,11 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
     seg_minmax<W>(sh, mn, mx);
     const uint32_t span = mx - mn;
     const int bits = span ? 32 - __clz((int)span) : 0;
-    for (int shift = 0; shift < bits; shift += kBits) {
-        uint32_t *skip = &sh.skip[shift / kBits];
+    const int passes = (bits + kBits - 1) / kBits;
+    for (int pass = 0, shift = 0; pass < passes; shift += digit_bits(bits, passes, pass), ++pass) {
+        const int nbits = digit_bits(bits, passes, pass);
+        const uint32_t mask = (1u << nbits) - 1u;
+        uint32_t *skip = &sh.skip[pass];
         // digit totals of the whole run
         if (t < kBins) hist[t] = 0u;
         __syncthreads();
@@ -560,7 +636,7 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                if (e0 + (uint32_t)(j * nthr) < m) atomicAdd(&hist[((kk[j] - mn) >> shift) & (kBins - 1)], 1u);
+                if (e0 + (uint32_t)(j * nthr) < m) atomicAdd(&hist[((kk[j] - mn) >> shift) & mask], 1u);
         }
         __syncthreads();
         if (t < kBins) {
@@ -571,7 +647,7 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
                 const uint32_t y = __shfl_up(x, off);
                 if (lane >= off) x += y;
             }
-            if (lane == 63) sh.wsum[t >> 6] = x;
+            if (lane == 63) wsum[t >> 6] = x;
             gbase[t] = x - c;
             run[t] = 0u;
         }
@@ -579,7 +655,7 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
         if (*skip) continue;  // uniform
         if (t < kBins) {
             uint32_t wpre = 0;
-            for (int w = 0; w < (t >> 6); ++w) wpre += sh.wsum[w];
+            for (int w = 0; w < (t >> 6); ++w) wpre += wsum[w];
             gbase[t] += wpre;
         }
         __syncthreads();
@@ -595,15 +671,15 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
             }
             for (int i = t; i < W * kBins / 2; i += nthr) ((uint32_t *)&sh.cnt[0][0])[i] = 0u;
             __syncthreads();
-            seg_rank<W>(sh, k, e0, mc, shift, kSegItems, dr);
+            seg_rank<W>(sh, k, e0, mc, shift, nbits, kSegItems, dr);
             __syncthreads();
-            seg_scan<W>(sh, mc, nullptr);
+            (void)seg_scan<W>(sh, mc, nullptr);
             // stage in digit order, then write each digit's run to its place
 #pragma unroll
             for (int r = 0; r < kSegItems; ++r) {
                 if (e0 + (uint32_t)(r * 64 + lane) < mc) {
-                    const uint32_t dg = dr[r] & (kBins - 1);
-                    const uint32_t pos = sh.lbase[dg] + sh.cnt[wave][dg] + (dr[r] >> 8);
+                    const uint32_t dg = dr[r] & 0xffffu;
+                    const uint32_t pos = sh.lbase[dg] + sh.cnt[wave][dg] + (dr[r] >> 16);
                     sh.key[pos] = k[r];
                     sh.val[pos] = v[r];
                 }
@@ -611,13 +687,13 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
             __syncthreads();
             for (uint32_t i = t; i < mc; i += nthr) {
                 const uint32_t kk = sh.key[i];
-                const uint32_t dg = (kk >> shift) & (kBins - 1);
+                const uint32_t dg = (kk >> shift) & mask;
                 const uint64_t pos = start + gbase[dg] + run[dg] + (i - sh.lbase[dg]);
                 kdst[pos] = hi | (kk + mn);
                 vdst[pos] = sh.val[i];
             }
             __syncthreads();
-            if (t < kBins) run[t] += sh.tot[t];
+            if (t < kBins) run[t] += (t + 1 < kBins ? (uint32_t)sh.lbase[t + 1] : mc) - sh.lbase[t];
             __syncthreads();
         }
         uint64_t *tk = ksrc; ksrc = kdst; kdst = tk;
@@ -673,10 +749,15 @@ size_t sort_tmp_bytes(uint64_t n)
 }
 
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
-                            int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt)
+                            int begin_bit, int end_bit, void *tmp, hipStream_t s, bool *result_in_alt,
+                            uint32_t *clear, uint64_t nclear)
 {
     *result_in_alt = false;
-    if (n <= 1 || end_bit <= begin_bit) return hipSuccess;
+    if (n <= 1 || end_bit <= begin_bit) {
+        if (nclear) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nclear + 255) / 256)), dim3(256), 0, s, clear,
+                                       nclear, 0u);
+        return hipGetLastError();
+    }
     uint32_t nb = sort_blocks(n);
     uint64_t cells = (uint64_t)nb * kBins;
     char *p = (char *)tmp;
@@ -684,11 +765,17 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     uint32_t *totals = (uint32_t *)(p + ((cells * sizeof(uint32_t) + 255) & ~(size_t)255));
     uint64_t *ki = keys, *ko = keys_alt;
     uint32_t *vi = vals, *vo = vals_alt;
-    for (int shift = begin_bit; shift < end_bit; shift += kBits) {
-        hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, n, shift, hist, nb);
-        hipLaunchKernelGGL(k_digit_scan, dim3(kBins), dim3(kThreads), 0, s, hist, nb, totals);
+    // ceil(bits / 8) passes with digits of (nearly) equal width: fewer bins
+    // per pass where the bits allow (longer runs per digit in the scatter)
+    const int bits = end_bit - begin_bit, passes = (bits + kBits - 1) / kBits;
+    for (int pass = 0, shift = begin_bit; pass < passes; ++pass) {
+        const int left = passes - pass, nbits = (bits - (shift - begin_bit) + left - 1) / left;
+        hipLaunchKernelGGL(k_hist, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, n, shift, nbits, hist, nb,
+                           clear, pass == 0 ? nclear : 0);
+        hipLaunchKernelGGL(k_digit_scan, dim3(1u << nbits), dim3(kThreads), 0, s, hist, nb, totals);
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kThreads), 0, s, (const uint64_t *)ki, (const uint32_t *)vi, n,
-                           shift, (const uint32_t *)hist, (const uint32_t *)totals, nb, ko, vo);
+                           shift, nbits, (const uint32_t *)hist, (const uint32_t *)totals, nb, ko, vo);
+        shift += nbits;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint64_t *tk = ki; ki = ko; ko = tk;
@@ -698,20 +785,13 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     return hipSuccess;
 }
 
-hipError_t launch_segment_classify(uint64_t n, const uint32_t *ranges, int64_t nlists, uint32_t *queues,
-                                   uint32_t *n_queued, uint32_t *note, hipStream_t s)
+hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
+                                     int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
+                                     uint32_t *done, SortPublish pub, hipStream_t s)
 {
-    if (n <= 1 || nlists <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_classify, dim3((unsigned)((nlists + 255) / 256)), dim3(256), 0, s, ranges,
-                       (uint32_t)nlists, queues, queues + nlists, n_queued, note);
-    return hipGetLastError();
-}
-
-hipError_t launch_segment_sort_short(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
-                                     int64_t nlists, hipStream_t s)
-{
-    if (n <= 1 || nlists <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists);
+    if (nlists <= 0) return launch_publish2(pub.a, pub.b, pub.host, pub.seq, note, s);
+    hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists,
+                       queues, queues + nlists, n_queued, note, done, pub);
     return hipGetLastError();
 }
 
@@ -735,9 +815,10 @@ hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *ke
     return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s)
+hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s,
+                              bool cleared)
 {
-    uint64_t m = 2ull * (uint64_t)ntiles;
+    uint64_t m = cleared ? 0 : 2ull * (uint64_t)ntiles;
     if (m) hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, ranges, m, 0u);
     if (n) hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, keys, n, ranges);
     return hipGetLastError();
