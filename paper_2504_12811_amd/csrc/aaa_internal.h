@@ -195,9 +195,9 @@ __device__ __forceinline__ uint32_t order_key(float f)
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// Tile-pair keep test shared by the pair counter and writer: pyramid minimum
-// below tau with a relative slack of 2e-4 (+1e-5) for float rounding.
-__device__ __forceinline__ bool keep_threshold(float m, float tau) { return m < tau * (1.0f + 2e-4f) + 1e-5f; }
+// Tile-pair keep test of the pair counter: pyramid minimum below this
+// limit, tau with a relative slack of 2e-4 (+1e-5) for float rounding.
+__device__ __forceinline__ float keep_limit(float tau) { return tau * (1.0f + 2e-4f) + 1e-5f; }
 
 }  // namespace aaa
 

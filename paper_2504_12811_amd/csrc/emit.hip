@@ -24,11 +24,73 @@ namespace {
 
 constexpr int kEmitBlocks = 2048;  // grid of the balanced emitter (grid-stride)
 
+// The candidates of tile_min_rho2 (Eq. 18) tested against thr without
+// divisions: each is a ratio with a positive denominator (|r|^2 on an edge
+// ray, |n|^2 on a face), compared as numerator < thr * denominator, and a
+// face minimum's feasibility is taken on its point scaled by |n|^2 (the
+// tolerance scales with it).
+__device__ __forceinline__ bool edge_below(const TileGeom<float> &g, float dX, float dY, float thr)
+{
+    float r[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r[k] = g.c0[k] + dX * g.c1[k] + dY * g.c2[k];
+        w[k] = g.w0[k] + dX * g.w1[k] + dY * g.w2[k];
+    }
+    const float l = g.l[0] + dX * g.l[1] + dY * g.l[2];
+    return l > 0.0f && dot3(w, w) < thr * dot3(r, r);  // behind the camera: the apex, tested apart
+}
+
+__device__ __forceinline__ bool face_below(const TileGeom<float> &g, bool vert, float D, float s, float lo, float hi,
+                                           float thr)
+{
+    const float *n0 = vert ? g.nx0 : g.ny0;
+    const float *n1 = vert ? g.nx1 : g.ny1;
+    const float *q0 = vert ? g.qx0 : g.qy0;
+    const float *q1 = vert ? g.qx1 : g.qy1;
+    float n[3], q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        n[k] = n0[k] - D * n1[k];
+        q[k] = q0[k] - D * q1[k];
+    }
+    const float nn = dot3(n, n);
+    float X[3];  // |n|^2 times the face minimum in view space
+#pragma unroll
+    for (int k = 0; k < 3; ++k) X[k] = nn * g.muv[k] - s * q[k];
+    const float o = vert ? X[1] : X[0];
+    const float a = o - lo * X[2], b = hi * X[2] - o;
+    const float scale = fabsf(o) + fabsf(X[2]) * (fabsf(lo) + fabsf(hi));
+    const float tol = 1e-4f * scale;
+    return s * s < thr * nn && a >= -tol && b >= -tol;
+}
+
+// Whether the minimum of rho^2 over the pyramid of tile (tx, ty) lies below
+// tau with the keep test's slack (keep_limit).
 __device__ __forceinline__ bool tile_keep(const TileGeom<float> &g, int tx, int ty, float tau, const CamDev &cam)
 {
-    float x0 = (float)(tx * kTile), y0 = (float)(ty * kTile);
-    float m = tile_min_rho2<float>(g, x0, x0 + kTile, y0, y0 + kTile, cam);
-    return keep_threshold(m, tau);
+    const float thr = keep_limit(tau);
+    const float x0 = (float)(tx * kTile), x1 = x0 + kTile, y0 = (float)(ty * kTile), y1 = y0 + kTile;
+    const float dX0 = x0 - g.xa, dX1 = x1 - g.xa, dY0 = y0 - g.ya, dY1 = y1 - g.ya;
+    const float sL = g.dx0 - dX0 * g.dx1, sR = g.dx0 - dX1 * g.dx1;
+    const float sT = g.dy0 - dY0 * g.dy1, sB = g.dy0 - dY1 * g.dy1;
+    const bool vL = sL < 0.0f, vR = sR > 0.0f, vT = sT < 0.0f, vB = sB > 0.0f;
+    if (!(vL || vR || vT || vB) || g.og2 < thr) return true;  // mean inside the pyramid, or the apex
+    // view slopes of the rectangle (one reciprocal per axis; the face test's
+    // tolerance covers its rounding)
+    const float ifx = __builtin_amdgcn_rcpf((float)cam.fx), ify = __builtin_amdgcn_rcpf((float)cam.fy);
+    const float cx = (float)cam.cx, cy = (float)cam.cy;
+    const float u0 = (x0 - cx) * ifx, u1 = (x1 - cx) * ifx, v0 = (y0 - cy) * ify, v1 = (y1 - cy) * ify;
+    bool below = false;
+    if (vL || vT) below = edge_below(g, dX0, dY0, thr);
+    if (!below && (vL || vB)) below = edge_below(g, dX0, dY1, thr);
+    if (!below && (vR || vT)) below = edge_below(g, dX1, dY0, thr);
+    if (!below && (vR || vB)) below = edge_below(g, dX1, dY1, thr);
+    if (!below && vL) below = face_below(g, true, dX0, sL, v0, v1, thr);
+    if (!below && vR) below = face_below(g, true, dX1, sR, v0, v1, thr);
+    if (!below && vT) below = face_below(g, false, dY0, sT, u0, u1, thr);
+    if (!below && vB) below = face_below(g, false, dY1, sB, u0, u1, thr);
+    return below;
 }
 
 // depth of the maximum on the line through the tile centre
