@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (500k 1080p, 3M 2064x2208 120deg and its zoom sweep, the "
                          "1M 720p 16-view training step) and the Tab. 5 ablations")
+    ap.add_argument("--frames-3m", type=int, default=0,
+                    help="only render the 3M 2064x2208 120deg primary view this many times (for kernel profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -118,6 +120,15 @@ def main():
     import torch
     from paper_2504_12811_amd import scenes as S
     from paper_2504_12811_amd.render import DeviceScene, Rasterizer
+
+    if args.frames_3m > 0:
+        scene, cam, _ = S.ood_scene()
+        ds = DeviceScene.from_host(scene, "cuda:0")
+        ras = Rasterizer(0)
+        st = S.Settings(ray_window=args.window)
+        r = _time_frames(ras, ds, [cam], st, steps=args.frames_3m, warmup=2)
+        print(json.dumps({"workload": "3M 2064x2208 120deg primary view", **r}), flush=True)
+        return
 
     t0 = time.time()
     scene, cams = S.headline(n=args.n)
