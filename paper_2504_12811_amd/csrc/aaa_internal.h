@@ -187,6 +187,60 @@ __device__ __forceinline__ void load_line_geom(const float4 *__restrict__ rec, T
     g.xa = q5.y; g.ya = q5.z;
 }
 
+// Wave-wide scans and reductions on DPP lane moves (VALU, a few cycles each)
+// instead of LDS permutes: an inclusive sum shifts within rows of 16 lanes
+// (row_shr 1, 2, 4, 8), then adds lane 15's sum into rows 1 and 3 and lane
+// 31's into rows 2 and 3 (row_bcast); lanes whose source lies outside the
+// row, or whose row is masked off, add the 0 passed as the old value.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15, rows 1 and 3
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31, rows 2 and 3
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_sum64(uint64_t x)
+{
+#define AAA_DPP64_STEP(ctrl, rows)                                                                              \
+    {                                                                                                           \
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, ctrl, rows, 0xF, false);  \
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), ctrl, rows, 0xF, \
+                                                                  false);                                       \
+        x += ((uint64_t)hi << 32) | lo;                                                                         \
+    }
+    AAA_DPP64_STEP(0x111, 0xF)
+    AAA_DPP64_STEP(0x112, 0xF)
+    AAA_DPP64_STEP(0x114, 0xF)
+    AAA_DPP64_STEP(0x118, 0xF)
+    AAA_DPP64_STEP(0x142, 0xA)
+    AAA_DPP64_STEP(0x143, 0xC)
+#undef AAA_DPP64_STEP
+    return x;
+}
+
+// Minimum and maximum over the wave, returned to every lane (wave-uniform):
+// quad swaps and the half-row and row mirrors leave each row's result in all
+// of its lanes, then the four row results are read out.
+__device__ __forceinline__ void wave_minmax(uint32_t &mn, uint32_t &mx)
+{
+#define AAA_DPP_MINMAX(ctrl)                                                                  \
+    mn = min(mn, (uint32_t)__builtin_amdgcn_update_dpp((int)mn, (int)mn, ctrl, 0xF, 0xF, false)); \
+    mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp((int)mx, (int)mx, ctrl, 0xF, 0xF, false));
+    AAA_DPP_MINMAX(0xB1)   // quad_perm 1,0,3,2
+    AAA_DPP_MINMAX(0x4E)   // quad_perm 2,3,0,1
+    AAA_DPP_MINMAX(0x141)  // row_half_mirror
+    AAA_DPP_MINMAX(0x140)  // row_mirror
+#undef AAA_DPP_MINMAX
+    mn = min(min((uint32_t)__builtin_amdgcn_readlane((int)mn, 0), (uint32_t)__builtin_amdgcn_readlane((int)mn, 16)),
+             min((uint32_t)__builtin_amdgcn_readlane((int)mn, 32), (uint32_t)__builtin_amdgcn_readlane((int)mn, 48)));
+    mx = max(max((uint32_t)__builtin_amdgcn_readlane((int)mx, 0), (uint32_t)__builtin_amdgcn_readlane((int)mx, 16)),
+             max((uint32_t)__builtin_amdgcn_readlane((int)mx, 32), (uint32_t)__builtin_amdgcn_readlane((int)mx, 48)));
+}
+
 // Order-preserving map of a float to uint32 (-0 -> +0; NaN never occurs).
 __device__ __forceinline__ uint32_t order_key(float f)
 {

@@ -156,16 +156,7 @@ __device__ __forceinline__ uint32_t quad_bits(float4 box, int tx, int ty)
 __device__ __forceinline__ uint64_t bits_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
 // exclusive prefix sum over the lanes of the wave
-__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v)
-{
-    const int lane = (int)__lane_id();
-    uint32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    return x - v;
-}
+__device__ __forceinline__ uint32_t wave_exclusive_sum(uint32_t v) { return wave_incl_sum(v) - v; }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
 {
@@ -326,11 +317,7 @@ __device__ __forceinline__ uint64_t block_exclusive_scan(uint64_t v, uint64_t *s
     // smem: 256 entries
     const int t = threadIdx.x;
     const int lane = __lane_id(), wave = t >> 6;
-    uint64_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint64_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
+    const uint64_t x = wave_incl_sum64(v);
     if (lane == 63) smem[wave] = x;
     __syncthreads();
     uint64_t wpre = 0;

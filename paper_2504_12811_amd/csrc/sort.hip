@@ -103,11 +103,7 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ 
             v[k] = i0 + k < nblocks ? row[i0 + k] : 0u;
             sum += v[k];
         }
-        uint32_t x = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
+        const uint32_t x = wave_incl_sum(sum);
         if (lane == 63) wsum[wave] = x;
         __syncthreads();
         uint32_t wpre = 0;
@@ -176,16 +172,8 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     // starts) and of the global digit totals (global starts)
     const bool live = t < (1 << nbits);  // digits past 2^nbits are empty
     const uint64_t dt = live ? totals[t] : 0u;
-    uint32_t x = tot;
-    uint64_t gx = dt;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        const uint64_t gy = __shfl_up(gx, off);
-        if (lane >= off) {
-            x += y;
-            gx += gy;
-        }
-    }
+    const uint32_t x = wave_incl_sum(tot);
+    const uint64_t gx = wave_incl_sum64(dt);
     if (lane == 63) {
         wsum[wave] = x;
         gsum[wave] = gx;
@@ -367,11 +355,7 @@ __device__ __forceinline__ bool seg_scan(SegShared<W> &sh, uint32_t m, uint32_t 
             mine += tot[j];
         }
         if (flag && one) *flag = 1u;
-        uint32_t x = mine;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(x, off);
-            if (t >= off) x += y;
-        }
+        const uint32_t x = wave_incl_sum(mine);
         uint32_t run = x - mine, lb[WORDS];
 #pragma unroll
         for (int j = 0; j < WORDS; ++j) {
@@ -437,11 +421,7 @@ __device__ __forceinline__ void seg_pass(SegShared<W> &sh, uint32_t (&k)[kSegIte
 template <int W>
 __device__ __forceinline__ void seg_minmax(SegShared<W> &sh, uint32_t &mn, uint32_t &mx)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        mn = min(mn, (uint32_t)__shfl_xor((int)mn, off));
-        mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
-    }
+    wave_minmax(mn, mx);
     if constexpr (W > 1) {
         const int wave = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -642,11 +622,7 @@ __device__ void seg_sort_global(SegShared<16> &sh, uint64_t *__restrict__ keys, 
         if (t < kBins) {
             const uint32_t c = hist[t];
             if (c == m) *skip = 1u;
-            uint32_t x = c;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(x, off);
-                if (lane >= off) x += y;
-            }
+            const uint32_t x = wave_incl_sum(c);
             if (lane == 63) wsum[t >> 6] = x;
             gbase[t] = x - c;
             run[t] = 0u;
