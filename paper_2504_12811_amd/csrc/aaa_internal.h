@@ -241,6 +241,13 @@ __device__ __forceinline__ void wave_minmax(uint32_t &mn, uint32_t &mx)
              max((uint32_t)__builtin_amdgcn_readlane((int)mx, 32), (uint32_t)__builtin_amdgcn_readlane((int)mx, 48)));
 }
 
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
+{
+    uint32_t mn = 0u;
+    wave_minmax(mn, x);
+    return x;
+}
+
 // Order-preserving map of a float to uint32 (-0 -> +0; NaN never occurs).
 __device__ __forceinline__ uint32_t order_key(float f)
 {

@@ -796,7 +796,7 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
     // (no copy that would wait for it); rows at or past the pixel's own count
     // are zeroed at use.
     uint32_t wcap = cap;  // the quadrant's largest count: its slot rows (>= 1 here)
-    for (int off = 32; off > 0; off >>= 1) wcap = max(wcap, (uint32_t)__shfl_xor((int)wcap, off));
+    wcap = wave_max(wcap);
     float2 s_next = slots[0];
 
     const uint32_t qbit = 1u << (kQuadShift + wave);
@@ -957,7 +957,7 @@ __global__ __launch_bounds__(256) void k_wave_caps(const ViewDev *__restrict__ v
     const int py = ty * kTile + (wave >> 1) * 8 + (lane >> 3);
     const bool inside = px < vw.cam.width && py < vw.cam.height;
     uint32_t m = inside ? n_ins[vw.pix_base + (size_t)py * vw.cam.width + px] : 0u;
-    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    m = wave_max(m);
     if (lane == 0) {
         caps[4 * tile + wave] = m;
         if (m > 0x10000u) atomicMax(max_big, m);  // rare: pixels with more than 65536 contributors
