@@ -15,6 +15,7 @@
 // items occupy increasing ranges, so the stable sort breaks key ties by item,
 // i.e. by Gaussian index within a view.
 #include <algorithm>
+#include <atomic>
 
 #include "aaa_internal.h"
 
@@ -22,7 +23,7 @@ namespace aaa {
 
 namespace {
 
-constexpr int kEmitBlocks = 2048;  // grid of the balanced emitter (grid-stride)
+constexpr int kEmitBlocks = 2048;  // grid of the balanced emitter (grid-stride), at most
 
 // The candidates of tile_min_rho2 (Eq. 18) tested against thr without
 // divisions: each is a ratio with a positive denominator (|r|^2 on an edge
@@ -432,6 +433,27 @@ hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t 
     return hipGetLastError();
 }
 
+// Grid of a grid-stride emitter kernel: the workgroups the device holds at
+// once (no second, late round of workgroups), at most kEmitBlocks.
+template <typename K>
+static unsigned resident_blocks(K kernel)
+{
+    static std::atomic<unsigned> cached[16];  // per device (0: not yet known)
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 16) return kEmitBlocks;
+    unsigned nb = cached[d].load(std::memory_order_relaxed);
+    if (nb == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || per_cu <= 0 ||
+            cus <= 0)
+            return kEmitBlocks;
+        nb = (unsigned)std::min<int64_t>((int64_t)per_cu * cus, kEmitBlocks);
+        cached[d].store(nb, std::memory_order_relaxed);
+    }
+    return nb;
+}
+
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull,
                               unsigned long long *tests, uint64_t *keep_bits, uint32_t *chunk_cnt,
@@ -439,7 +461,8 @@ hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 
                               hipStream_t s)
 {
     if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs<false>, dim3(kEmitBlocks), dim3(256), 0, s, rect, rec, cull, area_off, items, views,
+    hipLaunchKernelGGL(k_pairs<false>, dim3(resident_blocks(k_pairs<false>)), dim3(256), 0, s, rect, rec, cull,
+                       area_off, items, views,
                        nviews, tile_cull, tests, keep_bits, chunk_cnt, chunk_item, (const uint64_t *)nullptr, keep_cap,
                        (uint64_t)0, (uint64_t *)nullptr, (uint32_t *)nullptr, bbox, false, subtile);
     return hipGetLastError();
