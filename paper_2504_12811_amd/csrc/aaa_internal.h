@@ -377,12 +377,25 @@ struct SortPublish {
     uint64_t *host;
     uint64_t seq;
 };
+// Tile ranking by list length class for the blend's order (lists are
+// tiles): tile_key [nlists] receives rank | class << 27, class_count
+// [kOrderClasses] (zero at entry) the class sizes, class_start
+// [kOrderClasses] their starts, longest class first.  tile_key null: none.
+constexpr int kOrderClasses = 16;  // floor(log2(length + 1)), capped
+struct TileOrderScratch {
+    uint32_t *tile_key, *class_count, *class_start;
+};
 hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
                                      int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
-                                     uint32_t *done, SortPublish pub, hipStream_t s);
+                                     uint32_t *done, SortPublish pub, TileOrderScratch order, hipStream_t s);
 hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
                                     uint64_t n, const uint32_t *ranges, int64_t nlists, const uint32_t *queues,
                                     const uint32_t *n_queued, uint32_t which, hipStream_t s);
+// order[0 .. ntiles): the tiles by decreasing list length class (see
+// TileOrderScratch; any order within a class), so that the blend's longest
+// lists are dispatched first.
+hipError_t launch_tile_order(const uint32_t *tile_key, const uint32_t *class_start, int ntiles, uint32_t *order,
+                             hipStream_t s);
 // ranges [ntiles][2] of the sorted keys (cleared first unless `cleared`)
 hipError_t launch_tile_ranges(const uint64_t *keys, uint64_t n, uint32_t *ranges, int ntiles, hipStream_t s,
                               bool cleared = false);
@@ -414,6 +427,9 @@ struct BlendArgs {
     // *n_long (written by k_find_long) is at most kMaxLongTiles
     uint32_t long_list;
     const uint32_t *n_long;
+    // forward only: workgroup slot -> tile, tiles with longer lists first
+    // (null: slot = tile)
+    const uint32_t *tile_order;
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s);

@@ -78,7 +78,7 @@ uint64_t keep_cap_of(uint64_t max_pairs) { return ((max_pairs > 0 ? max_pairs : 
 
 struct Layout {
     size_t hdr, views, status, rect, bbox, pending, pending_n, area, area_off, rec, cull, bwd_list, keep_bits, chunk_item, chunk_cnt, kept_before, chunk_scan_tmp, scan_tmp, keys, keys_alt, vals, vals_alt, sort_tmp,
-        ranges, seg_long, long_tiles, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
+        ranges, seg_long, long_tiles, tile_order, masks, summary, n_done, n_ins, wave_caps, wave_off, wave_scan_tmp, grad_rec, total;
 };
 
 uint64_t summary_words(const Shape &sh, uint64_t mp) { return ((mp / 64 + (uint64_t)sh.total_tiles + 2) / 64 + 1) * 256; }
@@ -121,6 +121,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
     L.ranges = take((size_t)sh.total_tiles * 4 * 8);  // per tile, or per 8x8 sub-tile with AAA_SUBTILE_SORT
     L.seg_long = take((size_t)sh.total_tiles * 8 * 4);  // the two queues of lists for the longer per-list sorts
     L.long_tiles = take((size_t)sh.total_tiles * 4);
+    L.tile_order = take((size_t)sh.total_tiles * 8);  // the forward blend's tiles, longest lists first; tile keys
     L.masks = take((mp / 64 + (uint64_t)sh.total_tiles + 2) * 256 * 8);  // per-pixel masks of long lists
     L.summary = take(summary_words(sh, mp) * 8);
     L.n_done = take((size_t)sh.total_pixels * 4);
@@ -551,7 +552,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ctr, 0, 128, s));  // counters [0..7], long-tile count [8], the sort's queue counts [11..12]
+    HIP_TRY(hipMemsetAsync(ctr, 0, 256, s));  // counters [0..7], long-tile count [8], the sort's queue counts
+                                             // [11..12], the tile order's class counts [16..23]
 
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
@@ -613,6 +615,12 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     }
     STAGE_MARK(6);
     HIP_TRY(aaa::launch_tile_ranges(skeys, P, ranges, (int)nlists, s, true));
+    // the blend starts the tiles with the longest lists first (sub-tile
+    // lists: tile order); phase 2's filing workgroups rank the tiles by
+    // length class
+    uint32_t *tile_order = subtile ? nullptr : at<uint32_t>(ws, L.tile_order);
+    const aaa::TileOrderScratch order_scratch{tile_order ? tile_order + ntiles : nullptr, (uint32_t *)(ctr + 16),
+                                              (uint32_t *)(ctr + 24)};
     STAGE_MARK(7);
     // Phase 2: each list sorted by the depth word in place (the other pair
     // buffer is scratch for long lists).  Its first kernel sorts the lists
@@ -632,7 +640,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const uint64_t seq = ++ctx->sync_seq;
     HIP_TRY(aaa::launch_segment_sort_first(skeys, svals, P, ranges, nlists, queues, n_queued, list_note, list_done,
                                            aaa::SortPublish{kept_before + chunks, area_off + items, ctx->sync_host, seq},
-                                           s));
+                                           order_scratch, s));
     HIP_TRY(wait_published(ctx, s, seq));
     const uint32_t lists = P > 1 ? (uint32_t)ctx->sync_host[3] : 0u;
     if (!(lists & aaa::kNoteSortWide))
@@ -647,6 +655,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
             HIP_TRY(hipMemcpyAsync(svals, ovals, P * 4, hipMemcpyDeviceToDevice, s));
         }
     }
+    if (tile_order)
+        HIP_TRY(aaa::launch_tile_order(order_scratch.tile_key, order_scratch.class_start, (int)ntiles, tile_order, s));
     STAGE_MARK(8);
 
     aaa::BlendArgs ba;
@@ -668,6 +678,7 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     ba.wave_off = nullptr;
     ba.slots = nullptr;
     ba.rank16 = false;
+    ba.tile_order = tile_order;
     const int K = settings->ray_window;
     const bool long_all = (settings->flags & AAA_LONG_ALL) != 0;
     // the long-list route walks whole tiles: not with sub-tile lists
@@ -831,6 +842,7 @@ static int backward_run(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const
     ba.rank16 = rank16 && (settings->flags & AAA_WIDE_RANKS) == 0;
     ba.long_list = 0xffffffffu;
     ba.n_long = nullptr;
+    ba.tile_order = nullptr;
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));  // pass 1: window replay
     HIP_TRY(aaa::launch_grad(ba, s));                                     // pass 2: list order, wave sums
     aaa::GradOut go;

@@ -179,9 +179,13 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
     // share of dense and sparse image regions (contiguous bands per XCD left
     // the XCDs with dense bands working long after the others); with one
     // wave per workgroup the four quadrants of a tile share an XCD.
+    // The slots are dealt this way; with a tile order, slot s renders tile
+    // tile_order[s] (longest lists first, so the last workgroups to start
+    // are short ones).
     const int wq = (int)(blockIdx.x >> 3);
-    const int tile = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
-    if (tile >= ntiles) return;
+    const int slot = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
+    if (slot >= ntiles) return;
+    const int tile = a.tile_order ? (int)uniform_read(a.tile_order + slot) : slot;
     int v = 0;  // the view owning this tile (views are ordered by tile_base)
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
     const ViewDev &vw = a.views[v];

@@ -497,11 +497,14 @@ __device__ __forceinline__ void seg_sort_lds(SegShared<W> &sh, uint64_t *__restr
 // *note, with kNoteLongRoute / kNoteSortWide for lists longer than kLongList
 // / kSortNoteList (the latter are left to global passes over the whole key).
 // The last of these workgroups to finish publishes the note to the host.
+// With `order` (lists are tiles), they also rank the tiles by length class
+// (see launch_tile_order): a per-class count, then its prefix from the
+// longest class down, computed by the last of them.
 __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
                                                   const uint32_t *__restrict__ ranges, uint32_t nlists,
                                                   uint32_t *__restrict__ queue_mid, uint32_t *__restrict__ queue_large,
                                                   uint32_t *__restrict__ n_queued, uint32_t *note, uint32_t *done,
-                                                  SortPublish pub)
+                                                  SortPublish pub, TileOrderScratch order)
 {
     __shared__ SegShared<1> sh;
     const uint32_t list = blockIdx.x;
@@ -514,6 +517,22 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
         if (l < nlists) {
             const uint32_t a = ranges[2 * l], b = ranges[2 * l + 1];
             ml = b > a ? b - a : 0u;
+        }
+        const uint64_t lt = lanemask_lt();
+        if (order.tile_key) {
+            // length class of each tile, ranked within the class
+            const uint32_t cl = l < nlists ? (uint32_t)min(31 - __clz((int)(ml + 1u)), kOrderClasses - 1) : ~0u;
+            uint64_t left = __ballot(l < nlists);
+            while (left) {
+                const int leader = __ffsll((long long)left) - 1;
+                const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)cl, leader);
+                const uint64_t m = __ballot(cl == lc);
+                uint32_t at = 0u;
+                if ((int)threadIdx.x == leader) at = atomicAdd(&order.class_count[lc], (uint32_t)__popcll(m));
+                at = (uint32_t)__builtin_amdgcn_readlane((int)at, leader);
+                if (cl == lc) order.tile_key[l] = (at + (uint32_t)__popcll(m & lt)) | (lc << 27);
+                left &= ~m;
+            }
         }
         const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
         const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
@@ -533,13 +552,19 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
             __threadfence();
             if (atomicAdd(done, 1u) == filers - 1u) {
                 __threadfence();
+                if (order.tile_key) {
+                    uint32_t run = 0;
+                    for (int c = kOrderClasses - 1; c >= 0; --c) {
+                        order.class_start[c] = run;
+                        run += atomicAdd(&order.class_count[c], 0u);
+                    }
+                }
                 publish_words(pub.a, pub.b, pub.host, pub.seq, note);
             }
         }
         qh = (uint32_t)__shfl((int)qh, 0);
         qb = (uint32_t)__shfl((int)qb, 0);
         qm = (uint32_t)__shfl((int)qm, 0);
-        const uint64_t lt = lanemask_lt();
         if ((huge >> lane) & 1ull) queue_large[nlists - 1u - (qh + (uint32_t)__popcll(huge & lt))] = l;
         if ((big >> lane) & 1ull) queue_large[qb + (uint32_t)__popcll(big & lt)] = l;
         if ((mid >> lane) & 1ull) queue_mid[qm + (uint32_t)__popcll(mid & lt)] = l;
@@ -763,11 +788,11 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 
 hipError_t launch_segment_sort_first(uint64_t *keys, uint32_t *vals, uint64_t n, const uint32_t *ranges,
                                      int64_t nlists, uint32_t *queues, uint32_t *n_queued, uint32_t *note,
-                                     uint32_t *done, SortPublish pub, hipStream_t s)
+                                     uint32_t *done, SortPublish pub, TileOrderScratch order, hipStream_t s)
 {
     if (nlists <= 0) return launch_publish2(pub.a, pub.b, pub.host, pub.seq, note, s);
     hipLaunchKernelGGL(k_seg_first, dim3((unsigned)nlists), dim3(64), 0, s, keys, vals, ranges, (uint32_t)nlists,
-                       queues, queues + nlists, n_queued, note, done, pub);
+                       queues, queues + nlists, n_queued, note, done, pub, order);
     return hipGetLastError();
 }
 
@@ -788,6 +813,26 @@ hipError_t launch_segment_sort_rest(uint64_t *keys, uint32_t *vals, uint64_t *ke
     if (huge)
         hipLaunchKernelGGL(k_seg_huge, dim3((unsigned)huge), dim3(1024), 0, s, keys, vals, keys_alt, vals_alt, ranges,
                            queues + 2 * nlists, n_queued + 2);
+    return hipGetLastError();
+}
+
+// order[class_start[class] + rank] = tile for every tile, from the keys
+// (rank | class << 27) that the per-list sort's filing workgroups wrote.
+__global__ void k_tile_scatter(const uint32_t *__restrict__ tile_key, const uint32_t *__restrict__ class_start,
+                               int ntiles, uint32_t *__restrict__ order)
+{
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    const uint32_t k = tile_key[tile];
+    order[class_start[k >> 27] + (k & ((1u << 27) - 1u))] = (uint32_t)tile;
+}
+
+hipError_t launch_tile_order(const uint32_t *tile_key, const uint32_t *class_start, int ntiles, uint32_t *order,
+                             hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, tile_key, class_start,
+                       ntiles, order);
     return hipGetLastError();
 }
 
