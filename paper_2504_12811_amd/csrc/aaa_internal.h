@@ -427,8 +427,8 @@ struct BlendArgs {
     // *n_long (written by k_find_long) is at most kMaxLongTiles
     uint32_t long_list;
     const uint32_t *n_long;
-    // forward only: workgroup slot -> tile, tiles with longer lists first
-    // (null: slot = tile)
+    // workgroup slot -> tile, tiles with longer lists first (null: slot =
+    // tile); k_blend and k_grad
     const uint32_t *tile_order;
 };
 hipError_t launch_blend(const BlendArgs &a, int K, bool stats, bool pass1, hipStream_t s);

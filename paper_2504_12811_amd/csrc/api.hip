@@ -842,7 +842,7 @@ static int backward_run(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const
     ba.rank16 = rank16 && (settings->flags & AAA_WIDE_RANKS) == 0;
     ba.long_list = 0xffffffffu;
     ba.n_long = nullptr;
-    ba.tile_order = nullptr;
+    ba.tile_order = subtile ? nullptr : at<uint32_t>(ws, L.tile_order);  // the forward's, longest lists first
     HIP_TRY(aaa::launch_blend(ba, settings->ray_window, false, true, s));  // pass 1: window replay
     HIP_TRY(aaa::launch_grad(ba, s));                                     // pass 2: list order, wave sums
     aaa::GradOut go;

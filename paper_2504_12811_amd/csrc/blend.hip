@@ -759,9 +759,10 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
                                                    BlendArgs a)
 {
     const int ntiles = a.total_tiles;
-    const int wq = (int)(blockIdx.x >> 3);  // tiles dealt to the XCDs round-robin, as in k_blend
-    const int tile = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
-    if (tile >= ntiles) return;
+    const int wq = (int)(blockIdx.x >> 3);  // slots dealt to the XCDs round-robin, tile order as in k_blend
+    const int slot = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
+    if (slot >= ntiles) return;
+    const int tile = a.tile_order ? (int)uniform_read(a.tile_order + slot) : slot;
     int v = 0;
     while (v + 1 < a.nviews && a.views[v + 1].tile_base <= tile) ++v;
     const ViewDev &vw = a.views[v];
