@@ -378,10 +378,13 @@ struct SortPublish {
     uint64_t seq;
 };
 // Tile ranking by list length class for the blend's order (lists are
-// tiles): tile_key [nlists] receives rank | class << 27, class_count
-// [kOrderClasses] (zero at entry) the class sizes, class_start
+// tiles): tile_key [nlists] receives rank | class << kOrderRankBits,
+// class_count [kOrderClasses] (zero at entry) the class sizes, class_start
 // [kOrderClasses] their starts, longest class first.  tile_key null: none.
-constexpr int kOrderClasses = 16;  // floor(log2(length + 1)), capped
+// Classes: four per octave of length + 1 (the octave and the two bits
+// below its leading one), capped.
+constexpr int kOrderClasses = 64;
+constexpr int kOrderRankBits = 26;
 struct TileOrderScratch {
     uint32_t *tile_key, *class_count, *class_start;
 };

@@ -93,7 +93,7 @@ Layout layout(const Shape &sh, uint64_t max_pairs)
         return at;
     };
     const int64_t items = sh.n * sh.nviews > 0 ? sh.n * sh.nviews : 1;
-    L.hdr = take(256);
+    L.hdr = take(1024);
     L.views = take(sizeof(aaa::ViewDev) * (size_t)(sh.nviews > 0 ? sh.nviews : 1));
     L.status = take(items * 4);
     L.rect = take(items * 16);
@@ -552,8 +552,8 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     fill_views(n_views, cams, out_rgb, out_T, nullptr, ctx->views_host);
     HIP_TRY(hipMemcpyAsync(at<void>(ws, L.views), ctx->views_host, sizeof(aaa::ViewDev) * n_views,
                            hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ctr, 0, 256, s));  // counters [0..7], long-tile count [8], the sort's queue counts
-                                             // [11..12], the tile order's class counts [16..23]
+    HIP_TRY(hipMemsetAsync(ctr, 0, 384, s));  // counters [0..7], long-tile count [8], the sort's queue counts
+                                             // [11..12], the tile order's class counts [16..47]
 
     aaa::PreArgs pa = pre_args(scene, n_views, settings, ws, L);
     HIP_TRY(aaa::launch_preprocess(pa, s));
@@ -619,8 +619,9 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     // lists: tile order); phase 2's filing workgroups rank the tiles by
     // length class
     uint32_t *tile_order = subtile ? nullptr : at<uint32_t>(ws, L.tile_order);
+    static_assert(aaa::kOrderClasses <= 64, "class counts and starts in header words 16..79");
     const aaa::TileOrderScratch order_scratch{tile_order ? tile_order + ntiles : nullptr, (uint32_t *)(ctr + 16),
-                                              (uint32_t *)(ctr + 24)};
+                                              (uint32_t *)(ctr + 48)};
     STAGE_MARK(7);
     // Phase 2: each list sorted by the depth word in place (the other pair
     // buffer is scratch for long lists).  Its first kernel sorts the lists

@@ -521,25 +521,25 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
         const uint64_t lt = lanemask_lt();
         if (order.tile_key) {
             // length class of each tile, ranked within the class
-            const uint32_t cl = l < nlists ? (uint32_t)min(31 - __clz((int)(ml + 1u)), kOrderClasses - 1) : ~0u;
-            uint64_t left = __ballot(l < nlists);
-            while (left) {
-                const int leader = __ffsll((long long)left) - 1;
-                const uint32_t lc = (uint32_t)__builtin_amdgcn_readlane((int)cl, leader);
-                const uint64_t m = __ballot(cl == lc);
-                uint32_t at = 0u;
-                if ((int)threadIdx.x == leader) at = atomicAdd(&order.class_count[lc], (uint32_t)__popcll(m));
-                at = (uint32_t)__builtin_amdgcn_readlane((int)at, leader);
-                if (cl == lc) order.tile_key[l] = (at + (uint32_t)__popcll(m & lt)) | (lc << 27);
-                left &= ~m;
-            }
+            const uint32_t v = ml + 1u, e = 31u - (uint32_t)__clz((int)v);
+            const uint32_t sub = (e >= 2u ? v >> (e - 2u) : v << (2u - e)) & 3u;
+            const uint32_t cl = min(4u * e + sub, (uint32_t)kOrderClasses - 1u);
+            // the lanes of each class; its first lane adds the class's
+            // count for all of them (one atomic instruction for every class)
+            static_assert(kOrderClasses <= 64, "classes of 6 bits");
+            const uint64_t m = match_digit<6>(cl, l < nlists);
+            const uint32_t before = (uint32_t)__popcll(m & lt);
+            uint32_t at = 0u;
+            if (l < nlists && before == 0u) at = atomicAdd(&order.class_count[cl], (uint32_t)__popcll(m));
+            at = (uint32_t)__shfl((int)at, l < nlists ? __ffsll((long long)m) - 1 : lane);
+            if (l < nlists) order.tile_key[l] = (at + before) | (cl << kOrderRankBits);
         }
         const uint64_t huge = __ballot(ml > (uint32_t)kSegLarge && ml <= kSortNoteList);
         const uint64_t big = __ballot(ml > (uint32_t)kSegSmall && ml <= (uint32_t)kSegLarge);
         const uint64_t mid = __ballot(ml > (uint32_t)kSegWave && ml <= (uint32_t)kSegSmall);
         const uint64_t lng = __ballot(ml > kLongList);
         const uint64_t wide = __ballot(ml > kSortNoteList);
-        uint32_t qh = 0u, qb = 0u, qm = 0u;
+        uint32_t qh = 0u, qb = 0u, qm = 0u, last = 0u;
         if (lane == 0) {
             if (huge) qh = atomicAdd(&n_queued[2], (uint32_t)__popcll(huge));
             if (big) qb = atomicAdd(&n_queued[1], (uint32_t)__popcll(big));
@@ -548,19 +548,20 @@ __global__ __launch_bounds__(64) void k_seg_first(uint64_t *__restrict__ keys, u
                                   (mid ? kNoteSortMid : 0u) | (lng ? kNoteLongRoute : 0u) |
                                   (wide ? kNoteSortWide : 0u);
             if (bits) atomicOr(note, bits);
-            // the last filing workgroup publishes the complete note
             __threadfence();
-            if (atomicAdd(done, 1u) == filers - 1u) {
-                __threadfence();
-                if (order.tile_key) {
-                    uint32_t run = 0;
-                    for (int c = kOrderClasses - 1; c >= 0; --c) {
-                        order.class_start[c] = run;
-                        run += atomicAdd(&order.class_count[c], 0u);
-                    }
-                }
-                publish_words(pub.a, pub.b, pub.host, pub.seq, note);
+            last = atomicAdd(done, 1u) == filers - 1u;
+        }
+        // the last filing workgroup completes the tile order's class starts
+        // (lane c: class kOrderClasses - 1 - c) and publishes the note
+        if (__shfl((int)last, 0)) {
+            __threadfence();
+            if (order.tile_key) {
+                const int c = kOrderClasses - 1 - lane;
+                const uint32_t cnt = c >= 0 ? atomicAdd(&order.class_count[c], 0u) : 0u;
+                const uint32_t incl = wave_incl_sum(cnt);
+                if (c >= 0) order.class_start[c] = incl - cnt;
             }
+            if (lane == 0) publish_words(pub.a, pub.b, pub.host, pub.seq, note);
         }
         qh = (uint32_t)__shfl((int)qh, 0);
         qb = (uint32_t)__shfl((int)qb, 0);
@@ -824,7 +825,7 @@ __global__ void k_tile_scatter(const uint32_t *__restrict__ tile_key, const uint
     const int tile = blockIdx.x * blockDim.x + threadIdx.x;
     if (tile >= ntiles) return;
     const uint32_t k = tile_key[tile];
-    order[class_start[k >> 27] + (k & ((1u << 27) - 1u))] = (uint32_t)tile;
+    order[class_start[k >> kOrderRankBits] + (k & ((1u << kOrderRankBits) - 1u))] = (uint32_t)tile;
 }
 
 hipError_t launch_tile_order(const uint32_t *tile_key, const uint32_t *class_start, int ntiles, uint32_t *order,
