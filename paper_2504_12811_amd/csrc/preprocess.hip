@@ -252,11 +252,12 @@ __device__ bool preprocess_item(const PreArgs &a, int64_t item)
 }
 
 // Items with their mean outside the view pyramid are listed per workgroup
-// (pending[256 b + k], k < pending_n[b]) for k_view_cull.  Four waves per
-// SIMD (128 VGPRs, a few spilled) hide the double-precision latency better
-// than three.
+// (pending[256 b + k], k < pending_n[b]) for k_view_cull.  Three waves per
+// SIMD: the pass then holds its 154 VGPRs without spilling (at four, about
+// 20 spilled registers per lane moved more scratch traffic than the
+// parameters themselves).
 template <int DEG>
-__global__ __launch_bounds__(256, 4) void k_preprocess(PreArgs a)
+__global__ __launch_bounds__(256, 3) void k_preprocess(PreArgs a)
 {
     __shared__ uint32_t n_pend;
     if (threadIdx.x == 0) n_pend = 0;
