@@ -306,16 +306,15 @@ hipError_t launch_train_freq(const float *means, int64_t n, const TrainCam *cams
 // Pair emission over the batch's candidate tests, numbered by area_off (the
 // exclusive scan of the rectangle areas, items + 1 entries; at most keep_cap of them,
 // a multiple of 64; with more, the three kernels do nothing and the caller
-// must ask for a larger pair buffer).  chunk_item (keep_cap / 64 words) gets
-// the item of every 64th test; the counter stores, per chunk of 64 tests,
+// must ask for a larger pair buffer).  chunk_item (keep_cap / 64 words) holds
+// the item of every 64th test (written by the scan of the areas, see
+// launch_exclusive_scan); the counter stores, per chunk of 64 tests,
 // the keep bits (keep_bits, keep_cap / 64 words) and their number
 // (chunk_cnt); after an exclusive scan of the batch's chunks of chunk_cnt
 // into kept_before (launch_exclusive_scan with count_of = &area_off[items]),
 // the writer emits every kept test's pair at index
 // kept_before[chunk] + (kept tests before it in the chunk).  Items must
 // number below 2^32.
-hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t keep_cap, uint32_t *chunk_item,
-                              hipStream_t s);
 // subtile: count one pair per 8x8 sub-tile a kept test's box reaches (bbox)
 hipError_t launch_count_pairs(const int4 *rect, const float4 *rec, const float4 *cull, const uint64_t *area_off,
                               int64_t items, const ViewDev *views, int nviews, bool tile_cull,
@@ -351,9 +350,11 @@ size_t scan_tmp_bytes(int64_t n);
 // Exclusive scan of n counts into n + 1 offsets (the last: the total).  With
 // count_of (device), only the first min(n, ceil(*count_of / 64)) counts are
 // scanned (entries past them are never read) and the total is also stored
-// at out[n].
+// at out[n].  With chunk_item: chunk_item[c] = the index i whose range
+// [out[i], out[i + 1]) holds position 64 c, for c < cap_chunks.
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out /*n+1*/, int64_t n, void *tmp, hipStream_t s,
-                                 const uint64_t *count_of = nullptr);
+                                 const uint64_t *count_of = nullptr, uint32_t *chunk_item = nullptr,
+                                 uint64_t cap_chunks = 0);
 
 size_t sort_tmp_bytes(uint64_t n);
 // Stable LSD sort by bits [begin_bit, end_bit); clear[0 .. nclear) is

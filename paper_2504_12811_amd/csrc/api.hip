@@ -562,13 +562,15 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     const bool tile_cull = (settings->flags & AAA_NO_TILE_CULL) == 0;
     const int64_t items = n * n_views;
     uint64_t *area_off = at<uint64_t>(ws, L.area_off);
-    HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s));
     uint64_t *keep_bits = at<uint64_t>(ws, L.keep_bits);
     uint32_t *chunk_item = at<uint32_t>(ws, L.chunk_item);
     uint32_t *chunk_cnt = at<uint32_t>(ws, L.chunk_cnt);
     uint64_t *kept_before = at<uint64_t>(ws, L.kept_before);
     const uint64_t keep_cap = keep_cap_of(max_pairs), chunks = keep_cap / 64;
-    HIP_TRY(aaa::launch_chunk_items(area_off, items, keep_cap, chunk_item, s));
+    // candidate tests numbered by the scan of the areas, which also records
+    // the item of every 64th test
+    HIP_TRY(aaa::launch_exclusive_scan(pa.area, area_off, items, at<void>(ws, L.scan_tmp), s, nullptr, chunk_item,
+                                       chunks));
     const bool subtile = subtile_lists(settings);
     const int64_t nlists = list_count(ntiles, settings);
     HIP_TRY(aaa::launch_count_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, tile_cull,

@@ -6,10 +6,10 @@
 //
 // Work split: the candidate (item, rectangle tile) tests are numbered through
 // an exclusive scan of the rectangle areas, and every lane takes one test
-// (grid-stride), so lanes stay busy whatever the mix of rectangle sizes.  One
-// pass over the area offsets records the item of every 64th test
-// (k_chunk_items); a wave's 64 tests then lie between two recorded items and
-// each lane searches that bracket, held across the lanes.
+// (grid-stride), so lanes stay busy whatever the mix of rectangle sizes.  The
+// last kernel of that scan also records the item of every 64th test; a
+// wave's 64 tests then lie between two recorded items and each lane searches
+// that bracket, held across the lanes.
 //
 // Pairs are written in test order (item, then tile within the rectangle):
 // items occupy increasing ranges, so the stable sort breaks key ties by item,
@@ -378,9 +378,13 @@ __global__ __launch_bounds__(256) void k_scan_sums(uint64_t *__restrict__ sums, 
     if (threadIdx.x == 0) sums[nb] = carry;
 }
 
+// With chunk_item: chunk_item[c] = the element whose range [out[i],
+// out[i + 1]) holds position 64 c, for the chunks below cap_chunks (every
+// element writes the chunks that start inside its range).
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__ in, int64_t n_host,
                                                     const uint64_t *__restrict__ count_of,
-                                                    const uint64_t *__restrict__ sums, uint64_t *__restrict__ out)
+                                                    const uint64_t *__restrict__ sums, uint64_t *__restrict__ out,
+                                                    uint32_t *__restrict__ chunk_item, uint64_t cap_chunks)
 {
     __shared__ uint64_t sm[4];
     const int64_t n = scan_len(n_host, count_of);
@@ -402,36 +406,18 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *__restrict__
     uint64_t ex = block_exclusive_scan(acc, sm, tot) + sums[blockIdx.x];
     for (int k = 0; k < 4; ++k) {
         int64_t idx = b0 + threadIdx.x * 4 + k;
-        if (idx < n) out[idx] = ex;
+        if (idx < n) {
+            out[idx] = ex;
+            if (chunk_item && v[k]) {
+                const uint64_t c1 = (ex + v[k] - 1) >> 6;
+                for (uint64_t c = (ex + 63) >> 6; c <= c1 && c < cap_chunks; ++c) chunk_item[c] = (uint32_t)idx;
+            }
+        }
         ex += v[k];
     }
 }
 
-// chunk_item[c] = the item holding candidate test 64 c, for the chunks below
-// cap_chunks: every item with tests writes the chunks that start inside its
-// range [area_off[g], area_off[g + 1]).
-__global__ __launch_bounds__(256) void k_chunk_items(const uint64_t *__restrict__ area_off, int64_t nitems,
-                                                     uint64_t cap_chunks, uint32_t *__restrict__ chunk_item)
-{
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nitems;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t g0 = area_off[g], g1 = area_off[g + 1];
-        if (g1 <= g0) continue;
-        const uint64_t c1 = (g1 - 1) >> 6;
-        for (uint64_t c = (g0 + 63) >> 6; c <= c1 && c < cap_chunks; ++c) chunk_item[c] = (uint32_t)g;
-    }
-}
-
 }  // namespace
-
-hipError_t launch_chunk_items(const uint64_t *area_off, int64_t items, uint64_t keep_cap, uint32_t *chunk_item,
-                              hipStream_t s)
-{
-    if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_chunk_items, dim3((unsigned)std::min<int64_t>((items + 255) / 256, 4096)), dim3(256), 0, s,
-                       area_off, items, keep_cap / 64, chunk_item);
-    return hipGetLastError();
-}
 
 // Grid of a grid-stride emitter kernel: the workgroups the device holds at
 // once (no second, late round of workgroups), at most kEmitBlocks.
@@ -516,7 +502,7 @@ size_t scan_tmp_bytes(int64_t n)
 }
 
 hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out, int64_t n, void *tmp, hipStream_t s,
-                                 const uint64_t *count_of)
+                                 const uint64_t *count_of, uint32_t *chunk_item, uint64_t cap_chunks)
 {
     int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     uint64_t *sums = (uint64_t *)tmp;
@@ -526,7 +512,7 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint64_t *out, int64_t n, v
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, n, count_of, sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, sums, n, count_of);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, n, count_of, (const uint64_t *)sums,
-                       out);
+                       out, chunk_item, cap_chunks);
     return hipGetLastError();
 }
 
