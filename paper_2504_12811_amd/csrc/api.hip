@@ -380,7 +380,7 @@ void fold_events(aaa_ctx *c, int set)
 {
     if (!c->pending[set]) return;
     hipEvent_t *e = c->ev[set];
-    // e0 start | preprocess | e1 | count | e2 | scan | e3 .. host wait .. e4 | write | e5 | sort (list bits) | e6 |
+    // e0 start | preprocess | e1 | count | e2 | scan | e3 | publish | e4 | write | e5 .. host wait .. | sort (list bits) | e6 |
     // ranges | e7 | sort (within lists) | e8 | blend | e9
     const int a[AAA_NUM_STAGES] = {0, 1, 2, 4, 5, 6, 8, 0};
     const int b[AAA_NUM_STAGES] = {1, 2, 3, 5, 6, 7, 9, 9};
@@ -581,7 +581,20 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     HIP_TRY(aaa::launch_exclusive_scan(chunk_cnt, kept_before, (int64_t)chunks, at<void>(ws, L.chunk_scan_tmp), s,
                                        area_off + items));
     STAGE_MARK(3);
-    HIP_TRY(publish_and_wait(ctx, kept_before + chunks, area_off + items, s));
+    uint64_t count_seq = 0;
+    HIP_TRY(publish(ctx, kept_before + chunks, area_off + items, s, &count_seq));
+    uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
+    uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
+    STAGE_MARK(4);
+    // The writer needs no count from the host (a fixed grid; it stores no
+    // pair at or past max_pairs and does nothing when the tests overflow
+    // keep_cap), so it runs while the host waits for the count.
+    const bool quads = quad_values(n, settings) && !subtile;
+    HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, keep_bits,
+                                    chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads,
+                                    tile_cull, subtile, s));
+    STAGE_MARK(5);
+    HIP_TRY(wait_published(ctx, s, count_seq));
     uint64_t P = ctx->sync_host[0];
     const uint64_t C = ctx->sync_host[1];
     if (C > keep_cap) P = std::max<uint64_t>(max_pairs + 1, (C + 7) / 8);  // buffer too small to even count
@@ -591,14 +604,6 @@ int aaa_render_batch(aaa_ctx *ctx, const aaa_scene *scene, int n_views, const aa
     }
     if (P > max_pairs) return fail(AAA_ERR_PAIR_OVERFLOW, "%llu pairs exceed max_pairs %llu", (unsigned long long)P,
                                    (unsigned long long)max_pairs);
-    uint64_t *keys = at<uint64_t>(ws, L.keys), *keys_alt = at<uint64_t>(ws, L.keys_alt);
-    uint32_t *vals = at<uint32_t>(ws, L.vals), *vals_alt = at<uint32_t>(ws, L.vals_alt);
-    STAGE_MARK(4);
-    const bool quads = quad_values(n, settings) && !subtile;
-    HIP_TRY(aaa::launch_write_pairs(pa.rect, pa.rec, pa.cull, area_off, items, pa.views, n_views, keep_bits,
-                                    chunk_item, kept_before, keep_cap, max_pairs, keys, vals, pa.bbox, quads,
-                                    tile_cull, subtile, s));
-    STAGE_MARK(5);
     // Pair sort.  Phase 1: LSD passes over the list bits (the high word);
     // phase 2 (below) sorts each list by the depth word.
     bool in_alt = false;
