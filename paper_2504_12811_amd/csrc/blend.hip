@@ -49,6 +49,16 @@ struct PixelState {
     bool done;
 };
 
+// Slots per run on one XCD: the q-th slot that XCD x takes (consecutive
+// workgroups land on consecutive XCDs) is the (q % kXcdRun)-th of its
+// (q / kXcdRun)-th run of kXcdRun consecutive slots, so that neighbouring
+// slots (neighbouring tiles, which share records) share an L2 while the
+// XCDs still take the slot order together.  Launches cover a multiple of
+// 8 kXcdRun slots.
+constexpr int kXcdRun = 4;
+__device__ __forceinline__ int xcd_slot(int q, int x) { return ((q / kXcdRun) * 8 + x) * kXcdRun + q % kXcdRun; }
+inline int slot_runs(int nslots) { return (nslots + 8 * kXcdRun - 1) / (8 * kXcdRun) * kXcdRun; }
+
 struct Eval {
     float rx, ry, rz, wx, wy, wz, D, N;
 };
@@ -174,16 +184,16 @@ __global__ __launch_bounds__(64 * WPB) void k_blend(const float4 *__restrict__ r
                                                     BlendArgs a)
 {
     const int ntiles = a.total_tiles;
-    // Consecutive workgroups land on consecutive XCDs; tiles are dealt to the
-    // XCDs round-robin (tile t to XCD t % 8), so that each XCD gets an even
-    // share of dense and sparse image regions (contiguous bands per XCD left
-    // the XCDs with dense bands working long after the others); with one
-    // wave per workgroup the four quadrants of a tile share an XCD.
-    // The slots are dealt this way; with a tile order, slot s renders tile
+    // Consecutive workgroups land on consecutive XCDs; slots are dealt to the
+    // XCDs in short runs (xcd_slot), so that each XCD gets an even share of
+    // dense and sparse image regions (contiguous bands per XCD left the XCDs
+    // with dense bands working long after the others); with one wave per
+    // workgroup the four quadrants of a tile share an XCD.
+    // Without a tile order slot s renders tile s; with one, slot s renders tile
     // tile_order[s] (longest lists first, so the last workgroups to start
     // are short ones).
     const int wq = (int)(blockIdx.x >> 3);
-    const int slot = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
+    const int slot = xcd_slot(WPB == 4 ? wq : wq >> 2, (int)(blockIdx.x & 7));
     if (slot >= ntiles) return;
     const int tile = a.tile_order ? (int)uniform_read(a.tile_order + slot) : slot;
     int v = 0;  // the view owning this tile (views are ordered by tile_base)
@@ -759,8 +769,8 @@ __global__ __launch_bounds__(64 * WPB) void k_grad(const float4 *__restrict__ re
                                                    BlendArgs a)
 {
     const int ntiles = a.total_tiles;
-    const int wq = (int)(blockIdx.x >> 3);  // slots dealt to the XCDs round-robin, tile order as in k_blend
-    const int slot = (WPB == 4 ? wq : wq >> 2) * 8 + (int)(blockIdx.x & 7);
+    const int wq = (int)(blockIdx.x >> 3);  // slots dealt to the XCDs and tile order as in k_blend
+    const int slot = xcd_slot(WPB == 4 ? wq : wq >> 2, (int)(blockIdx.x & 7));
     if (slot >= ntiles) return;
     const int tile = a.tile_order ? (int)uniform_read(a.tile_order + slot) : slot;
     int v = 0;
@@ -869,7 +879,7 @@ template <int K>
 hipError_t launch_k(const BlendArgs &a, bool stats, bool pass1, hipStream_t s)
 {
     const int ntiles = a.total_tiles;
-    const int per = (ntiles + 7) / 8;
+    const int per = slot_runs(ntiles);
     dim3 tiles((unsigned)(per * 8)), quads((unsigned)(per * 8 * 4));
     if (pass1 && a.rank16)
         hipLaunchKernelGGL((k_blend<K, false, true, uint16_t>), tiles, dim3(256), 0, s, a.rec, a.vals, a);
@@ -980,7 +990,7 @@ hipError_t launch_wave_caps(const ViewDev *views, int nviews, int total_tiles, c
 hipError_t launch_grad(const BlendArgs &a, hipStream_t s)
 {
     if (a.total_tiles <= 0) return hipSuccess;
-    const int per = (a.total_tiles + 7) / 8;
+    const int per = slot_runs(a.total_tiles);
     hipLaunchKernelGGL(k_grad<1>, dim3((unsigned)(per * 8 * 4)), dim3(64), 0, s, a.rec, a.vals, a);
     return hipGetLastError();
 }
